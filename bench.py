@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Benchmark of the TreePM force step on one MI355X.
+
+One step = the whole hot path on all particles of the workload, as the
+Arepo paper computes a force the first time (Sec. 3.1: geometric criterion
+first, then the relative criterion with |a| of that first pass):
+
+    build_tree -> pm_long_range (deposit, FFT solve, difference, interpolate)
+    -> compute_forces(BH) -> |a_tree + a_pm| -> compute_forces(relative)
+
+Default workload: periodic box L = 100 of 128^3 particles (grid plus
+Zel'dovich displacements of a Gaussian field with P(k) ~ k^-2, rms 0.1
+cell), eps = L/6400, TreePM with a 256^3 mesh, r_s = 1.25 cells, r_cut =
+4.5 r_s, theta = 0.5, alpha = 0.0025; inputs are resident in HBM.  The value
+is force evaluations per second (N per step); FP32 is the headline, the FP64
+path is measured beside it.  The walk kernel is timed by the library's own
+events around its launches; the FP64 CPU oracle is timed on a bounded sample
+of the same step on the host cores.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle force evals/s + p50/p99 latency, FP32 vs FP64 at 99%-ile err<=1%"
+
+# Algorithmic flops per interaction (FMA = 2): Newtonian monopole or pair:
+# 3 sub + r^2 (1 mul + 2 fma) + rinv^2, m rinv^3 (3 mul) + 3 fma accumulate
+# = 17 (+1 rsqrt); the short-range factor adds r, x = r / 2 r_s, exp(-x^2),
+# erfc(x), the combination and the product: 19 (+ exp, rcp).
+FLOPS_NEWTON = 17
+FLOPS_TREEPM = 17 + 19
+PEAK = {"fp32": 157.3, "fp64": 78.6}  # TFLOP/s, MI355X vector ALU
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3, choices=[2, 3, 4])
+    ap.add_argument("--precision", default="both", choices=["both", "fp32", "fp64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=8192)
+    return ap.parse_args()
+
+
+def workload(cfg):
+    from paper_1909_04667_amd import workloads as W
+    c = W.CONFIGS[cfg]
+    p = W.make_config(cfg)
+    kw = dict(eps=c["eps"], theta=c["theta"], alpha=c.get("alpha", 0.0025))
+    if c["periodic"]:
+        kw.update(periodic=True, box_size=c["box"], pm_grid=c["pm_grid"], asmth=c["asmth"],
+                  rcut=c["rcut"])
+    return c, p, kw
+
+
+def run_gpu(p, kw, prec, steps, warmup):
+    import torch
+    from paper_1909_04667_amd import binding as B
+    dev = torch.device("cuda:0")
+    t = lambda a, dt=torch.float64: torch.as_tensor(a, dtype=dt, device=dev).contiguous()
+    x, y, z = t(p.x), t(p.y), t(p.z)
+    n = p.n
+    idx = torch.arange(n, dtype=torch.int32, device=dev)
+    ctx = B.Context(precision=prec, **kw)
+    dt = ctx.dtype
+    acc_pm = torch.empty((3, n), dtype=dt, device=dev)
+    acc_bh = torch.empty((3, n), dtype=dt, device=dev)
+    acc = torch.empty((3, n), dtype=dt, device=dev)
+    anorm = torch.zeros(n, dtype=torch.float64, device=dev)
+    nint_bh = torch.empty(n, dtype=torch.int32, device=dev)
+    nint = torch.empty(n, dtype=torch.int32, device=dev)
+    periodic = bool(kw.get("periodic"))
+
+    def step():
+        ctx.build_tree(x, y, z)
+        if periodic:
+            ctx.pm_long_range(idx, acc=acc_pm)
+        ctx.compute_forces(idx, "bh", acc=acc_bh, n_interactions=nint_bh)
+        ctx.accel_norm(idx, acc_bh, acc_pm if periodic else None, out=anorm)
+        ctx.compute_forces(idx, "rel", a_old_norm=anorm, acc=acc, n_interactions=nint)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.check()
+    for k in ctx.TIMERS:
+        ctx.timing_read(k)  # drop warm-up records
+    ctx.timing(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for s in range(steps):
+        step()
+        ev[s + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.timing(False)
+    per_step = [ev[s].elapsed_time(ev[s + 1]) for s in range(steps)]
+    timers = {k: ctx.timing_read(k) for k in ctx.TIMERS}
+    ctx.check()
+    inter_bh = int(nint_bh.to(torch.int64).sum())
+    inter_rel = int(nint.to(torch.int64).sum())
+    total = (acc + acc_pm) if periodic else acc
+    out = dict(prec=prec, ms_per_step=sum(per_step) / steps, per_step=per_step, wall=wall,
+               timers=timers, inter_bh=inter_bh, inter_rel=inter_rel, n=n,
+               acc=total.double().cpu(), entries=ctx.tree_info()[1])
+    ctx.close()
+    return out
+
+
+def pct(v, q):
+    v = sorted(v)
+    if not v:
+        return float("nan")
+    k = min(len(v) - 1, max(0, int(math.ceil(q / 100.0 * len(v))) - 1))
+    return v[k]
+
+
+def cpu_baseline(p, kw, sample, cfg):
+    """The FP64 oracle on the host: tree build and PM solve of the whole
+    system, both walks on a bounded sample of targets, scaled to N."""
+    import numpy as np
+    import oracle as O
+    periodic = bool(kw.get("periodic"))
+    rng = np.random.default_rng(0)
+    samp = np.sort(rng.choice(p.n, min(sample, p.n), replace=False))
+    t0 = time.perf_counter()
+    T = O.Tree(p.x, p.y, p.z, periodic=periodic, box=kw.get("box_size", 0.0))
+    t_build = time.perf_counter() - t0
+    rs = kw.get("asmth", 1.25) * kw.get("box_size", 0.0) / kw["pm_grid"] if periodic else 0.0
+    t_pm = 0.0
+    apm = 0.0
+    if periodic:
+        t0 = time.perf_counter()
+        apm, _ = O.pm(p.x, p.y, p.z, None, kw["box_size"], kw["pm_grid"], 1.0, rs,
+                      targets=samp, want_pot=False)
+        t_pm = time.perf_counter() - t0
+    Pb = O.make_params(periodic=periodic, box=kw.get("box_size", 0.0), eps=kw["eps"],
+                       theta=kw["theta"], treepm=periodic, rs=rs,
+                       rcut=kw.get("rcut", 4.5) * rs if periodic else 0.0)
+    t0 = time.perf_counter()
+    a, _, _ = T.walk(Pb, targets=samp)
+    t_bh = time.perf_counter() - t0
+    an = np.zeros(p.n)
+    an[samp] = np.linalg.norm(a + apm, axis=0)
+    Pr = O.make_params(periodic=periodic, box=kw.get("box_size", 0.0), eps=kw["eps"],
+                       opening="rel", alpha=kw["alpha"], treepm=periodic, rs=rs,
+                       rcut=kw.get("rcut", 4.5) * rs if periodic else 0.0)
+    t0 = time.perf_counter()
+    ar, _, _ = T.walk(Pr, targets=samp, anorm=an)
+    t_rel = time.perf_counter() - t0
+    step = t_build + t_pm + (t_bh + t_rel) * p.n / samp.size
+    return {"value": p.n / step, "unit": "force evals/s", "cores": O.max_threads(),
+            "kind": "oracle",
+            "sample": (f"config {cfg}: single-threaded tree build of all {p.n} particles "
+                       f"({t_build:.1f} s)"
+                       + (f", PM solve of the full {kw['pm_grid']}^3 mesh ({t_pm:.1f} s)"
+                          if periodic else "")
+                       + f", BH + relative walks of {samp.size} sampled targets on "
+                         f"{O.max_threads()} threads ({t_bh + t_rel:.1f} s) scaled to N"),
+            "seconds": {"build": t_build, "pm": t_pm, "walk_bh_sample": t_bh,
+                        "walk_rel_sample": t_rel, "step_estimate": step},
+            "acc_sample": (ar + apm), "samp": samp}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; the multi-GPU design is "
+                          "described in DESIGN.md and not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    c, p, kw = workload(args.config)
+    precs = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
+    res = {pr: run_gpu(p, kw, pr, args.steps, args.warmup) for pr in precs}
+    head = res[precs[0]]
+    periodic = bool(kw.get("periodic"))
+    fl = FLOPS_TREEPM if periodic else FLOPS_NEWTON
+
+    def summary(r):
+        ms_rel, k_rel = r["timers"]["walk_rel"]
+        ms_bh, k_bh = r["timers"]["walk"]
+        walk_ms = ms_rel / max(k_rel, 1)
+        return {
+            "value": r["n"] / (r["ms_per_step"] * 1e-3),
+            "ms_per_step": r["ms_per_step"],
+            "latency_ms": {"p50": pct(r["per_step"], 50), "p99": pct(r["per_step"], 99)},
+            "kernel_ms": {
+                "walk_rel": walk_ms, "walk_bh": ms_bh / max(k_bh, 1),
+                "build": r["timers"]["build"][0] / max(r["timers"]["build"][1], 1),
+                "sort": r["timers"]["sort"][0] / max(r["timers"]["sort"][1], 1),
+                "pm_solve": r["timers"]["pm_solve"][0] / max(r["timers"]["pm_solve"][1], 1),
+                "pm_interp": r["timers"]["pm_interp"][0] / max(r["timers"]["pm_interp"][1], 1)},
+            "interactions_per_step": {"bh": r["inter_bh"], "rel": r["inter_rel"]},
+            "interactions_per_particle_rel": r["inter_rel"] / r["n"],
+            "tree_entries": r["entries"],
+        }
+
+    out_prec = {pr: summary(r) for pr, r in res.items()}
+    h = out_prec[precs[0]]
+    walk_ms = h["kernel_ms"]["walk_rel"]
+    achieved = res[precs[0]]["inter_rel"] * fl / (walk_ms * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": h["value"],
+        "unit": "force evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64"}[precs[0]],
+        "data": "synthetic",
+        "config": {"workload": c["name"], "n_particles": p.n, "box": kw.get("box_size"),
+                   "pm_grid": kw.get("pm_grid"), "eps": kw["eps"], "theta": kw["theta"],
+                   "alpha": kw["alpha"], "asmth": kw.get("asmth"), "rcut": kw.get("rcut"),
+                   "step": "build + PM + BH walk + |a| + relative walk, all particles",
+                   "parallelism": "single GPU"},
+        "latency_ms": h["latency_ms"],
+        "per_precision": out_prec,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK[precs[0]],
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[precs[0]], "traffic": None,
+                     "kernel": f"k_walk{'32' if precs[0] == 'fp32' else '64'} (relative pass)",
+                     "flops_per_interaction": fl},
+    }
+    if len(precs) == 2:
+        a32, a64 = res["fp32"]["acc"].numpy(), res["fp64"]["acc"].numpy()
+        na = np.linalg.norm(a64, axis=0)
+        e = np.linalg.norm(a32 - a64, axis=0) / np.maximum(na, 1e-3 * np.sqrt(np.mean(na ** 2)))
+        line["fp32_vs_fp64_err"] = {"p50": float(np.percentile(e, 50)),
+                                    "p99": float(np.percentile(e, 99)),
+                                    "max": float(e.max())}
+        line["fp32_speedup_vs_fp64"] = out_prec["fp64"]["ms_per_step"] / h["ms_per_step"]
+    if not args.no_cpu:
+        cb = cpu_baseline(p, kw, args.cpu_sample, args.config)
+        a_or = cb.pop("acc_sample")
+        samp = cb.pop("samp")
+        a64 = res["fp64"]["acc"].numpy()[:, samp] if "fp64" in res else None
+        if a64 is not None:
+            na = np.linalg.norm(a_or, axis=0)
+            e = np.linalg.norm(a64 - a_or, axis=0) / np.maximum(
+                na, 1e-3 * np.sqrt(np.mean(na ** 2)))
+            # each side's relative pass uses its own |a| from its own first pass
+            cb["gpu_fp64_vs_oracle_err"] = {"p99": float(np.percentile(e, 99)),
+                                            "max": float(e.max())}
+        line["cpu_baseline"] = cb
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

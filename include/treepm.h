@@ -1,0 +1,189 @@
+/*
+ * treepm.h -- C ABI of the MI355X (gfx950) TreePM gravity library.
+ *
+ * The library computes the gravitational accelerations of the currently
+ * active particles of an N-body system by the TreePM method of the Arepo code
+ * (Weinberger, Springel & Pakmor, "The AREPO public code release", ApJS 2020):
+ *
+ *   tpm_build_tree      Sec. 3.1  enclosing cube, Peano-Hilbert keys (the
+ *                                 ordering of Sec. 8), radix sort, octree with
+ *                                 monopole moments, rebuilt for every call
+ *                                 sequence (no dynamic updates)
+ *   tpm_compute_forces  Sec. 3.1  tree walk with the relative or geometric
+ *                                 opening criterion and the 1.2 L box rule;
+ *                       Sec. 3.2  spline softening (zero-lag potential -Gm/eps,
+ *                                 Newtonian beyond 2.8 eps);
+ *                       Sec. 3.4  short-range truncation and cutoff when a PM
+ *                                 mesh is configured
+ *   tpm_pm_long_range   Sec. 3.3/3.4  CIC deposit, FFT Poisson solve with the
+ *                                 long-range Gaussian filter and CIC
+ *                                 deconvolution, four-point finite difference,
+ *                                 CIC interpolation
+ *
+ * Conventions for every entry point:
+ *   - All particle arrays are DEVICE pointers (HIP global memory), borrowed
+ *     for the duration of the stream work the call enqueues; the library never
+ *     frees or writes caller inputs.  Outputs are written by kernels on the
+ *     context's stream; they are valid once that stream has reached the call.
+ *   - Returns TPM_OK (0) or a negative error code.  Arguments are validated on
+ *     the host before anything is enqueued: on an error no output is written.
+ *     Index arrays live on the device and are checked there: an out-of-range
+ *     index yields NaN outputs for that position and sets a sticky device flag
+ *     that tpm_check() reports (and clears).
+ *   - Not thread-safe per context; different contexts are independent.
+ *   - Layouts: "[3][n]" means three contiguous planes x, y, z of n values.
+ */
+#ifndef TREEPM_H
+#define TREEPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPM_OK 0
+#define TPM_EINVAL (-1)   /* invalid argument or parameter */
+#define TPM_ENOMEM (-2)   /* device or pinned-host allocation failed */
+#define TPM_EDEVICE (-3)  /* a HIP runtime call failed (text in tpm_last_error) */
+#define TPM_ESTATE (-4)   /* call out of order (e.g. forces before a build) */
+#define TPM_EINDEX (-5)   /* tpm_check(): an active index was out of range */
+
+#define TPM_OPEN_BH 0     /* geometric criterion  L > theta d            (Sec. 3.1) */
+#define TPM_OPEN_REL 1    /* relative  G m L^2 / d^4 > alpha |a_old|      (Sec. 3.1) */
+
+#define TPM_FP64 0        /* FP64 walk: bit-compatible with the FP64 reference contract */
+#define TPM_FP32 1        /* FP32 walk on node-relative offsets, FP64 moments */
+
+/* Run-time parameters (the gravity parameters of the paper's Table 1). */
+typedef struct tpm_params {
+    int32_t periodic;       /* 1: periodic cube of side box_size (requires pm_grid > 0) */
+    int32_t precision;      /* TPM_FP64 or TPM_FP32 (walk and mesh arithmetic) */
+    int32_t want_potential; /* 1: compute potentials too */
+    int32_t pm_grid;        /* PM mesh cells per side (power of two, 8..1024); 0: no PM */
+    double box_size;        /* periodic box side (ignored when periodic == 0) */
+    double G;               /* gravitational constant (> 0) */
+    double eps;             /* softening length; spline support 2.8 eps (> 0) */
+    double theta;           /* ErrTolTheta (>= 0) */
+    double alpha;           /* ErrTolForceAcc (> 0) */
+    double asmth;           /* ASMTH: r_s = asmth * box_size / pm_grid (> 0 with PM) */
+    double rcut;            /* RCUT: short-range cutoff r_cut = rcut * r_s (> 0 with PM) */
+    double shift[3];        /* root placement in [0,1)^3: non-periodic, fraction of the
+                               slack of the power-of-two root cube; periodic, box shift
+                               as a fraction of box_size (Sec. 3.1, random placement) */
+} tpm_params;
+
+typedef struct tpm_ctx tpm_ctx;
+
+/* Create a context bound to a HIP stream (NULL: the null stream) on the
+ * current device.  Validates *p (TPM_EINVAL).  No device memory is allocated
+ * until the first build.  *out receives the context, NULL on error. */
+int tpm_create(const tpm_params *p, void *hip_stream, tpm_ctx **out);
+
+/* Free every device and host buffer of the context (synchronises its stream). */
+int tpm_destroy(tpm_ctx *ctx);
+
+/* Text of the last error of this context (never NULL; "" when none). */
+const char *tpm_last_error(const tpm_ctx *ctx);
+
+/* Rebind the context to another stream. */
+int tpm_set_stream(tpm_ctx *ctx, void *hip_stream);
+
+/* Upper bound of the device bytes a build of n particles allocates, for
+ * admission by memory budget.  Returns -1 on invalid parameters. */
+int64_t tpm_bytes_needed(const tpm_params *p, int64_t n);
+
+/* Device bytes the context holds now. */
+int64_t tpm_bytes_held(const tpm_ctx *ctx);
+
+/* Build the tree (Sec. 3.1) of n >= 1 particles.
+ * x, y, z: device double[n] positions; periodic inputs must lie in
+ *          [0, box_size) (other values are folded by one box length and then
+ *          clamped to the root cube).
+ * mass:    device double[n], or NULL for equal masses 1/n.
+ * Steps: root cube -> 63-bit Peano-Hilbert keys -> stable radix sort (ties by
+ * index) -> depth-first threaded octree (internal node = cell holding >= 2
+ * particles; a depth-21 cell holding several particles lists them in index
+ * order) -> FP64 monopole moments, children summed in curve order.
+ * Synchronises the stream once (to size the node arrays).  Invalidates any
+ * cached PM mesh. */
+int tpm_build_tree(tpm_ctx *ctx, int64_t n, const double *x, const double *y,
+                   const double *z, const double *mass);
+
+/* Tree force on the active particles (Sec. 3.1, 3.2, 3.4).
+ * opening:     TPM_OPEN_BH or TPM_OPEN_REL.
+ * n_act:       number of active particles (>= 0).
+ * active_idx:  device int32[n_act], indices into the build's particle order,
+ *              any order; duplicates are allowed (each gets the same result).
+ * a_old_norm:  device double[n] in build order, |a| of the previous force
+ *              (needed by TPM_OPEN_REL; ignored by TPM_OPEN_BH, may be NULL).
+ * acc:         device [3][n_act] in active_idx order; double for TPM_FP64,
+ *              float for TPM_FP32.  With a PM mesh this is the short-range
+ *              (truncated) part only; add tpm_pm_long_range for the total.
+ * pot:         device [n_act] of the same type, or NULL.
+ * n_interactions: device uint32[n_act] node + particle interactions per
+ *              target (the cost factor g_i of Sec. 8), or NULL.
+ * Enqueues work only; does not synchronise. */
+int tpm_compute_forces(tpm_ctx *ctx, int32_t opening, int64_t n_act, const int32_t *active_idx,
+                       const double *a_old_norm, void *acc, void *pot,
+                       uint32_t *n_interactions);
+
+/* Long-range PM acceleration at the active particles (Sec. 3.3, 3.4).
+ * Requires pm_grid > 0 and a periodic box (else TPM_EINVAL).  The mesh is
+ * solved from ALL particles of the last build on first use after that build
+ * and cached; every call interpolates.  acc: device [3][n_act], pot: device
+ * [n_act] or NULL, dtype as in tpm_compute_forces.  Does not synchronise. */
+int tpm_pm_long_range(tpm_ctx *ctx, int64_t n_act, const int32_t *active_idx, void *acc,
+                      void *pot);
+
+/* |a| per particle for the relative criterion of the next pass (Sec. 3.1:
+ * |a| of the previous force computation).  For k < n_act:
+ *   out[active_idx[k]] = |acc_a[:,k] + acc_b[:,k]|  (computed in double)
+ * acc_a, acc_b: device [3][n_act] of the context's dtype (acc_b may be NULL,
+ * e.g. the tree part and the PM part of a TreePM force); out: device
+ * double[n] in build order (entries of inactive particles are untouched).
+ * Out-of-range indices are skipped and flagged for tpm_check. */
+int tpm_accel_norm(tpm_ctx *ctx, int64_t n_act, const int32_t *active_idx, const void *acc_a,
+                   const void *acc_b, double *out);
+
+/* Measurement: when enabled, the library records HIP events on its stream
+ * immediately around the kernels of one class, so the elapsed time is the
+ * kernels' own duration.  tpm_timing_read synchronises the stream, returns
+ * the summed milliseconds and the number of timed launches of class kind
+ * since the last read, and resets them. */
+#define TPM_TIMER_WALK 0       /* tree-walk kernel, geometric criterion */
+#define TPM_TIMER_BUILD 1      /* whole tree build (keys .. moments) */
+#define TPM_TIMER_PM_SOLVE 2   /* deposit + FFT solve */
+#define TPM_TIMER_PM_INTERP 3  /* difference + interpolation kernel */
+#define TPM_TIMER_SORT 4       /* radix sort within the build */
+#define TPM_TIMER_WALK_REL 5   /* tree-walk kernel, relative criterion */
+int tpm_timing_enable(tpm_ctx *ctx, int on);
+int tpm_timing_read(tpm_ctx *ctx, int kind, double *ms, int64_t *launches);
+
+/* Synchronise the stream and report sticky device-side errors
+ * (TPM_EINDEX for an out-of-range active index); clears them. */
+int tpm_check(tpm_ctx *ctx);
+
+/* Sizes of the current tree: particles, depth-first entries (nodes +
+ * particles), and the root frame {x0, y0, z0, L_root}.  Synchronises. */
+int tpm_tree_info(tpm_ctx *ctx, int64_t *n, int64_t *n_entries, double *frame4);
+
+/* Copy the tree to caller-owned HOST buffers for verification (any pointer
+ * may be NULL; array sizes are n_entries or n as noted).  Entry e, in
+ * depth-first order: level[e] (0..21; -1 for a particle entry), first[e]
+ * (rank of its first particle in key order), count[e] (particles below),
+ * skip[e] (index of the entry after its subtree), pidx[e] (build index of the
+ * particle, -1 for nodes), mass[e], com[3][n_entries] (centre of mass, tree
+ * frame), cen[3][n_entries] (geometric centre of nodes, position of
+ * particles); key[n] sorted keys and perm[n] build index of the particle of
+ * each rank.  Synchronises. */
+int tpm_export_tree(tpm_ctx *ctx, int32_t *level, int64_t *first, int64_t *count,
+                    int64_t *skip, int64_t *pidx, double *mass, double *com, double *cen,
+                    uint64_t *key, int64_t *perm);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TREEPM_H */

@@ -1,0 +1,232 @@
+"""Thin ctypes binding of ``libtreepm.so`` (argument marshalling only).
+
+Every step of the force computation runs in the library's HIP kernels; this
+module only turns torch tensors into device pointers and the current torch
+stream into the library's stream.  If the library is missing the binding
+raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtreepm.so")
+
+TPM_OK, TPM_EINVAL, TPM_ENOMEM, TPM_EDEVICE, TPM_ESTATE, TPM_EINDEX = 0, -1, -2, -3, -4, -5
+OPEN = {"bh": 0, "rel": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+
+
+class TpmParams(C.Structure):
+    _fields_ = [("periodic", C.c_int32), ("precision", C.c_int32),
+                ("want_potential", C.c_int32), ("pm_grid", C.c_int32),
+                ("box_size", C.c_double), ("G", C.c_double), ("eps", C.c_double),
+                ("theta", C.c_double), ("alpha", C.c_double), ("asmth", C.c_double),
+                ("rcut", C.c_double), ("shift", C.c_double * 3)]
+
+
+class TreePMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"treepm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with paper_1909_04667_amd.build.build() "
+                "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        P = C.POINTER
+        L.tpm_create.argtypes = [P(TpmParams), vp, P(vp)]
+        L.tpm_destroy.argtypes = [vp]
+        L.tpm_last_error.argtypes = [vp]
+        L.tpm_last_error.restype = C.c_char_p
+        L.tpm_set_stream.argtypes = [vp, vp]
+        L.tpm_bytes_needed.argtypes = [P(TpmParams), i64]
+        L.tpm_bytes_needed.restype = i64
+        L.tpm_bytes_held.argtypes = [vp]
+        L.tpm_bytes_held.restype = i64
+        L.tpm_build_tree.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.tpm_compute_forces.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp]
+        L.tpm_pm_long_range.argtypes = [vp, i64, vp, vp, vp]
+        L.tpm_check.argtypes = [vp]
+        L.tpm_tree_info.argtypes = [vp, P(i64), P(i64), P(d)]
+        L.tpm_export_tree.argtypes = [vp] + [vp] * 10
+        L.tpm_accel_norm.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.tpm_timing_enable.argtypes = [vp, C.c_int]
+        L.tpm_timing_read.argtypes = [vp, C.c_int, P(d), P(i64)]
+        _lib = L
+    return _lib
+
+
+def make_params(*, periodic=False, precision="fp64", want_potential=False, pm_grid=0,
+                box_size=0.0, G=1.0, eps=0.01, theta=0.5, alpha=0.0025, asmth=1.25,
+                rcut=4.5, shift=(0.0, 0.0, 0.0)) -> TpmParams:
+    p = TpmParams()
+    p.periodic = int(periodic)
+    p.precision = PRECISION[precision]
+    p.want_potential = int(want_potential)
+    p.pm_grid = int(pm_grid)
+    p.box_size = float(box_size)
+    p.G = float(G)
+    p.eps = float(eps)
+    p.theta = float(theta)
+    p.alpha = float(alpha)
+    p.asmth = float(asmth)
+    p.rcut = float(rcut)
+    for a in range(3):
+        p.shift[a] = float(shift[a])
+    return p
+
+
+def bytes_needed(params: TpmParams, n: int) -> int:
+    return int(lib().tpm_bytes_needed(C.byref(params), int(n)))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """One tree (and PM mesh) on one device, bound to a stream."""
+
+    def __init__(self, params: TpmParams | None = None, stream=None, **kw):
+        self.params = params if params is not None else make_params(**kw)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.dtype = torch.float32 if self.params.precision == 1 else torch.float64
+        h = C.c_void_p()
+        rc = lib().tpm_create(C.byref(self.params), _stream_handle(self.stream), C.byref(h))
+        if rc != TPM_OK:
+            raise TreePMError(rc, "tpm_create rejected the parameters")
+        self.h = h
+        self.n = 0
+        self._keep = ()
+
+    def _rc(self, rc):
+        if rc != TPM_OK:
+            raise TreePMError(rc, lib().tpm_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tpm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        self._rc(lib().tpm_set_stream(self.h, _stream_handle(stream)))
+
+    # -- the three operations of the hot path ---------------------------------
+    def build_tree(self, x, y, z, mass=None):
+        for t in (x, y, z) + ((mass,) if mass is not None else ()):
+            if t.dtype != torch.float64:
+                raise ValueError("positions and masses must be float64")
+        n = x.numel()
+        self._keep = (x, y, z, mass)  # inputs stay alive while the stream uses them
+        self._rc(lib().tpm_build_tree(self.h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(mass)))
+        self.n = n
+
+    def compute_forces(self, active_idx, opening="bh", a_old_norm=None, acc=None, pot=None,
+                       n_interactions=None, want_pot=None):
+        if active_idx.dtype != torch.int32:
+            raise ValueError("active_idx must be int32")
+        na = active_idx.numel()
+        dev = active_idx.device
+        if acc is None:
+            acc = torch.empty((3, na), dtype=self.dtype, device=dev)
+        if pot is None and (want_pot or (want_pot is None and self.params.want_potential)):
+            pot = torch.empty(na, dtype=self.dtype, device=dev)
+        if a_old_norm is not None and a_old_norm.dtype != torch.float64:
+            raise ValueError("a_old_norm must be float64")
+        self._rc(lib().tpm_compute_forces(self.h, OPEN[opening], na, _ptr(active_idx),
+                                          _ptr(a_old_norm), _ptr(acc), _ptr(pot),
+                                          _ptr(n_interactions)))
+        return acc, pot
+
+    def pm_long_range(self, active_idx, acc=None, pot=None, want_pot=None):
+        if active_idx.dtype != torch.int32:
+            raise ValueError("active_idx must be int32")
+        na = active_idx.numel()
+        if acc is None:
+            acc = torch.empty((3, na), dtype=self.dtype, device=active_idx.device)
+        if pot is None and (want_pot or (want_pot is None and self.params.want_potential)):
+            pot = torch.empty(na, dtype=self.dtype, device=active_idx.device)
+        self._rc(lib().tpm_pm_long_range(self.h, na, _ptr(active_idx), _ptr(acc), _ptr(pot)))
+        return acc, pot
+
+    def accel_norm(self, active_idx, acc_a, acc_b=None, out=None):
+        """|acc_a + acc_b| into a float64 array in build order (for 'rel')."""
+        if out is None:
+            out = torch.zeros(self.n, dtype=torch.float64, device=active_idx.device)
+        self._rc(lib().tpm_accel_norm(self.h, active_idx.numel(), _ptr(active_idx),
+                                      _ptr(acc_a), _ptr(acc_b), _ptr(out)))
+        return out
+
+    # -- measurement -----------------------------------------------------------
+    TIMERS = {"walk": 0, "build": 1, "pm_solve": 2, "pm_interp": 3, "sort": 4, "walk_rel": 5}
+
+    def timing(self, on: bool = True):
+        self._rc(lib().tpm_timing_enable(self.h, int(on)))
+
+    def timing_read(self, kind: str):
+        ms = C.c_double()
+        k = C.c_int64()
+        self._rc(lib().tpm_timing_read(self.h, self.TIMERS[kind], C.byref(ms), C.byref(k)))
+        return float(ms.value), int(k.value)
+
+    # -- checks and verification --------------------------------------------
+    def check(self):
+        rc = lib().tpm_check(self.h)
+        if rc != TPM_OK:
+            raise TreePMError(rc, lib().tpm_last_error(self.h).decode())
+
+    def bytes_held(self) -> int:
+        return int(lib().tpm_bytes_held(self.h))
+
+    def tree_info(self):
+        n = C.c_int64()
+        E = C.c_int64()
+        fr = (C.c_double * 4)()
+        self._rc(lib().tpm_tree_info(self.h, C.byref(n), C.byref(E), fr))
+        return int(n.value), int(E.value), list(fr)
+
+    def export_tree(self):
+        import numpy as np
+        n, E, fr = self.tree_info()
+        out = dict(level=np.empty(E, np.int32), first=np.empty(E, np.int64),
+                   count=np.empty(E, np.int64), skip=np.empty(E, np.int64),
+                   pidx=np.empty(E, np.int64), mass=np.empty(E), com=np.empty(3 * E),
+                   cen=np.empty(3 * E), key=np.empty(n, np.uint64), perm=np.empty(n, np.int64))
+        args = [C.c_void_p(out[k].ctypes.data) for k in
+                ("level", "first", "count", "skip", "pidx", "mass", "com", "cen", "key", "perm")]
+        self._rc(lib().tpm_export_tree(self.h, *args))
+        out["com"] = out["com"].reshape(3, E)
+        out["cen"] = out["cen"].reshape(3, E)
+        out["frame"] = np.array(fr)
+        return out

@@ -1,0 +1,422 @@
+// C ABI of the gfx950 TreePM library: argument validation, buffer ownership,
+// error reporting and the verification export.  The hot path lives in
+// build.hip, walk.hip and pm.hip.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tpm_internal.h"
+
+namespace tpm {
+
+int fail(tpm_ctx *c, int code, const std::string &msg) {
+    if (c)
+        c->err = msg;
+    return code;
+}
+
+int hip_check(tpm_ctx *c, hipError_t e, const char *what) {
+    if (e == hipSuccess)
+        return TPM_OK;
+    const int code = (e == hipErrorOutOfMemory) ? TPM_ENOMEM : TPM_EDEVICE;
+    return fail(c, code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int ensure(tpm_ctx *c, DBuf &b, size_t bytes) {
+    if (bytes == 0)
+        bytes = 16;
+    if (b.cap >= bytes)
+        return TPM_OK;
+    if (b.p) {
+        TPM_HIP(c, hipStreamSynchronize(c->stream));
+        TPM_HIP(c, hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    const size_t want = bytes + bytes / 8;  // headroom for slightly larger rebuilds
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, TPM_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+    }
+    b.p = p;
+    b.cap = want;
+    return TPM_OK;
+}
+
+size_t bytes_held(const tpm_ctx *c) {
+    const DBuf *all[] = {&c->frame, &c->bbox, &c->key[0], &c->key[1], &c->idx[0], &c->idx[1],
+                         &c->hist, &c->scan_tmp, &c->perm, &c->rank, &c->ps, &c->ms, &c->qs,
+                         &c->dR, &c->cnt, &c->base, &c->lvl_cursor, &c->lvl_list, &c->rec64,
+                         &c->rec32, &c->efirst, &c->ecount, &c->pe, &c->mark, &c->act, &c->slot,
+                         &c->counters, &c->res, &c->rpot, &c->rnint, &c->err_flag, &c->mesh_q,
+                         &c->mesh_c, &c->mesh_phi, &c->twiddle, &c->green_axis};
+    size_t s = 0;
+    for (const DBuf *b : all)
+        s += b->cap;
+    return s;
+}
+
+static hipEvent_t take_event(tpm_ctx *c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+int timer_begin(tpm_ctx *c, int kind) {
+    if (!c->timing)
+        return TPM_OK;
+    hipEvent_t e = take_event(c);
+    if (!e)
+        return fail(c, TPM_EDEVICE, "hipEventCreate failed");
+    TPM_HIP(c, hipEventRecord(e, c->stream));
+    c->timed[kind].push_back({e, nullptr});
+    return TPM_OK;
+}
+
+int timer_end(tpm_ctx *c, int kind) {
+    if (!c->timing || c->timed[kind].empty() || c->timed[kind].back().second)
+        return TPM_OK;
+    hipEvent_t e = take_event(c);
+    if (!e)
+        return fail(c, TPM_EDEVICE, "hipEventCreate failed");
+    TPM_HIP(c, hipEventRecord(e, c->stream));
+    c->timed[kind].back().second = e;
+    return TPM_OK;
+}
+
+static void free_all(tpm_ctx *c) {
+    for (auto &v : c->timed) {
+        for (auto &pr : v) {
+            if (pr.first)
+                (void)hipEventDestroy(pr.first);
+            if (pr.second)
+                (void)hipEventDestroy(pr.second);
+        }
+        v.clear();
+    }
+    for (hipEvent_t e : c->event_pool)
+        (void)hipEventDestroy(e);
+    c->event_pool.clear();
+    DBuf *all[] = {&c->frame, &c->bbox, &c->key[0], &c->key[1], &c->idx[0], &c->idx[1],
+                   &c->hist, &c->scan_tmp, &c->perm, &c->rank, &c->ps, &c->ms, &c->qs,
+                   &c->dR, &c->cnt, &c->base, &c->lvl_cursor, &c->lvl_list, &c->rec64,
+                   &c->rec32, &c->efirst, &c->ecount, &c->pe, &c->mark, &c->act, &c->slot,
+                   &c->counters, &c->res, &c->rpot, &c->rnint, &c->err_flag, &c->mesh_q,
+                   &c->mesh_c, &c->mesh_phi, &c->twiddle, &c->green_axis};
+    for (DBuf *b : all) {
+        if (b->p)
+            (void)hipFree(b->p);
+        b->p = nullptr;
+        b->cap = 0;
+    }
+    if (c->hpin)
+        (void)hipHostFree(c->hpin);
+    c->hpin = nullptr;
+}
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static const char *validate(const tpm_params *p) {
+    if (!p)
+        return "params is NULL";
+    if (p->precision != TPM_FP64 && p->precision != TPM_FP32)
+        return "precision must be TPM_FP64 or TPM_FP32";
+    if (!(p->G > 0.0) || !std::isfinite(p->G))
+        return "G must be positive";
+    if (!(p->eps > 0.0) || !std::isfinite(p->eps))
+        return "eps must be positive";
+    if (!(p->theta >= 0.0) || !std::isfinite(p->theta))
+        return "theta must be >= 0";
+    if (!(p->alpha > 0.0) || !std::isfinite(p->alpha))
+        return "alpha must be positive";
+    for (int a = 0; a < 3; a++)
+        if (!(p->shift[a] >= 0.0 && p->shift[a] < 1.0))
+            return "shift must lie in [0, 1)";
+    if (p->periodic) {
+        if (!(p->box_size > 0.0) || !std::isfinite(p->box_size))
+            return "periodic box_size must be positive";
+        if (p->pm_grid == 0)
+            return "a periodic box needs the PM mesh (pm_grid > 0)";
+    }
+    if (p->pm_grid != 0) {
+        if (!p->periodic)
+            return "the PM mesh is implemented for periodic boxes only";
+        if (!is_pow2(p->pm_grid) || p->pm_grid < 8 || p->pm_grid > 1024)
+            return "pm_grid must be a power of two in [8, 1024]";
+        if (!(p->asmth > 0.0) || !(p->rcut > 0.0))
+            return "asmth and rcut must be positive";
+        const double rs = p->asmth * p->box_size / p->pm_grid;
+        if (!(p->rcut * rs < 0.5 * p->box_size))
+            return "cutoff radius must be below half the box";
+    }
+    if (p->want_potential != 0 && p->want_potential != 1)
+        return "want_potential must be 0 or 1";
+    return nullptr;
+}
+
+}  // namespace tpm
+
+using namespace tpm;
+
+extern "C" {
+
+int tpm_create(const tpm_params *p, void *hip_stream, tpm_ctx **out) {
+    if (!out)
+        return TPM_EINVAL;
+    *out = nullptr;
+    if (validate(p))
+        return TPM_EINVAL;
+    tpm_ctx *c = new (std::nothrow) tpm_ctx();
+    if (!c)
+        return TPM_ENOMEM;
+    c->P = *p;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return TPM_EDEVICE;
+    }
+    if (hipHostMalloc((void **)&c->hpin, 256 * sizeof(uint32_t), hipHostMallocDefault) !=
+        hipSuccess) {
+        delete c;
+        return TPM_ENOMEM;
+    }
+    *out = c;
+    return TPM_OK;
+}
+
+int tpm_destroy(tpm_ctx *c) {
+    if (!c)
+        return TPM_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+    return TPM_OK;
+}
+
+const char *tpm_last_error(const tpm_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+int tpm_set_stream(tpm_ctx *c, void *s) {
+    if (!c)
+        return TPM_EINVAL;
+    c->stream = (hipStream_t)s;
+    return TPM_OK;
+}
+
+int64_t tpm_bytes_needed(const tpm_params *p, int64_t n) {
+    if (validate(p) || n < 1)
+        return -1;
+    // per particle: sort buffers, ranks, sorted SoA, build scratch, active set,
+    // results; per entry (estimated at 2.5 n): records, first/count, level list
+    const int64_t per_part = 16 + 8 + 4 + 4 + 24 + 8 + 8 + 1 + 4 + 4 + 4 + 12 + 24 + 8 + 4;
+    const int64_t per_entry = 64 + (p->precision == TPM_FP32 ? 32 : 0) + 12;
+    int64_t b = n * per_part + (n * 5 / 2 + 64) * per_entry + (1 << 20);
+    if (p->pm_grid > 0) {
+        const int64_t n3 = (int64_t)p->pm_grid * p->pm_grid * p->pm_grid;
+        b += n3 * (8 + (p->precision == TPM_FP32 ? 12 : 24));
+    }
+    return b + b / 8;
+}
+
+int64_t tpm_bytes_held(const tpm_ctx *c) { return c ? (int64_t)bytes_held(c) : -1; }
+
+int tpm_build_tree(tpm_ctx *c, int64_t n, const double *x, const double *y, const double *z,
+                   const double *mass) {
+    if (!c)
+        return TPM_EINVAL;
+    if (n < 1 || n > (int64_t(1) << 30))
+        return fail(c, TPM_EINVAL, "n must lie in [1, 2^30]");
+    if (!x || !y || !z)
+        return fail(c, TPM_EINVAL, "positions must not be NULL");
+    TPM_HIP(c, hipSetDevice(c->device));
+    c->built = 0;
+    c->pm_ready = 0;
+    c->epoch = 0;  // marks must be cleared before the next active set
+    if (!c->err_flag.p) {
+        TPM_TRY(ensure(c, c->err_flag, 16));
+        TPM_TRY(fill_u32(c, (uint32_t *)c->err_flag.p, 0u, 4));
+    }
+    TPM_TRY(timer_begin(c, TPM_TIMER_BUILD));
+    TPM_TRY(build(c, n, x, y, z, mass));
+    TPM_TRY(timer_end(c, TPM_TIMER_BUILD));
+    c->built = 1;
+    return TPM_OK;
+}
+
+int tpm_compute_forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx,
+                       const double *anorm, void *acc, void *pot, uint32_t *nint) {
+    if (!c)
+        return TPM_EINVAL;
+    if (!c->built)
+        return fail(c, TPM_ESTATE, "compute_forces before build_tree");
+    if (opening != TPM_OPEN_BH && opening != TPM_OPEN_REL)
+        return fail(c, TPM_EINVAL, "opening must be TPM_OPEN_BH or TPM_OPEN_REL");
+    if (n_act < 0 || n_act > (int64_t(1) << 31) - 1)
+        return fail(c, TPM_EINVAL, "n_act out of range");
+    if (n_act > 0 && (!idx || !acc))
+        return fail(c, TPM_EINVAL, "active_idx and acc must not be NULL");
+    if (opening == TPM_OPEN_REL && n_act > 0 && !anorm)
+        return fail(c, TPM_EINVAL, "the relative criterion needs a_old_norm");
+    TPM_HIP(c, hipSetDevice(c->device));
+    return forces(c, opening, n_act, idx, anorm, acc, pot, nint);
+}
+
+int tpm_pm_long_range(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, void *pot) {
+    if (!c)
+        return TPM_EINVAL;
+    if (c->P.pm_grid <= 0 || !c->P.periodic)
+        return fail(c, TPM_EINVAL, "no PM mesh configured");
+    if (!c->built)
+        return fail(c, TPM_ESTATE, "pm_long_range before build_tree");
+    if (n_act < 0 || n_act > (int64_t(1) << 31) - 1)
+        return fail(c, TPM_EINVAL, "n_act out of range");
+    if (n_act > 0 && (!idx || !acc))
+        return fail(c, TPM_EINVAL, "active_idx and acc must not be NULL");
+    TPM_HIP(c, hipSetDevice(c->device));
+    if (!c->pm_ready) {
+        TPM_TRY(timer_begin(c, TPM_TIMER_PM_SOLVE));
+        TPM_TRY(pm_solve(c));
+        TPM_TRY(timer_end(c, TPM_TIMER_PM_SOLVE));
+        c->pm_ready = 1;
+    }
+    TPM_TRY(timer_begin(c, TPM_TIMER_PM_INTERP));
+    TPM_TRY(pm_interp(c, n_act, idx, acc, pot));
+    return timer_end(c, TPM_TIMER_PM_INTERP);
+}
+
+int tpm_accel_norm(tpm_ctx *c, int64_t n_act, const int32_t *idx, const void *a, const void *b,
+                   double *out) {
+    if (!c)
+        return TPM_EINVAL;
+    if (!c->built)
+        return fail(c, TPM_ESTATE, "accel_norm before build_tree");
+    if (n_act < 0 || n_act > (int64_t(1) << 31) - 1)
+        return fail(c, TPM_EINVAL, "n_act out of range");
+    if (n_act > 0 && (!idx || !a || !out))
+        return fail(c, TPM_EINVAL, "active_idx, acc_a and out must not be NULL");
+    TPM_HIP(c, hipSetDevice(c->device));
+    return accel_norm(c, n_act, idx, a, b, out);
+}
+
+int tpm_timing_enable(tpm_ctx *c, int on) {
+    if (!c)
+        return TPM_EINVAL;
+    c->timing = on ? 1 : 0;
+    return TPM_OK;
+}
+
+int tpm_timing_read(tpm_ctx *c, int kind, double *ms, int64_t *launches) {
+    if (!c || kind < 0 || kind >= 8)
+        return TPM_EINVAL;
+    TPM_HIP(c, hipStreamSynchronize(c->stream));
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (auto &pr : c->timed[kind]) {
+        if (pr.first && pr.second) {
+            float t = 0.0f;
+            TPM_HIP(c, hipEventElapsedTime(&t, pr.first, pr.second));
+            sum += t;
+            cnt++;
+        }
+        if (pr.first)
+            c->event_pool.push_back(pr.first);
+        if (pr.second)
+            c->event_pool.push_back(pr.second);
+    }
+    c->timed[kind].clear();
+    if (ms)
+        *ms = sum;
+    if (launches)
+        *launches = cnt;
+    return TPM_OK;
+}
+
+int tpm_check(tpm_ctx *c) {
+    if (!c)
+        return TPM_EINVAL;
+    TPM_HIP(c, hipStreamSynchronize(c->stream));
+    if (!c->err_flag.p)
+        return TPM_OK;
+    uint32_t f = 0;
+    TPM_HIP(c, hipMemcpy(&f, c->err_flag.p, 4, hipMemcpyDeviceToHost));
+    if (f) {
+        TPM_TRY(fill_u32(c, (uint32_t *)c->err_flag.p, 0u, 4));
+        TPM_HIP(c, hipStreamSynchronize(c->stream));
+        return fail(c, TPM_EINDEX, "an active index was out of range");
+    }
+    return TPM_OK;
+}
+
+int tpm_tree_info(tpm_ctx *c, int64_t *n, int64_t *ne, double *frame4) {
+    if (!c)
+        return TPM_EINVAL;
+    if (!c->built)
+        return fail(c, TPM_ESTATE, "no tree built");
+    TPM_HIP(c, hipStreamSynchronize(c->stream));
+    if (n)
+        *n = c->n;
+    if (ne)
+        *ne = c->E;
+    if (frame4) {
+        for (int a = 0; a < 3; a++)
+            frame4[a] = c->frame_host.x0[a];
+        frame4[3] = c->frame_host.L;
+    }
+    return TPM_OK;
+}
+
+int tpm_export_tree(tpm_ctx *c, int32_t *level, int64_t *first, int64_t *count, int64_t *skip,
+                    int64_t *pidx, double *mass, double *com, double *cen, uint64_t *key,
+                    int64_t *perm) {
+    if (!c)
+        return TPM_EINVAL;
+    if (!c->built)
+        return fail(c, TPM_ESTATE, "no tree built");
+    TPM_HIP(c, hipStreamSynchronize(c->stream));
+    const int64_t n = c->n, E = c->E;
+    std::vector<Rec64> rec(E);
+    std::vector<uint32_t> ef(E), ec(E);
+    std::vector<int32_t> pm(n);
+    TPM_HIP(c, hipMemcpy(rec.data(), c->rec64.p, E * sizeof(Rec64), hipMemcpyDeviceToHost));
+    TPM_HIP(c, hipMemcpy(ef.data(), c->efirst.p, E * 4, hipMemcpyDeviceToHost));
+    TPM_HIP(c, hipMemcpy(ec.data(), c->ecount.p, E * 4, hipMemcpyDeviceToHost));
+    TPM_HIP(c, hipMemcpy(pm.data(), c->perm.p, n * 4, hipMemcpyDeviceToHost));
+    if (key)
+        TPM_HIP(c, hipMemcpy(key, c->key[0].p, n * 8, hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < E; e++) {
+        const Rec64 &R = rec[e];
+        const bool part = (R.meta & kParticleFlag) != 0;
+        if (level)
+            level[e] = part ? -1 : (int32_t)(R.meta & 0xffu);
+        if (first)
+            first[e] = ef[e];
+        if (count)
+            count[e] = ec[e];
+        if (skip)
+            skip[e] = R.skip;
+        if (pidx)
+            pidx[e] = part ? pm[ef[e]] : -1;
+        if (mass)
+            mass[e] = R.mass;
+        for (int a = 0; a < 3; a++) {
+            if (com)
+                com[a * E + e] = R.com[a];
+            if (cen)
+                cen[a * E + e] = R.cen[a];
+        }
+    }
+    if (perm)
+        for (int64_t s = 0; s < n; s++)
+            perm[s] = pm[s];
+    return TPM_OK;
+}
+
+}  // extern "C"

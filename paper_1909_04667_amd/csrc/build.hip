@@ -1,0 +1,508 @@
+// Tree build for gfx950 (Sec. 3.1 of the Arepo paper: enclosing cube, a tree
+// rebuilt for every force computation, monopole moments; Sec. 8: Peano-
+// Hilbert ordering).
+//
+// Instead of inserting particles one by one, the tree is derived from the
+// sorted 63-bit keys: a node is a key prefix shared by at least two particles,
+// which is exactly the tree sequential insertion produces.  Every particle
+// starts the nodes whose prefix level lies between its common-prefix depths
+// with its left and right neighbours, so one scan over per-particle counts
+// gives the depth-first position of every entry, and skip pointers (end of a
+// subtree) come from a galloping search for the end of each prefix run.
+#include "tpm_internal.h"
+
+#include <vector>
+
+namespace tpm {
+namespace {
+
+constexpr int kBlock = 256;
+
+// ---- root cube -------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_bbox_partial(const double *__restrict__ x,
+                                                         const double *__restrict__ y,
+                                                         const double *__restrict__ z,
+                                                         int64_t n, double *__restrict__ part) {
+    __shared__ double s[6][kBlock];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const double *c[3] = {x, y, z};
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            double v = c[a][i];
+            lo[a] = fmin(lo[a], v);
+            hi[a] = fmax(hi[a], v);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        s[a][threadIdx.x] = lo[a];
+        s[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                s[a][threadIdx.x] = fmin(s[a][threadIdx.x], s[a][threadIdx.x + w]);
+                s[3 + a][threadIdx.x] = fmax(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + w]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6)
+        part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// Smallest power of two >= ext (1 + 2^-20) (1 when every particle coincides);
+// the corner sits below the minimum by a fraction shift of the slack.
+__global__ void k_frame_final(const double *__restrict__ part, int nparts, Frame *F,
+                              double s0, double s1, double s2) {
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < nparts; b++)
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmin(lo[a], part[b * 6 + a]);
+            hi[a] = fmax(hi[a], part[b * 6 + 3 + a]);
+        }
+    double ext = 0.0;
+    for (int a = 0; a < 3; a++) {
+        double e = hi[a] - lo[a];
+        ext = e > ext ? e : ext;
+    }
+    double L = 1.0;
+    if (ext > 0.0) {
+        double t = ext * (1.0 + 0x1p-20);
+        int ex;
+        double m = frexp(t, &ex);
+        L = (m == 0.5) ? ldexp(1.0, ex - 1) : ldexp(1.0, ex);
+    }
+    const double sh[3] = {s0, s1, s2};
+    for (int a = 0; a < 3; a++)
+        F->x0[a] = lo[a] - sh[a] * (L - (hi[a] - lo[a]));
+    F->L = L;
+    F->S = 2097152.0 / L;
+    F->box = 0.0;
+    F->periodic = 0;
+}
+
+// ---- keys ------------------------------------------------------------------
+
+// Tree-frame coordinate and 21-bit cell index of one coordinate value.
+__device__ __forceinline__ void to_frame(double xv, double x0, const Frame &F, double &p,
+                                         uint32_t &q) {
+    p = xv;
+    double u = p - x0;
+    if (F.periodic) {
+        if (u >= F.L) {
+            p = xv - F.L;
+            u = p - x0;
+        } else if (u < 0.0) {
+            p = xv + F.L;
+            u = p - x0;
+        }
+    }
+    double f = floor(u * F.S);
+    f = fmax(f, 0.0);
+    f = fmin(f, 2097151.0);
+    q = (uint32_t)f;
+}
+
+// Spread the low 21 bits of v to every third bit.
+__device__ __forceinline__ uint64_t dilate3(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// Peano-Hilbert index of a 21-bit cell (Skilling 2004, transpose form),
+// branch-free: each level either inverts the low bits of axis 0 or exchanges
+// them with the axis whose bit is clear; the closing Gray-code correction is
+// a suffix parity computed with shifts.
+__device__ __forceinline__ uint64_t hilbert_key(uint32_t a0, uint32_t a1, uint32_t a2) {
+    uint32_t X0 = a0, X1 = a1, X2 = a2;
+#pragma unroll
+    for (int b = kBits - 1; b >= 1; --b) {
+        const uint32_t P = (1u << b) - 1u;
+        const uint32_t m0 = 0u - ((X0 >> b) & 1u);
+        X0 ^= P & m0;
+        const uint32_t m1 = 0u - ((X1 >> b) & 1u);
+        const uint32_t t1 = (X0 ^ X1) & P & ~m1;
+        X0 ^= (P & m1) | t1;
+        X1 ^= t1;
+        const uint32_t m2 = 0u - ((X2 >> b) & 1u);
+        const uint32_t t2 = (X0 ^ X2) & P & ~m2;
+        X0 ^= (P & m2) | t2;
+        X2 ^= t2;
+    }
+    X1 ^= X0;
+    X2 ^= X1;
+    uint32_t z = X2;  // z_j = parity of bits >= j of X2
+    z ^= z >> 1;
+    z ^= z >> 2;
+    z ^= z >> 4;
+    z ^= z >> 8;
+    z ^= z >> 16;
+    const uint32_t t = z >> 1;
+    X0 ^= t;
+    X1 ^= t;
+    X2 ^= t;
+    return (dilate3(X0) << 2) | (dilate3(X1) << 1) | dilate3(X2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ x,
+                                                 const double *__restrict__ y,
+                                                 const double *__restrict__ z, int64_t n,
+                                                 const Frame *__restrict__ Fp,
+                                                 uint64_t *__restrict__ key,
+                                                 uint32_t *__restrict__ idx) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const Frame F = *Fp;
+    double p;
+    uint32_t q0, q1, q2;
+    to_frame(x[i], F.x0[0], F, p, q0);
+    to_frame(y[i], F.x0[1], F, p, q1);
+    to_frame(z[i], F.x0[2], F, p, q2);
+    key[i] = hilbert_key(q0, q1, q2);
+    idx[i] = (uint32_t)i;
+}
+
+// ---- gather into curve order -------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_gather(
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
+    const double *__restrict__ mass, int64_t n, const Frame *__restrict__ Fp,
+    const uint32_t *__restrict__ sidx, int32_t *__restrict__ perm, int32_t *__restrict__ rank,
+    double *__restrict__ ps, double *__restrict__ ms, uint64_t *__restrict__ qs) {
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n)
+        return;
+    const Frame F = *Fp;
+    const uint32_t i = sidx[s];
+    perm[s] = (int32_t)i;
+    rank[i] = (int32_t)s;
+    double p0, p1, p2;
+    uint32_t q0, q1, q2;
+    to_frame(x[i], F.x0[0], F, p0, q0);
+    to_frame(y[i], F.x0[1], F, p1, q1);
+    to_frame(z[i], F.x0[2], F, p2, q2);
+    ps[s] = p0;
+    ps[n + s] = p1;
+    ps[2 * n + s] = p2;
+    ms[s] = mass ? mass[i] : 1.0 / (double)n;
+    qs[s] = ((uint64_t)q0 << 42) | ((uint64_t)q1 << 21) | (uint64_t)q2;
+}
+
+// ---- topology ----------------------------------------------------------------
+
+// Number of leading 3-bit groups two keys share (0..21).
+__device__ __forceinline__ int common_levels(uint64_t a, uint64_t b) {
+    uint64_t d = a ^ b;
+    if (d == 0)
+        return kMaxLevel;
+    int top = 63 - __clzll((long long)d);
+    return (kMaxLevel - 1) - top / 3;
+}
+
+// Per particle: depth shared with the right neighbour, entries it starts
+// (nodes at levels (dL, dR] plus itself) and a per-level node histogram.
+__global__ __launch_bounds__(kBlock) void k_count(const uint64_t *__restrict__ key, int64_t n,
+                                                  int8_t *__restrict__ dR,
+                                                  uint32_t *__restrict__ cnt,
+                                                  uint32_t *__restrict__ lvl_count) {
+    __shared__ uint32_t h[kLevels];
+    if (threadIdx.x < kLevels)
+        h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s < n) {
+        const uint64_t k = key[s];
+        const int r = (s + 1 < n) ? common_levels(k, key[s + 1]) : -1;
+        const int l = (s > 0) ? common_levels(key[s - 1], k) : -1;
+        dR[s] = (int8_t)r;
+        const int nn = r > l ? r - l : 0;
+        cnt[s] = (uint32_t)nn + 1u;
+        for (int lev = l + 1; lev <= r; lev++)
+            atomicAdd(&h[lev], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kLevels && h[threadIdx.x])
+        atomicAdd(&lvl_count[threadIdx.x], h[threadIdx.x]);
+}
+
+__device__ __forceinline__ uint64_t prefix_at(uint64_t k, int lev) {
+    return k >> (3 * (kMaxLevel - lev));
+}
+
+// Emit the particle entry and the node entries a particle starts, deepest
+// first so that each run end is searched from the previous one.
+__global__ __launch_bounds__(kBlock) void k_emit(
+    const uint64_t *__restrict__ key, int64_t n, const int8_t *__restrict__ dR,
+    const uint32_t *__restrict__ base, uint32_t E, const Frame *__restrict__ Fp,
+    const double *__restrict__ ps, const double *__restrict__ ms,
+    const uint64_t *__restrict__ qs, Rec64 *__restrict__ rec, uint32_t *__restrict__ efirst,
+    uint32_t *__restrict__ ecount, uint32_t *__restrict__ pe, uint32_t *__restrict__ cursor,
+    uint32_t *__restrict__ lvl_list) {
+    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n)
+        return;
+    const Frame F = *Fp;
+    const int r = dR[s];
+    const int l = (s > 0) ? (int)dR[s - 1] : -1;
+    const uint32_t b = base[s];
+    const int nn = r > l ? r - l : 0;
+    // particle entry
+    const uint32_t ep = b + (uint32_t)nn;
+    {
+        Rec64 R;
+        R.com[0] = ps[s];
+        R.com[1] = ps[n + s];
+        R.com[2] = ps[2 * n + s];
+        R.mass = ms[s];
+        R.cen[0] = R.com[0];
+        R.cen[1] = R.com[1];
+        R.cen[2] = R.com[2];
+        R.skip = ep + 1u;
+        R.meta = kParticleFlag | (uint32_t)kMaxLevel;
+        rec[ep] = R;
+        efirst[ep] = (uint32_t)s;
+        ecount[ep] = 1u;
+        pe[s] = ep;
+    }
+    if (nn == 0)
+        return;
+    const uint64_t k = key[s];
+    const uint64_t qq = qs[s];
+    const uint32_t q[3] = {(uint32_t)(qq >> 42) & 0x1fffffu, (uint32_t)(qq >> 21) & 0x1fffffu,
+                           (uint32_t)qq & 0x1fffffu};
+    int64_t end = s;
+    for (int lev = r; lev > l; --lev) {
+        const uint64_t P = prefix_at(k, lev);
+        // gallop: key[end] carries prefix P; find the last index that does
+        int64_t lo = end, hi = end + 1, step = 1;
+        while (hi < n && prefix_at(key[hi], lev) == P) {
+            lo = hi;
+            step <<= 1;
+            hi = lo + step;
+        }
+        if (hi > n)
+            hi = n;
+        while (hi - lo > 1) {
+            int64_t mid = lo + ((hi - lo) >> 1);
+            if (prefix_at(key[mid], lev) == P)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        end = lo;
+        const uint32_t e = b + (uint32_t)(lev - l - 1);
+        Rec64 R;
+        const double len = ldexp(F.L, -lev);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const uint32_t P_a = q[a] >> (kBits - lev);
+            R.cen[a] = F.x0[a] + ((double)P_a + 0.5) * len;
+            R.com[a] = 0.0;
+        }
+        R.mass = 0.0;
+        R.skip = (end + 1 < n) ? base[end + 1] : E;
+        R.meta = (uint32_t)lev;
+        rec[e] = R;
+        efirst[e] = (uint32_t)s;
+        ecount[e] = (uint32_t)(end - s + 1);
+        lvl_list[atomicAdd(&cursor[lev], 1u)] = e;
+    }
+}
+
+// Monopole moments of the nodes of one level, children in curve order:
+// M = (M1 + M2) + ..., X = fma(M_k, s_k, X), s = X / M.
+__global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec,
+                                                    const uint32_t *__restrict__ list,
+                                                    uint32_t count) {
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= count)
+        return;
+    const uint32_t e = list[i];
+    const uint32_t end = rec[e].skip;
+    double M = 0.0, X0 = 0.0, X1 = 0.0, X2 = 0.0;
+    for (uint32_t k = e + 1; k < end; k = rec[k].skip) {
+        const double mk = rec[k].mass;
+        M = M + mk;
+        X0 = fma(mk, rec[k].com[0], X0);
+        X1 = fma(mk, rec[k].com[1], X1);
+        X2 = fma(mk, rec[k].com[2], X2);
+    }
+    rec[e].mass = M;
+    rec[e].com[0] = X0 / M;
+    rec[e].com[1] = X1 / M;
+    rec[e].com[2] = X2 / M;
+}
+
+// FP32 records: exact integer centres, float offsets of the centre of mass.
+__global__ __launch_bounds__(kBlock) void k_pack32(const Rec64 *__restrict__ rec, uint32_t E,
+                                                   const uint32_t *__restrict__ efirst,
+                                                   const uint64_t *__restrict__ qs,
+                                                   const Frame *__restrict__ Fp, double G,
+                                                   Rec32 *__restrict__ out) {
+    uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= E)
+        return;
+    const Frame F = *Fp;
+    const Rec64 R = rec[e];
+    const bool part = (R.meta & kParticleFlag) != 0;
+    const int lev = (int)(R.meta & 0xffu);
+    const uint64_t qq = qs[efirst[e]];
+    const uint32_t q[3] = {(uint32_t)(qq >> 42) & 0x1fffffu, (uint32_t)(qq >> 21) & 0x1fffffu,
+                           (uint32_t)qq & 0x1fffffu};
+    int32_t C[3];
+    double off[3];
+    const double len = ldexp(F.L, -lev);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const uint32_t P = q[a] >> (kBits - lev);
+        C[a] = (int32_t)(((2u * P + 1u) << (kBits - lev)));
+        const double cen = F.x0[a] + ((double)P + 0.5) * len;
+        off[a] = R.com[a] - cen;
+    }
+    Rec32 o;
+    o.dx = (float)off[0];
+    o.dy = (float)off[1];
+    o.dz = (float)off[2];
+    o.gm = (float)(G * R.mass);
+    o.cx_meta = C[0] | (lev << 22) | ((part ? 1 : 0) << 27);
+    o.cy = C[1];
+    o.cz = C[2];
+    o.skip = R.skip;
+    out[e] = o;
+}
+
+}  // namespace
+
+int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double *z,
+          const double *mass) {
+    hipStream_t st = c->stream;
+    const tpm_params &P = c->P;
+    // per-particle buffers
+    TPM_TRY(ensure(c, c->frame, sizeof(Frame)));
+    for (int b = 0; b < 2; b++) {
+        TPM_TRY(ensure(c, c->key[b], (size_t)n * 8));
+        TPM_TRY(ensure(c, c->idx[b], (size_t)n * 4));
+    }
+    TPM_TRY(ensure(c, c->perm, (size_t)n * 4));
+    TPM_TRY(ensure(c, c->rank, (size_t)n * 4));
+    TPM_TRY(ensure(c, c->ps, (size_t)n * 24));
+    TPM_TRY(ensure(c, c->ms, (size_t)n * 8));
+    TPM_TRY(ensure(c, c->qs, (size_t)n * 8));
+    TPM_TRY(ensure(c, c->dR, (size_t)n));
+    TPM_TRY(ensure(c, c->cnt, (size_t)n * 4));
+    TPM_TRY(ensure(c, c->base, (size_t)n * 4));
+    TPM_TRY(ensure(c, c->pe, (size_t)n * 4));
+    TPM_TRY(ensure(c, c->counters, 64 * sizeof(uint32_t)));
+    TPM_TRY(ensure(c, c->lvl_cursor, 32 * sizeof(uint32_t)));
+    Frame *F = (Frame *)c->frame.p;
+
+    // 1. root cube
+    if (P.periodic) {
+        Frame h{};
+        for (int a = 0; a < 3; a++)
+            h.x0[a] = -(P.shift[a] * P.box_size);
+        h.L = P.box_size;
+        h.S = 2097152.0 / P.box_size;
+        h.box = P.box_size;
+        h.periodic = 1;
+        c->frame_host = h;
+        TPM_HIP(c, hipMemcpyAsync(F, &c->frame_host, sizeof(Frame), hipMemcpyHostToDevice, st));
+    } else {
+        const int nparts = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+        TPM_TRY(ensure(c, c->bbox, (size_t)nparts * 6 * sizeof(double)));
+        k_bbox_partial<<<nparts, kBlock, 0, st>>>(x, y, z, n, (double *)c->bbox.p);
+        TPM_LAUNCHED(c, "k_bbox_partial");
+        k_frame_final<<<1, 64, 0, st>>>((const double *)c->bbox.p, nparts, F, P.shift[0],
+                                        P.shift[1], P.shift[2]);
+        TPM_LAUNCHED(c, "k_frame_final");
+    }
+    // 2. keys, 3. sort, gather
+    k_keys<<<grid_for(n, kBlock), kBlock, 0, st>>>(x, y, z, n, F, (uint64_t *)c->key[0].p,
+                                                   (uint32_t *)c->idx[0].p);
+    TPM_LAUNCHED(c, "k_keys");
+    TPM_TRY(radix_sort_pairs(c, n));
+    k_gather<<<grid_for(n, kBlock), kBlock, 0, st>>>(
+        x, y, z, mass, n, F, (const uint32_t *)c->idx[0].p, (int32_t *)c->perm.p,
+        (int32_t *)c->rank.p, (double *)c->ps.p, (double *)c->ms.p, (uint64_t *)c->qs.p);
+    TPM_LAUNCHED(c, "k_gather");
+    // 4. topology: counts, scan, one readback of the sizes
+    const uint64_t *key = (const uint64_t *)c->key[0].p;
+    uint32_t *lvl_count = (uint32_t *)c->counters.p;  // [0..21] level counts, [32] total
+    TPM_TRY(fill_u32(c, lvl_count, 0u, 64));
+    k_count<<<grid_for(n, kBlock), kBlock, 0, st>>>(key, n, (int8_t *)c->dR.p,
+                                                    (uint32_t *)c->cnt.p, lvl_count);
+    TPM_LAUNCHED(c, "k_count");
+    TPM_TRY(scan_u32(c, (const uint32_t *)c->cnt.p, (uint32_t *)c->base.p, n, lvl_count + 32));
+    TPM_HIP(c, hipMemcpyAsync(c->hpin, lvl_count, 64 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                              st));
+    if (!P.periodic)
+        TPM_HIP(c, hipMemcpyAsync(&c->frame_host, F, sizeof(Frame), hipMemcpyDeviceToHost, st));
+    TPM_HIP(c, hipStreamSynchronize(st));
+    const uint32_t E = c->hpin[32];
+    if ((uint64_t)E != (uint64_t)n + [&] {
+            uint64_t s = 0;
+            for (int l = 0; l < kLevels; l++)
+                s += c->hpin[l];
+            return s;
+        }())
+        return fail(c, TPM_EDEVICE, "tree build: entry count mismatch");
+    // cursor starts go through the upload half of the pinned buffer, which is
+    // rewritten only after the next build's readback synchronisation
+    uint32_t *up = c->hpin + 64;
+    uint32_t off = 0;
+    for (int l = 0; l < kLevels; l++) {
+        c->level_count[l] = c->hpin[l];
+        c->level_off[l] = off;
+        up[l] = off;
+        off += c->level_count[l];
+    }
+    c->level_off[kLevels] = off;
+    TPM_TRY(ensure(c, c->rec64, (size_t)E * sizeof(Rec64)));
+    TPM_TRY(ensure(c, c->efirst, (size_t)E * 4));
+    TPM_TRY(ensure(c, c->ecount, (size_t)E * 4));
+    TPM_TRY(ensure(c, c->lvl_list, (size_t)(off > 0 ? off : 1) * 4));
+    TPM_HIP(c, hipMemcpyAsync(c->lvl_cursor.p, up, kLevels * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, st));
+    Rec64 *rec = (Rec64 *)c->rec64.p;
+    k_emit<<<grid_for(n, kBlock), kBlock, 0, st>>>(
+        key, n, (const int8_t *)c->dR.p, (const uint32_t *)c->base.p, E, F,
+        (const double *)c->ps.p, (const double *)c->ms.p, (const uint64_t *)c->qs.p, rec,
+        (uint32_t *)c->efirst.p, (uint32_t *)c->ecount.p, (uint32_t *)c->pe.p,
+        (uint32_t *)c->lvl_cursor.p, (uint32_t *)c->lvl_list.p);
+    TPM_LAUNCHED(c, "k_emit");
+    // 5. moments, deepest level first
+    for (int l = kMaxLevel; l >= 0; l--) {
+        const uint32_t cnt = c->level_count[l];
+        if (!cnt)
+            continue;
+        k_moments<<<grid_for(cnt, kBlock), kBlock, 0, st>>>(
+            rec, (const uint32_t *)c->lvl_list.p + c->level_off[l], cnt);
+        TPM_LAUNCHED(c, "k_moments");
+    }
+    if (P.precision == TPM_FP32) {
+        TPM_TRY(ensure(c, c->rec32, (size_t)E * sizeof(Rec32)));
+        k_pack32<<<grid_for(E, kBlock), kBlock, 0, st>>>(rec, E, (const uint32_t *)c->efirst.p,
+                                                         (const uint64_t *)c->qs.p, F, P.G,
+                                                         (Rec32 *)c->rec32.p);
+        TPM_LAUNCHED(c, "k_pack32");
+    }
+    c->n = n;
+    c->E = E;
+    return TPM_OK;
+}
+
+}  // namespace tpm

@@ -1,0 +1,150 @@
+// Internal declarations of the gfx950 TreePM library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/treepm.h"
+
+namespace tpm {
+
+constexpr int kBits = 21;          // bits per axis of the integer coordinate
+constexpr int kMaxLevel = 21;      // deepest octree level (63-bit keys)
+constexpr int kLevels = kMaxLevel + 1;
+constexpr uint32_t kParticleFlag = 1u << 8;
+
+// Root frame of the last build, resident in device memory.
+struct Frame {
+    double x0[3];     // corner of the root cube (tree frame)
+    double L;         // side of the root cube
+    double S;         // 2^21 / L
+    double box;       // periodic box side (0 when isolated)
+    int32_t periodic;
+    int32_t pad;
+};
+
+// FP64 walk record, one per depth-first entry (64 bytes: one scalar-cache
+// line).  Particle entries: com = position, cen = position.
+struct alignas(64) Rec64 {
+    double com[3];
+    double mass;
+    double cen[3];
+    uint32_t skip;    // index of the entry after this subtree
+    uint32_t meta;    // level (bits 0-7) | kParticleFlag
+};
+
+// FP32 walk record (32 bytes).  Geometry is exact integer: the centre of the
+// cube is C * u with C = (2 P + 1) 2^(21-level), u = L_root 2^-22, P the
+// cube's integer corner at its level; a particle uses its depth-21 cell.
+// dcom = (centre of mass - centre) rounded to float; gm = G * mass.
+struct alignas(32) Rec32 {
+    float dx, dy, dz, gm;
+    int32_t cx_meta;  // C_x (22 bits) | level << 22 | particle << 27
+    int32_t cy, cz;
+    uint32_t skip;
+};
+
+struct DBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace tpm
+
+struct tpm_ctx {
+    tpm_params P;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    int64_t n = 0;          // particles of the last build
+    int64_t E = 0;          // depth-first entries of the last build
+    int built = 0;
+    int pm_ready = 0;
+    uint32_t epoch = 0;     // active-set marking generation
+    tpm::Frame frame_host{};
+    uint32_t level_count[tpm::kLevels] = {};
+    uint32_t level_off[tpm::kLevels + 1] = {};
+    // host pinned scratch for small readbacks
+    uint32_t *hpin = nullptr;
+    // device buffers
+    tpm::DBuf frame;            // Frame
+    tpm::DBuf bbox;             // per-block min/max partials
+    tpm::DBuf key[2], idx[2];   // sort ping-pong
+    tpm::DBuf hist;             // radix histograms / offsets
+    tpm::DBuf scan_tmp;         // scan block sums
+    tpm::DBuf perm, rank;       // rank -> build index, build index -> rank
+    tpm::DBuf ps, ms, qs;       // sorted positions [3][n], masses, packed q
+    tpm::DBuf dR, cnt, base;    // build: neighbour depth, entries per particle
+    tpm::DBuf lvl_cursor, lvl_list;
+    tpm::DBuf rec64, rec32, efirst, ecount;
+    tpm::DBuf pe;               // rank -> entry
+    tpm::DBuf mark, act, slot, counters;
+    tpm::DBuf res, rpot, rnint; // walk results in slot order
+    tpm::DBuf err_flag;
+    // particle mesh
+    tpm::DBuf mesh_q;           // fixed-point deposit
+    tpm::DBuf mesh_c;           // complex work mesh
+    tpm::DBuf mesh_phi;         // real potential
+    tpm::DBuf twiddle;          // FFT twiddles
+    tpm::DBuf green_axis;       // per-axis k^2 and deconvolution tables
+    // measurement: event pairs per timer class, and a pool of spare events
+    int timing = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[8];
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace tpm {
+
+// Error plumbing ---------------------------------------------------------
+int fail(tpm_ctx *c, int code, const std::string &msg);
+int hip_check(tpm_ctx *c, hipError_t e, const char *what);
+int ensure(tpm_ctx *c, DBuf &b, size_t bytes);
+size_t bytes_held(const tpm_ctx *c);
+
+#define TPM_TRY(expr)            \
+    do {                         \
+        int _rc = (expr);        \
+        if (_rc != TPM_OK)       \
+            return _rc;          \
+    } while (0)
+
+#define TPM_HIP(c, expr) TPM_TRY(::tpm::hip_check((c), (expr), #expr))
+#define TPM_LAUNCHED(c, name) TPM_TRY(::tpm::hip_check((c), hipGetLastError(), name))
+
+// Primitives (prims.hip) ---------------------------------------------------
+// Exclusive scan of n uint32 values; total written to d_total if non-null.
+int scan_u32(tpm_ctx *c, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *d_total);
+// Stable ascending sort of (key, value) pairs; result lands in key[0]/idx[0].
+int radix_sort_pairs(tpm_ctx *c, int64_t n);
+int fill_u32(tpm_ctx *c, uint32_t *p, uint32_t v, int64_t n);
+int fill_u64(tpm_ctx *c, uint64_t *p, uint64_t v, int64_t n);
+
+// Build (build.hip) --------------------------------------------------------
+int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double *z,
+          const double *mass);
+
+// Walk (walk.hip) ----------------------------------------------------------
+int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const double *anorm,
+           void *acc, void *pot, uint32_t *nint);
+int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx);
+
+// Particle mesh (pm.hip) -----------------------------------------------------
+int pm_solve(tpm_ctx *c);
+int pm_interp(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, void *pot);
+
+// Bracket kernels of one timer class with events (no-op unless enabled).
+int timer_begin(tpm_ctx *c, int kind);
+int timer_end(tpm_ctx *c, int kind);
+int accel_norm(tpm_ctx *c, int64_t n_act, const int32_t *idx, const void *a, const void *b,
+               double *out);
+
+inline unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace tpm

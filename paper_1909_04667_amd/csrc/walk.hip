@@ -1,0 +1,605 @@
+// Tree walk for gfx950 (Sec. 3.1 opening criteria and box rule, Sec. 3.2
+// spline softening, Sec. 3.4 short-range truncation and cutoff).
+//
+// One wavefront walks the depth-first entry list for 64 active particles that
+// are adjacent on the Peano-Hilbert curve.  The wave keeps ONE cursor: every
+// lane owns a "next" index (the entry its own depth-first walk needs next);
+// lanes whose next equals the cursor evaluate the entry, lanes that accepted
+// or discarded an ancestor sit out until the cursor reaches their next.  The
+// cursor descends (c + 1) when any lane opens the entry and otherwise jumps
+// to the entry's skip pointer -- that is the minimum of all lanes' next, since
+// subtrees nest.  Entries are read with wave-uniform (scalar) loads, so each
+// lane sees exactly the entry sequence of its own recursive walk, in order:
+// the FP64 path reproduces a sequential FP64 walk bit for bit apart from the
+// last bits of erfc/exp.
+#include "tpm_internal.h"
+
+namespace tpm {
+namespace {
+
+constexpr int kBlock = 256;
+
+struct WalkArgs {
+    const void *rec;
+    uint32_t E;
+    uint32_t n;
+    const uint32_t *act;
+    const uint32_t *nuniq;
+    const double *ps;
+    const uint64_t *qs;
+    const uint32_t *pe;
+    const int32_t *perm;
+    const double *anorm;
+    double x0[3];
+    double L;
+    double box, half;
+    double G, theta2, alpha, h, hinv, h3inv, rc2, inv2rs;
+    // single-precision copies
+    float fu, fL, ftheta2, falpha, fh2, fhinv, fh3inv, frc2, finv2rs;
+    void *res;
+    void *rpot;
+    uint32_t *rnint;
+};
+
+// ---- FP64 arithmetic (fixed operation order, explicit fma) -------------------
+
+__device__ __forceinline__ double spline_g64(double u) {
+    if (u < 0.5) {
+        double u2 = u * u;
+        return fma(u2, fma(32.0, u, -38.4), 32.0 / 3.0);
+    }
+    double cubic = fma(fma(fma(-32.0 / 3.0, u, 38.4), u, -48.0), u, 64.0 / 3.0);
+    return cubic - 1.0 / (15.0 * (u * u * u));
+}
+
+__device__ __forceinline__ double spline_phi64(double u) {
+    double u2 = u * u;
+    if (u < 0.5)
+        return u2 * (16.0 / 3.0 + u2 * (-48.0 / 5.0 + u * (32.0 / 5.0))) - 14.0 / 5.0;
+    return u2 * (32.0 / 3.0 + u * (-16.0 + u * (48.0 / 5.0 + u * (-32.0 / 15.0)))) - 16.0 / 5.0 +
+           1.0 / (15.0 * u);
+}
+
+template <bool TPM, bool POT>
+__device__ __forceinline__ void interact64(const WalkArgs &A, double m, double d0, double d1,
+                                           double d2, double dd, double &a0, double &a1,
+                                           double &a2, double &pot) {
+    const double Gm = A.G * m;
+    const double r = sqrt(dd);
+    double fac, phi = 0.0;
+    if (r >= A.h) {
+        const double rinv = 1.0 / r;
+        fac = Gm * rinv * rinv * rinv;
+        if (POT)
+            phi = -Gm * rinv;
+    } else {
+        const double u = r / A.h;
+        fac = (Gm * A.h3inv) * spline_g64(u);
+        if (POT)
+            phi = (Gm * A.hinv) * spline_phi64(u);
+    }
+    if (TPM) {
+        const double x = r * A.inv2rs;
+        fac = fac * (erfc(x) + (x * 1.1283791670955126) * exp(-(x * x)));
+        if (POT)
+            phi = phi * erfc(x);
+    }
+    a0 = fma(fac, d0, a0);
+    a1 = fma(fac, d1, a1);
+    a2 = fma(fac, d2, a2);
+    if (POT)
+        pot += phi;
+}
+
+template <bool PER>
+__device__ __forceinline__ double wrap64(double d, double box, double half) {
+    if (PER) {
+        if (d > half)
+            d -= box;
+        else if (d < -half)
+            d += box;
+    }
+    return d;
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT>
+__global__ __launch_bounds__(kBlock) void k_walk64(const WalkArgs A) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t nu = *A.nuniq;
+    if (wave * 64u >= nu)
+        return;  // whole wavefront
+    const uint32_t slot = wave * 64u + lane;
+    const bool valid = slot < nu;
+    const uint32_t s = A.act[valid ? slot : wave * 64u];
+    const double x0 = A.ps[s], x1 = A.ps[A.n + s], x2 = A.ps[2 * (size_t)A.n + s];
+    const uint32_t self = A.pe[s];
+    double an = 0.0;
+    if (OPEN == TPM_OPEN_REL)
+        an = A.anorm[A.perm[s]];
+    uint32_t next = valid ? 0u : 0xffffffffu;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, pot = 0.0;
+    uint32_t nint = 0;
+    const Rec64 *__restrict__ R = (const Rec64 *)A.rec;
+    uint32_t c = 0;
+    while (c < A.E) {
+        const uint32_t cu = __builtin_amdgcn_readfirstlane(c);
+        const Rec64 r = R[cu];
+        bool desc = false;
+        if (next == cu) {
+            const double d0 = wrap64<PER>(r.com[0] - x0, A.box, A.half);
+            const double d1 = wrap64<PER>(r.com[1] - x1, A.box, A.half);
+            const double d2 = wrap64<PER>(r.com[2] - x2, A.box, A.half);
+            const double dd = fma(d0, d0, fma(d1, d1, d2 * d2));
+            if (r.meta & kParticleFlag) {
+                next = cu + 1u;
+                if (cu != self && (!TPM || dd < A.rc2)) {
+                    interact64<TPM, POT>(A, r.mass, d0, d1, d2, dd, a0, a1, a2, pot);
+                    nint++;
+                }
+            } else {
+                const double L = ldexp(A.L, -(int)(r.meta & 0xffu));
+                const double c0 = wrap64<PER>(r.cen[0] - x0, A.box, A.half);
+                const double c1 = wrap64<PER>(r.cen[1] - x1, A.box, A.half);
+                const double c2 = wrap64<PER>(r.cen[2] - x2, A.box, A.half);
+                bool discard = false;
+                if (TPM) {
+                    const double hl = 0.5 * L;
+                    double e0 = fabs(c0) - hl, e1 = fabs(c1) - hl, e2 = fabs(c2) - hl;
+                    e0 = e0 > 0.0 ? e0 : 0.0;
+                    e1 = e1 > 0.0 ? e1 : 0.0;
+                    e2 = e2 > 0.0 ? e2 : 0.0;
+                    discard = fma(e0, e0, fma(e1, e1, e2 * e2)) > A.rc2;
+                }
+                if (discard) {
+                    next = r.skip;
+                } else {
+                    bool open;
+                    if (OPEN == TPM_OPEN_BH)
+                        open = (L * L) > A.theta2 * dd;
+                    else
+                        open = (A.G * r.mass) * (L * L) > (A.alpha * an) * (dd * dd);
+                    const double lim = 0.6 * L;
+                    if (fabs(c0) < lim && fabs(c1) < lim && fabs(c2) < lim)
+                        open = true;
+                    if (open) {
+                        next = cu + 1u;
+                        desc = true;
+                    } else {
+                        interact64<TPM, POT>(A, r.mass, d0, d1, d2, dd, a0, a1, a2, pot);
+                        nint++;
+                        next = r.skip;
+                    }
+                }
+            }
+        }
+        c = __ballot(desc) ? cu + 1u : r.skip;
+    }
+    if (valid) {
+        double *res = (double *)A.res;
+        res[slot] = a0;
+        res[A.n + slot] = a1;
+        res[2 * (size_t)A.n + slot] = a2;
+        if (POT)
+            ((double *)A.rpot)[slot] = pot;
+        A.rnint[slot] = nint;
+    }
+}
+
+// ---- FP32 walk ----------------------------------------------------------------
+
+__device__ __forceinline__ float spline_g32(float u) {
+    if (u < 0.5f) {
+        const float u2 = u * u;
+        return fmaf(u2, fmaf(32.0f, u, -38.4f), 10.6666667f);
+    }
+    const float cubic = fmaf(fmaf(fmaf(-10.6666667f, u, 38.4f), u, -48.0f), u, 21.3333333f);
+    return cubic - __builtin_amdgcn_rcpf(15.0f * u * u * u);
+}
+
+__device__ __forceinline__ float spline_phi32(float u) {
+    const float u2 = u * u;
+    if (u < 0.5f)
+        return fmaf(u2, fmaf(u2, fmaf(u, 6.4f, -9.6f), 5.33333333f), -2.8f);
+    return fmaf(u2, fmaf(u, fmaf(u, fmaf(u, -2.13333333f, 9.6f), -16.0f), 10.6666667f), -3.2f) +
+           __builtin_amdgcn_rcpf(15.0f * u);
+}
+
+template <bool TPM, bool POT>
+__device__ __forceinline__ void interact32(const WalkArgs &A, float gm, float d0, float d1,
+                                           float d2, float dd, float &a0, float &a1, float &a2,
+                                           float &pot) {
+    float fac, phi = 0.0f, r = 0.0f;
+    if (dd >= A.fh2) {
+        const float rinv = __builtin_amdgcn_rsqf(dd);
+        fac = gm * rinv * rinv * rinv;
+        if (POT)
+            phi = -gm * rinv;
+        if (TPM)
+            r = dd * rinv;
+    } else {
+        r = __builtin_amdgcn_sqrtf(dd);
+        const float u = r * A.fhinv;
+        fac = (gm * A.fh3inv) * spline_g32(u);
+        if (POT)
+            phi = (gm * A.fhinv) * spline_phi32(u);
+    }
+    if (TPM) {
+        // erfc by Abramowitz & Stegun 7.1.26 (|error| < 1.5e-7), sharing
+        // exp(-x^2) with the Gaussian term of the short-range factor
+        const float x = r * A.finv2rs;
+        const float g = __builtin_amdgcn_exp2f(-(x * x) * 1.44269504f);
+        const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+        const float poly =
+            t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f),
+                             -0.284496736f),
+                     0.254829592f);
+        const float ec = poly * g;
+        fac *= fmaf(x * 1.12837917f, g, ec);
+        if (POT)
+            phi *= ec;
+    }
+    a0 = fmaf(fac, d0, a0);
+    a1 = fmaf(fac, d1, a1);
+    a2 = fmaf(fac, d2, a2);
+    if (POT)
+        pot += phi;
+}
+
+template <bool PER>
+__device__ __forceinline__ int32_t wrapi(int32_t d) {
+    if (PER) {  // the periodic box spans 2^22 units
+        if (d > (1 << 21))
+            d -= (1 << 22);
+        else if (d < -(1 << 21))
+            d += (1 << 22);
+    }
+    return d;
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT>
+__global__ __launch_bounds__(kBlock) void k_walk32(const WalkArgs A) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t nu = *A.nuniq;
+    if (wave * 64u >= nu)
+        return;
+    const uint32_t slot = wave * 64u + lane;
+    const bool valid = slot < nu;
+    const uint32_t s = A.act[valid ? slot : wave * 64u];
+    // own depth-21 cell centre (integer, units of u = L_root 2^-22) and the
+    // float offset of the particle from it
+    const uint64_t qq = A.qs[s];
+    const uint32_t q0 = (uint32_t)(qq >> 42) & 0x1fffffu, q1 = (uint32_t)(qq >> 21) & 0x1fffffu,
+                   q2 = (uint32_t)qq & 0x1fffffu;
+    const int32_t G0 = (int32_t)(2u * q0 + 1u), G1 = (int32_t)(2u * q1 + 1u),
+                  G2 = (int32_t)(2u * q2 + 1u);
+    const double len21 = ldexp(A.L, -kMaxLevel);
+    const float xr0 = (float)(A.ps[s] - (A.x0[0] + ((double)q0 + 0.5) * len21));
+    const float xr1 = (float)(A.ps[A.n + s] - (A.x0[1] + ((double)q1 + 0.5) * len21));
+    const float xr2 = (float)(A.ps[2 * (size_t)A.n + s] - (A.x0[2] + ((double)q2 + 0.5) * len21));
+    const uint32_t self = A.pe[s];
+    float an = 0.0f;
+    if (OPEN == TPM_OPEN_REL)
+        an = (float)A.anorm[A.perm[s]];
+    const float alpha_an = A.falpha * an;
+    uint32_t next = valid ? 0u : 0xffffffffu;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, pot = 0.0f;
+    uint32_t nint = 0;
+    const Rec32 *__restrict__ R = (const Rec32 *)A.rec;
+    uint32_t c = 0;
+    while (c < A.E) {
+        const uint32_t cu = __builtin_amdgcn_readfirstlane(c);
+        const Rec32 r = R[cu];
+        bool desc = false;
+        if (next == cu) {
+            const int32_t cm = r.cx_meta;
+            const float o0 = (float)wrapi<PER>((cm & 0x3fffff) - G0) * A.fu;
+            const float o1 = (float)wrapi<PER>(r.cy - G1) * A.fu;
+            const float o2 = (float)wrapi<PER>(r.cz - G2) * A.fu;
+            // target -> centre of the entry, and target -> centre of mass
+            const float c0 = o0 - xr0, c1 = o1 - xr1, c2 = o2 - xr2;
+            const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
+            const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+            if (cm & (1 << 27)) {
+                next = cu + 1u;
+                if (cu != self && (!TPM || dd < A.frc2)) {
+                    interact32<TPM, POT>(A, r.gm, d0, d1, d2, dd, a0, a1, a2, pot);
+                    nint++;
+                }
+            } else {
+                const float L = __builtin_amdgcn_ldexpf(A.fL, -((cm >> 22) & 31));
+                bool discard = false;
+                if (TPM) {
+                    const float hl = 0.5f * L;
+                    const float e0 = fmaxf(fabsf(c0) - hl, 0.0f);
+                    const float e1 = fmaxf(fabsf(c1) - hl, 0.0f);
+                    const float e2 = fmaxf(fabsf(c2) - hl, 0.0f);
+                    discard = fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) > A.frc2;
+                }
+                if (discard) {
+                    next = r.skip;
+                } else {
+                    const float L2 = L * L;
+                    bool open;
+                    if (OPEN == TPM_OPEN_BH)
+                        open = L2 > A.ftheta2 * dd;
+                    else
+                        open = r.gm * L2 > alpha_an * (dd * dd);
+                    const float lim = 0.6f * L;
+                    if (fabsf(c0) < lim && fabsf(c1) < lim && fabsf(c2) < lim)
+                        open = true;
+                    if (open) {
+                        next = cu + 1u;
+                        desc = true;
+                    } else {
+                        interact32<TPM, POT>(A, r.gm, d0, d1, d2, dd, a0, a1, a2, pot);
+                        nint++;
+                        next = r.skip;
+                    }
+                }
+            }
+        }
+        c = __ballot(desc) ? cu + 1u : r.skip;
+    }
+    if (valid) {
+        float *res = (float *)A.res;
+        res[slot] = a0;
+        res[A.n + slot] = a1;
+        res[2 * (size_t)A.n + slot] = a2;
+        if (POT)
+            ((float *)A.rpot)[slot] = pot;
+        A.rnint[slot] = nint;
+    }
+}
+
+// ---- active set -> slots in curve order --------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_mark(const int32_t *__restrict__ idx, int64_t n_act,
+                                                 int64_t n, const int32_t *__restrict__ rank,
+                                                 uint32_t *__restrict__ mark, uint32_t epoch) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n_act)
+        return;
+    const int32_t i = idx[k];
+    if (i < 0 || (int64_t)i >= n)
+        return;  // reported by the output kernel
+    mark[rank[i]] = epoch;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flags(const uint32_t *__restrict__ mark, int64_t n,
+                                                  uint32_t epoch, uint32_t *__restrict__ flag) {
+    int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r < n)
+        flag[r] = mark[r] == epoch ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact(const uint32_t *__restrict__ flag,
+                                                    const uint32_t *__restrict__ pos, int64_t n,
+                                                    uint32_t *__restrict__ act,
+                                                    uint32_t *__restrict__ slot) {
+    int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r < n && flag[r]) {
+        act[pos[r]] = (uint32_t)r;
+        slot[r] = pos[r];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_output(
+    const int32_t *__restrict__ idx, int64_t n_act, int64_t n, const int32_t *__restrict__ rank,
+    const uint32_t *__restrict__ slot, const T *__restrict__ res, const T *__restrict__ rpot,
+    const uint32_t *__restrict__ rnint, T *__restrict__ acc, T *__restrict__ pot,
+    uint32_t *__restrict__ nint, uint32_t *__restrict__ err) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n_act)
+        return;
+    const int32_t i = idx[k];
+    if (i < 0 || (int64_t)i >= n) {
+        const T nan = (T)NAN;
+        acc[k] = nan;
+        acc[n_act + k] = nan;
+        acc[2 * n_act + k] = nan;
+        if (pot)
+            pot[k] = nan;
+        if (nint)
+            nint[k] = 0xffffffffu;
+        atomicOr(err, 1u);
+        return;
+    }
+    const uint32_t sl = slot[rank[i]];
+    acc[k] = res[sl];
+    acc[n_act + k] = res[n + sl];
+    acc[2 * n_act + k] = res[2 * n + sl];
+    if (pot)
+        pot[k] = rpot[sl];
+    if (nint)
+        nint[k] = rnint[sl];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_accel_norm(const int32_t *__restrict__ idx,
+                                                       int64_t n_act, int64_t n,
+                                                       const T *__restrict__ a,
+                                                       const T *__restrict__ b,
+                                                       double *__restrict__ out,
+                                                       uint32_t *__restrict__ err) {
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n_act)
+        return;
+    const int32_t i = idx[k];
+    if (i < 0 || (int64_t)i >= n) {
+        atomicOr(err, 1u);
+        return;
+    }
+    double v[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        v[d] = (double)a[d * n_act + k];
+        if (b)
+            v[d] += (double)b[d * n_act + k];
+    }
+    out[i] = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT>
+void launch_walk(const WalkArgs &A, bool fp32, unsigned blocks, hipStream_t st) {
+    if (fp32)
+        k_walk32<PER, TPM, OPEN, POT><<<blocks, kBlock, 0, st>>>(A);
+    else
+        k_walk64<PER, TPM, OPEN, POT><<<blocks, kBlock, 0, st>>>(A);
+}
+
+template <bool PER, bool TPM>
+void dispatch_open_pot(const WalkArgs &A, bool fp32, int open, bool pot, unsigned blocks,
+                       hipStream_t st) {
+    if (open == TPM_OPEN_BH) {
+        if (pot)
+            launch_walk<PER, TPM, TPM_OPEN_BH, true>(A, fp32, blocks, st);
+        else
+            launch_walk<PER, TPM, TPM_OPEN_BH, false>(A, fp32, blocks, st);
+    } else {
+        if (pot)
+            launch_walk<PER, TPM, TPM_OPEN_REL, true>(A, fp32, blocks, st);
+        else
+            launch_walk<PER, TPM, TPM_OPEN_REL, false>(A, fp32, blocks, st);
+    }
+}
+
+}  // namespace
+
+int accel_norm(tpm_ctx *c, int64_t n_act, const int32_t *idx, const void *a, const void *b,
+               double *out) {
+    if (n_act == 0)
+        return TPM_OK;
+    const unsigned g = grid_for(n_act, kBlock);
+    if (c->P.precision == TPM_FP32)
+        k_accel_norm<float><<<g, kBlock, 0, c->stream>>>(idx, n_act, c->n, (const float *)a,
+                                                         (const float *)b, out,
+                                                         (uint32_t *)c->err_flag.p);
+    else
+        k_accel_norm<double><<<g, kBlock, 0, c->stream>>>(idx, n_act, c->n, (const double *)a,
+                                                          (const double *)b, out,
+                                                          (uint32_t *)c->err_flag.p);
+    TPM_LAUNCHED(c, "k_accel_norm");
+    return TPM_OK;
+}
+
+int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
+    const int64_t n = c->n;
+    hipStream_t st = c->stream;
+    TPM_TRY(ensure(c, c->mark, (size_t)n * 4));
+    TPM_TRY(ensure(c, c->act, (size_t)n * 4));
+    TPM_TRY(ensure(c, c->slot, (size_t)n * 4));
+    uint32_t *mark = (uint32_t *)c->mark.p;
+    if (++c->epoch == 0 || c->epoch == 1) {  // fresh or wrapped: clear the marks
+        TPM_TRY(fill_u32(c, mark, 0u, n));
+        c->epoch = 1;
+    }
+    if (n_act > 0) {
+        k_mark<<<grid_for(n_act, kBlock), kBlock, 0, st>>>(idx, n_act, n,
+                                                           (const int32_t *)c->rank.p, mark,
+                                                           c->epoch);
+        TPM_LAUNCHED(c, "k_mark");
+    }
+    uint32_t *flag = (uint32_t *)c->cnt.p;  // build scratch, free after the build
+    uint32_t *pos = (uint32_t *)c->base.p;
+    k_flags<<<grid_for(n, kBlock), kBlock, 0, st>>>(mark, n, c->epoch, flag);
+    TPM_LAUNCHED(c, "k_flags");
+    uint32_t *nuniq = (uint32_t *)c->counters.p + 40;
+    TPM_TRY(scan_u32(c, flag, pos, n, nuniq));
+    k_compact<<<grid_for(n, kBlock), kBlock, 0, st>>>(flag, pos, n, (uint32_t *)c->act.p,
+                                                      (uint32_t *)c->slot.p);
+    TPM_LAUNCHED(c, "k_compact");
+    return TPM_OK;
+}
+
+int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const double *anorm,
+           void *acc, void *pot, uint32_t *nint) {
+    const tpm_params &P = c->P;
+    const int64_t n = c->n;
+    hipStream_t st = c->stream;
+    const bool fp32 = P.precision == TPM_FP32;
+    const size_t esz = fp32 ? 4 : 8;
+    TPM_TRY(ensure(c, c->res, (size_t)3 * n * esz));
+    TPM_TRY(ensure(c, c->rpot, (size_t)n * esz));
+    TPM_TRY(ensure(c, c->rnint, (size_t)n * 4));
+    TPM_TRY(ensure(c, c->err_flag, 16));
+    if (n_act == 0)
+        return TPM_OK;
+    TPM_TRY(select_active(c, n_act, idx));
+
+    WalkArgs A{};
+    A.rec = fp32 ? c->rec32.p : c->rec64.p;
+    A.E = (uint32_t)c->E;
+    A.n = (uint32_t)n;
+    A.act = (const uint32_t *)c->act.p;
+    A.nuniq = (const uint32_t *)c->counters.p + 40;
+    A.ps = (const double *)c->ps.p;
+    A.qs = (const uint64_t *)c->qs.p;
+    A.pe = (const uint32_t *)c->pe.p;
+    A.perm = (const int32_t *)c->perm.p;
+    A.anorm = anorm;
+    for (int a = 0; a < 3; a++)
+        A.x0[a] = c->frame_host.x0[a];
+    A.L = c->frame_host.L;
+    A.box = P.periodic ? P.box_size : 0.0;
+    A.half = 0.5 * A.box;
+    const bool tpm_on = P.pm_grid > 0;
+    const double rs = tpm_on ? P.asmth * P.box_size / P.pm_grid : 1.0;
+    const double rcut = tpm_on ? P.rcut * rs : 0.0;
+    A.G = P.G;
+    A.theta2 = P.theta * P.theta;
+    A.alpha = P.alpha;
+    A.h = 2.8 * P.eps;
+    A.hinv = 1.0 / A.h;
+    A.h3inv = A.hinv * A.hinv * A.hinv;
+    A.rc2 = rcut * rcut;
+    A.inv2rs = 0.5 / rs;
+    A.fu = (float)ldexp(A.L, -22);
+    A.fL = (float)A.L;
+    A.ftheta2 = (float)A.theta2;
+    A.falpha = (float)A.alpha;
+    A.fh2 = (float)(A.h * A.h);
+    A.fhinv = (float)A.hinv;
+    A.fh3inv = (float)A.h3inv;
+    A.frc2 = (float)A.rc2;
+    A.finv2rs = (float)A.inv2rs;
+    A.res = c->res.p;
+    A.rpot = c->rpot.p;
+    A.rnint = (uint32_t *)c->rnint.p;
+
+    const int64_t waves = (std::min<int64_t>(n_act, n) + 63) / 64;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    const bool want_pot = pot != nullptr && P.want_potential;
+    const int tkind = opening == TPM_OPEN_REL ? TPM_TIMER_WALK_REL : TPM_TIMER_WALK;
+    TPM_TRY(timer_begin(c, tkind));
+    if (P.periodic) {
+        if (tpm_on)
+            dispatch_open_pot<true, true>(A, fp32, opening, want_pot, blocks, st);
+        else
+            dispatch_open_pot<true, false>(A, fp32, opening, want_pot, blocks, st);
+    } else {
+        if (tpm_on)
+            dispatch_open_pot<false, true>(A, fp32, opening, want_pot, blocks, st);
+        else
+            dispatch_open_pot<false, false>(A, fp32, opening, want_pot, blocks, st);
+    }
+    TPM_LAUNCHED(c, "k_walk");
+    TPM_TRY(timer_end(c, tkind));
+    const unsigned ob = grid_for(n_act, kBlock);
+    if (fp32)
+        k_output<float><<<ob, kBlock, 0, st>>>(
+            idx, n_act, n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
+            (const float *)c->res.p, (const float *)c->rpot.p, (const uint32_t *)c->rnint.p,
+            (float *)acc, want_pot ? (float *)pot : nullptr, nint, (uint32_t *)c->err_flag.p);
+    else
+        k_output<double><<<ob, kBlock, 0, st>>>(
+            idx, n_act, n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
+            (const double *)c->res.p, (const double *)c->rpot.p, (const uint32_t *)c->rnint.p,
+            (double *)acc, want_pot ? (double *)pot : nullptr, nint, (uint32_t *)c->err_flag.p);
+    TPM_LAUNCHED(c, "k_output");
+    return TPM_OK;
+}
+
+}  // namespace tpm
