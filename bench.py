@@ -42,6 +42,10 @@ FLOPS_TREEPM = 17 + 19
 PEAK = {"fp32": 157.3, "fp64": 78.6}  # TFLOP/s, MI355X vector ALU
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,8 +188,12 @@ def main():
         sys.exit(2)
     import numpy as np
     c, p, kw = workload(args.config)
+    log(f"workload {c['name']} N={p.n} ready")
     precs = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
-    res = {pr: run_gpu(p, kw, pr, args.steps, args.warmup) for pr in precs}
+    res = {}
+    for pr in precs:
+        res[pr] = run_gpu(p, kw, pr, args.steps, args.warmup)
+        log(f"{pr}: {res[pr]['ms_per_step']:.3f} ms/step")
     head = res[precs[0]]
     periodic = bool(kw.get("periodic"))
     fl = FLOPS_TREEPM if periodic else FLOPS_NEWTON
@@ -247,6 +255,7 @@ def main():
                                     "max": float(e.max())}
         line["fp32_speedup_vs_fp64"] = out_prec["fp64"]["ms_per_step"] / h["ms_per_step"]
     if not args.no_cpu:
+        log("timing the CPU oracle on a sample")
         cb = cpu_baseline(p, kw, args.cpu_sample, args.config)
         a_or = cb.pop("acc_sample")
         samp = cb.pop("samp")

@@ -17,11 +17,12 @@ OUT = os.path.join(HERE, "libtreepm.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["prims.hip", "build.hip", "walk.hip", "pm.hip", "api.hip"]
 
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function",
+    "-Wall", "-Wno-unused-function", "-I", INCLUDE,
 ]
 
 

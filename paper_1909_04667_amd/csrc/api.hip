@@ -2,6 +2,7 @@
 // error reporting and the verification export.  The hot path lives in
 // build.hip, walk.hip and pm.hip.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -180,6 +181,12 @@ int tpm_create(const tpm_params *p, void *hip_stream, tpm_ctx **out) {
         return TPM_ENOMEM;
     c->P = *p;
     c->stream = (hipStream_t)hip_stream;
+    // tuning override of the walk variant (0 automatic, 1 shared cursor,
+    // 2 independent lanes); both variants give identical results
+    if (const char *m = std::getenv("TPM_WALK_MODE")) {
+        const int v = std::atoi(m);
+        c->walk_mode = (v == 1 || v == 2) ? v : 0;
+    }
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return TPM_EDEVICE;

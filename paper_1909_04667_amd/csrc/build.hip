@@ -224,15 +224,21 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint64_t *__restrict__ k
         h[threadIdx.x] = 0;
     __syncthreads();
     int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int r = -1, l = -1;
     if (s < n) {
         const uint64_t k = key[s];
-        const int r = (s + 1 < n) ? common_levels(k, key[s + 1]) : -1;
-        const int l = (s > 0) ? common_levels(key[s - 1], k) : -1;
+        r = (s + 1 < n) ? common_levels(k, key[s + 1]) : -1;
+        l = (s > 0) ? common_levels(key[s - 1], k) : -1;
         dR[s] = (int8_t)r;
         const int nn = r > l ? r - l : 0;
         cnt[s] = (uint32_t)nn + 1u;
-        for (int lev = l + 1; lev <= r; lev++)
-            atomicAdd(&h[lev], 1u);
+    }
+    // one LDS add per wavefront and level
+    const int lane = threadIdx.x & 63;
+    for (int lev = 0; lev < kLevels; lev++) {
+        const uint64_t m = __ballot(lev > l && lev <= r);
+        if (m && lane == __ffsll((long long)m) - 1)
+            atomicAdd(&h[lev], (uint32_t)__popcll(m));
     }
     __syncthreads();
     if (threadIdx.x < kLevels && h[threadIdx.x])
@@ -253,13 +259,33 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     uint32_t *__restrict__ ecount, uint32_t *__restrict__ pe, uint32_t *__restrict__ cursor,
     uint32_t *__restrict__ lvl_list) {
     int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= n)
+    const bool live = s < n;
+    const int r = live ? (int)dR[s] : -1;
+    const int l = (live && s > 0) ? (int)dR[s - 1] : -1;
+    const uint32_t b = live ? base[s] : 0u;
+    const int nn = r > l ? r - l : 0;
+    // level lists: one cursor atomic per wavefront and level (nodes of level
+    // lev started by this particle sit at entry b + lev - l - 1)
+    {
+        const int lane = threadIdx.x & 63;
+        const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+        for (int lev = 0; lev < kLevels; lev++) {
+            const bool has = lev > l && lev <= r;
+            const uint64_t m = __ballot(has);
+            if (!m)
+                continue;
+            const int leader = __ffsll((long long)m) - 1;
+            uint32_t at = 0;
+            if (lane == leader)
+                at = atomicAdd(&cursor[lev], (uint32_t)__popcll(m));
+            at = __shfl(at, leader, 64);
+            if (has)
+                lvl_list[at + (uint32_t)__popcll(m & lt)] = b + (uint32_t)(lev - l - 1);
+        }
+    }
+    if (!live)
         return;
     const Frame F = *Fp;
-    const int r = dR[s];
-    const int l = (s > 0) ? (int)dR[s - 1] : -1;
-    const uint32_t b = base[s];
-    const int nn = r > l ? r - l : 0;
     // particle entry
     const uint32_t ep = b + (uint32_t)nn;
     {
@@ -319,7 +345,6 @@ __global__ __launch_bounds__(kBlock) void k_emit(
         rec[e] = R;
         efirst[e] = (uint32_t)s;
         ecount[e] = (uint32_t)(end - s + 1);
-        lvl_list[atomicAdd(&cursor[lev], 1u)] = e;
     }
 }
 

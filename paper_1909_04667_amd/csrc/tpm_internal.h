@@ -8,7 +8,7 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/treepm.h"
+#include "treepm.h"
 
 namespace tpm {
 
@@ -65,6 +65,7 @@ struct tpm_ctx {
     int built = 0;
     int pm_ready = 0;
     uint32_t epoch = 0;     // active-set marking generation
+    int walk_mode = 0;      // 0: automatic, 1: shared cursor, 2: independent lanes
     tpm::Frame frame_host{};
     uint32_t level_count[tpm::kLevels] = {};
     uint32_t level_off[tpm::kLevels + 1] = {};

@@ -248,12 +248,10 @@ __device__ __forceinline__ void interact32(const WalkArgs &A, float gm, float d0
 
 template <bool PER>
 __device__ __forceinline__ int32_t wrapi(int32_t d) {
-    if (PER) {  // the periodic box spans 2^22 units
-        if (d > (1 << 21))
-            d -= (1 << 22);
-        else if (d < -(1 << 21))
-            d += (1 << 22);
-    }
+    // the periodic box spans 2^22 units: the nearest image is the difference
+    // modulo 2^22, sign-extended from 22 bits (one bit-field extract)
+    if (PER)
+        d = (int32_t)((uint32_t)d << 10) >> 10;
     return d;
 }
 
@@ -353,6 +351,193 @@ __global__ __launch_bounds__(kBlock) void k_walk32(const WalkArgs A) {
     }
 }
 
+// ---- lane-independent walks ------------------------------------------------
+//
+// Each lane walks its own targets: its cursor follows exactly the depth-first
+// sequence of its own walk (open -> next entry, accept/discard -> skip), so
+// the accumulation order per target is the same as in the shared-cursor walk
+// and in a sequential walk.  Entries are gathered per lane.  A wavefront owns
+// a chunk of 64 * K consecutive slots; lane l takes slots l, l + 64, ... of
+// the chunk one after the other, which evens out the lanes' work while the
+// wave's targets stay spatially close on the curve.
+
+template <bool PER, bool TPM, int OPEN, bool POT>
+__global__ __launch_bounds__(kBlock) void k_walk64i(const WalkArgs A, uint32_t K) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t nu = *A.nuniq;
+    const uint32_t base = wave * 64u * K;
+    if (base >= nu)
+        return;
+    const uint32_t chunk_end = min(nu, base + 64u * K);
+    const Rec64 *__restrict__ R = (const Rec64 *)A.rec;
+    uint32_t slot = base + lane;
+    bool live = slot < chunk_end;
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0, an = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0, pot = 0.0;
+    uint32_t self = 0, nint = 0, e = 0;
+    auto start = [&](uint32_t sl) {
+        const uint32_t s = A.act[sl];
+        x0 = A.ps[s];
+        x1 = A.ps[A.n + s];
+        x2 = A.ps[2 * (size_t)A.n + s];
+        self = A.pe[s];
+        if (OPEN == TPM_OPEN_REL)
+            an = A.anorm[A.perm[s]];
+        a0 = a1 = a2 = pot = 0.0;
+        nint = 0;
+        e = 0;
+    };
+    if (live)
+        start(slot);
+    while (__ballot(live)) {
+        if (live) {
+            const Rec64 r = R[e];
+            const double d0 = wrap64<PER>(r.com[0] - x0, A.box, A.half);
+            const double d1 = wrap64<PER>(r.com[1] - x1, A.box, A.half);
+            const double d2 = wrap64<PER>(r.com[2] - x2, A.box, A.half);
+            const double dd = fma(d0, d0, fma(d1, d1, d2 * d2));
+            bool inter, step_in;
+            if (r.meta & kParticleFlag) {
+                step_in = true;
+                inter = e != self && (!TPM || dd < A.rc2);
+            } else {
+                const double L = ldexp(A.L, -(int)(r.meta & 0xffu));
+                const double c0 = wrap64<PER>(r.cen[0] - x0, A.box, A.half);
+                const double c1 = wrap64<PER>(r.cen[1] - x1, A.box, A.half);
+                const double c2 = wrap64<PER>(r.cen[2] - x2, A.box, A.half);
+                bool discard = false;
+                if (TPM) {
+                    const double hl = 0.5 * L;
+                    double e0 = fabs(c0) - hl, e1 = fabs(c1) - hl, e2 = fabs(c2) - hl;
+                    e0 = e0 > 0.0 ? e0 : 0.0;
+                    e1 = e1 > 0.0 ? e1 : 0.0;
+                    e2 = e2 > 0.0 ? e2 : 0.0;
+                    discard = fma(e0, e0, fma(e1, e1, e2 * e2)) > A.rc2;
+                }
+                bool open = false;
+                if (!discard) {
+                    if (OPEN == TPM_OPEN_BH)
+                        open = (L * L) > A.theta2 * dd;
+                    else
+                        open = (A.G * r.mass) * (L * L) > (A.alpha * an) * (dd * dd);
+                    const double lim = 0.6 * L;
+                    if (fabs(c0) < lim && fabs(c1) < lim && fabs(c2) < lim)
+                        open = true;
+                }
+                step_in = open;
+                inter = !discard && !open;
+            }
+            if (inter) {
+                interact64<TPM, POT>(A, r.mass, d0, d1, d2, dd, a0, a1, a2, pot);
+                nint++;
+            }
+            e = step_in ? e + 1u : r.skip;
+            if (e >= A.E) {
+                double *res = (double *)A.res;
+                res[slot] = a0;
+                res[A.n + slot] = a1;
+                res[2 * (size_t)A.n + slot] = a2;
+                if (POT)
+                    ((double *)A.rpot)[slot] = pot;
+                A.rnint[slot] = nint;
+                slot += 64u;
+                live = slot < chunk_end;
+                if (live)
+                    start(slot);
+            }
+        }
+    }
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT>
+__global__ __launch_bounds__(kBlock) void k_walk32i(const WalkArgs A, uint32_t K) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t nu = *A.nuniq;
+    const uint32_t base = wave * 64u * K;
+    if (base >= nu)
+        return;
+    const uint32_t chunk_end = min(nu, base + 64u * K);
+    const Rec32 *__restrict__ R = (const Rec32 *)A.rec;
+    const double len21 = ldexp(A.L, -kMaxLevel);
+    uint32_t slot = base + lane;
+    bool live = slot < chunk_end;
+    int32_t G0 = 0, G1 = 0, G2 = 0;
+    float xr0 = 0.f, xr1 = 0.f, xr2 = 0.f, alpha_an = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f,
+          pot = 0.f;
+    uint32_t self = 0, nint = 0, e = 0;
+    auto start = [&](uint32_t sl) {
+        const uint32_t s = A.act[sl];
+        const uint64_t qq = A.qs[s];
+        const uint32_t q0 = (uint32_t)(qq >> 42) & 0x1fffffu,
+                       q1 = (uint32_t)(qq >> 21) & 0x1fffffu, q2 = (uint32_t)qq & 0x1fffffu;
+        G0 = (int32_t)(2u * q0 + 1u);
+        G1 = (int32_t)(2u * q1 + 1u);
+        G2 = (int32_t)(2u * q2 + 1u);
+        xr0 = (float)(A.ps[s] - (A.x0[0] + ((double)q0 + 0.5) * len21));
+        xr1 = (float)(A.ps[A.n + s] - (A.x0[1] + ((double)q1 + 0.5) * len21));
+        xr2 = (float)(A.ps[2 * (size_t)A.n + s] - (A.x0[2] + ((double)q2 + 0.5) * len21));
+        self = A.pe[s];
+        alpha_an = 0.f;
+        if (OPEN == TPM_OPEN_REL)
+            alpha_an = A.falpha * (float)A.anorm[A.perm[s]];
+        a0 = a1 = a2 = pot = 0.f;
+        nint = 0;
+        e = 0;
+    };
+    if (live)
+        start(slot);
+    while (__ballot(live)) {
+        if (live) {
+            const Rec32 r = R[e];
+            const int32_t cm = r.cx_meta;
+            const float c0 = fmaf((float)wrapi<PER>((cm & 0x3fffff) - G0), A.fu, -xr0);
+            const float c1 = fmaf((float)wrapi<PER>(r.cy - G1), A.fu, -xr1);
+            const float c2 = fmaf((float)wrapi<PER>(r.cz - G2), A.fu, -xr2);
+            const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
+            const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+            const bool part = (cm & (1 << 27)) != 0;
+            const float L = __builtin_amdgcn_ldexpf(A.fL, -((cm >> 22) & 31));
+            bool discard = false;
+            if (TPM) {
+                const float hl = 0.5f * L;
+                const float e0 = fmaxf(fabsf(c0) - hl, 0.0f);
+                const float e1 = fmaxf(fabsf(c1) - hl, 0.0f);
+                const float e2 = fmaxf(fabsf(c2) - hl, 0.0f);
+                discard = !part && fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) > A.frc2;
+            }
+            const float L2 = L * L;
+            bool crit;
+            if (OPEN == TPM_OPEN_BH)
+                crit = L2 > A.ftheta2 * dd;
+            else
+                crit = r.gm * L2 > alpha_an * (dd * dd);
+            const float lim = 0.6f * L;
+            const bool box = fabsf(c0) < lim && fabsf(c1) < lim && fabsf(c2) < lim;
+            const bool open = !part && !discard && (crit || box);
+            const bool inter = part ? (e != self && (!TPM || dd < A.frc2)) : (!discard && !open);
+            if (inter) {
+                interact32<TPM, POT>(A, r.gm, d0, d1, d2, dd, a0, a1, a2, pot);
+                nint++;
+            }
+            e = (part || open) ? e + 1u : r.skip;
+            if (e >= A.E) {
+                float *res = (float *)A.res;
+                res[slot] = a0;
+                res[A.n + slot] = a1;
+                res[2 * (size_t)A.n + slot] = a2;
+                if (POT)
+                    ((float *)A.rpot)[slot] = pot;
+                A.rnint[slot] = nint;
+                slot += 64u;
+                live = slot < chunk_end;
+                if (live)
+                    start(slot);
+            }
+        }
+    }
+}
+
 // ---- active set -> slots in curve order --------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_mark(const int32_t *__restrict__ idx, int64_t n_act,
@@ -442,27 +627,40 @@ __global__ __launch_bounds__(kBlock) void k_accel_norm(const int32_t *__restrict
     out[i] = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
 }
 
+struct Launch {
+    bool fp32;
+    bool lanes;       // lane-independent walk
+    uint32_t K;       // slots per lane (lane-independent walk)
+    unsigned blocks;
+};
+
 template <bool PER, bool TPM, int OPEN, bool POT>
-void launch_walk(const WalkArgs &A, bool fp32, unsigned blocks, hipStream_t st) {
-    if (fp32)
-        k_walk32<PER, TPM, OPEN, POT><<<blocks, kBlock, 0, st>>>(A);
-    else
-        k_walk64<PER, TPM, OPEN, POT><<<blocks, kBlock, 0, st>>>(A);
+void launch_walk(const WalkArgs &A, const Launch &L, hipStream_t st) {
+    if (L.lanes) {
+        if (L.fp32)
+            k_walk32i<PER, TPM, OPEN, POT><<<L.blocks, kBlock, 0, st>>>(A, L.K);
+        else
+            k_walk64i<PER, TPM, OPEN, POT><<<L.blocks, kBlock, 0, st>>>(A, L.K);
+    } else {
+        if (L.fp32)
+            k_walk32<PER, TPM, OPEN, POT><<<L.blocks, kBlock, 0, st>>>(A);
+        else
+            k_walk64<PER, TPM, OPEN, POT><<<L.blocks, kBlock, 0, st>>>(A);
+    }
 }
 
 template <bool PER, bool TPM>
-void dispatch_open_pot(const WalkArgs &A, bool fp32, int open, bool pot, unsigned blocks,
-                       hipStream_t st) {
+void dispatch_open_pot(const WalkArgs &A, const Launch &L, int open, bool pot, hipStream_t st) {
     if (open == TPM_OPEN_BH) {
         if (pot)
-            launch_walk<PER, TPM, TPM_OPEN_BH, true>(A, fp32, blocks, st);
+            launch_walk<PER, TPM, TPM_OPEN_BH, true>(A, L, st);
         else
-            launch_walk<PER, TPM, TPM_OPEN_BH, false>(A, fp32, blocks, st);
+            launch_walk<PER, TPM, TPM_OPEN_BH, false>(A, L, st);
     } else {
         if (pot)
-            launch_walk<PER, TPM, TPM_OPEN_REL, true>(A, fp32, blocks, st);
+            launch_walk<PER, TPM, TPM_OPEN_REL, true>(A, L, st);
         else
-            launch_walk<PER, TPM, TPM_OPEN_REL, false>(A, fp32, blocks, st);
+            launch_walk<PER, TPM, TPM_OPEN_REL, false>(A, L, st);
     }
 }
 
@@ -569,21 +767,34 @@ int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const
     A.rpot = c->rpot.p;
     A.rnint = (uint32_t *)c->rnint.p;
 
-    const int64_t waves = (std::min<int64_t>(n_act, n) + 63) / 64;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    const int64_t groups = (std::min<int64_t>(n_act, n) + 63) / 64;
+    Launch LA;
+    LA.fp32 = fp32;
+    // lane-independent walks pay off where the interaction is expensive and
+    // the wavefront's union of cutoff spheres is large: FP64 with TreePM
+    LA.lanes = c->walk_mode == 2 || (c->walk_mode == 0 && !fp32 && tpm_on);
+    LA.K = 1;
+    if (LA.lanes) {
+        // several slots per lane once there are enough wavefronts to fill the chip
+        const int64_t slots_per_chip = 256 * 4 * 8;
+        while (LA.K < 8 && groups / (2 * LA.K) >= 2 * slots_per_chip)
+            LA.K *= 2;
+    }
+    const int64_t waves = (groups + LA.K - 1) / LA.K;
+    LA.blocks = (unsigned)((waves + 3) / 4);
     const bool want_pot = pot != nullptr && P.want_potential;
     const int tkind = opening == TPM_OPEN_REL ? TPM_TIMER_WALK_REL : TPM_TIMER_WALK;
     TPM_TRY(timer_begin(c, tkind));
     if (P.periodic) {
         if (tpm_on)
-            dispatch_open_pot<true, true>(A, fp32, opening, want_pot, blocks, st);
+            dispatch_open_pot<true, true>(A, LA, opening, want_pot, st);
         else
-            dispatch_open_pot<true, false>(A, fp32, opening, want_pot, blocks, st);
+            dispatch_open_pot<true, false>(A, LA, opening, want_pot, st);
     } else {
         if (tpm_on)
-            dispatch_open_pot<false, true>(A, fp32, opening, want_pot, blocks, st);
+            dispatch_open_pot<false, true>(A, LA, opening, want_pot, st);
         else
-            dispatch_open_pot<false, false>(A, fp32, opening, want_pot, blocks, st);
+            dispatch_open_pot<false, false>(A, LA, opening, want_pot, st);
     }
     TPM_LAUNCHED(c, "k_walk");
     TPM_TRY(timer_end(c, tkind));
