@@ -182,6 +182,36 @@ int tpm_export_tree(tpm_ctx *ctx, int32_t *level, int64_t *first, int64_t *count
                     int64_t *skip, int64_t *pidx, double *mass, double *com, double *cen,
                     uint64_t *key, int64_t *perm);
 
+/* ---- Serving: continuous batching over many systems ---------------------
+ * A batch stages tree-force requests (one per context per batch) of many
+ * resident systems with uneven N and active fractions (the time-step bins of
+ * Sec. 7.2) and walks all of them in ONE persistent launch per precision:
+ * wavefronts pop work items (a group of 64 curve-adjacent targets of one
+ * request) from a device counter until the finite list is exhausted.  Every
+ * work item runs the same per-group walk as tpm_compute_forces, so each
+ * request's result is bit-identical alone and in any mix.
+ * All work is enqueued on the batch's stream; the caller orders each
+ * context's build (and PM solve) before the launch (same stream or an
+ * event).  Potentials are not produced by batches. */
+typedef struct tpm_batch tpm_batch;
+
+int tpm_batch_create(void *hip_stream, tpm_batch **out);
+int tpm_batch_destroy(tpm_batch *batch);
+const char *tpm_batch_last_error(const tpm_batch *batch);
+
+/* Stage one request: arguments as tpm_compute_forces (acc [3][n_act] of the
+ * context's dtype, n_interactions nullable).  TPM_EINVAL if the context is
+ * already staged in this batch; TPM_ESTATE if it has no tree. */
+int tpm_batch_add(tpm_batch *batch, tpm_ctx *ctx, int32_t opening, int64_t n_act,
+                  const int32_t *active_idx, const double *a_old_norm, void *acc,
+                  uint32_t *n_interactions);
+
+/* Enqueue the staged requests: active-set selection per request, one
+ * persistent walk per precision, outputs per request; then clear the
+ * stage.  Does not synchronise (except to reuse its pinned staging table
+ * after the previous launch). */
+int tpm_batch_launch(tpm_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

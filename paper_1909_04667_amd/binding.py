@@ -65,6 +65,12 @@ def lib():
         L.tpm_accel_norm.argtypes = [vp, i64, vp, vp, vp, vp]
         L.tpm_timing_enable.argtypes = [vp, C.c_int]
         L.tpm_timing_read.argtypes = [vp, C.c_int, P(d), P(i64)]
+        L.tpm_batch_create.argtypes = [vp, P(vp)]
+        L.tpm_batch_destroy.argtypes = [vp]
+        L.tpm_batch_last_error.argtypes = [vp]
+        L.tpm_batch_last_error.restype = C.c_char_p
+        L.tpm_batch_add.argtypes = [vp, vp, i32, i64, vp, vp, vp, vp]
+        L.tpm_batch_launch.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -230,3 +236,45 @@ class Context:
         out["cen"] = out["cen"].reshape(3, E)
         out["frame"] = np.array(fr)
         return out
+
+
+class Batch:
+    """Continuous batching of tree-force requests over many contexts."""
+
+    def __init__(self, stream=None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        rc = lib().tpm_batch_create(_stream_handle(self.stream), C.byref(h))
+        if rc != TPM_OK:
+            raise TreePMError(rc, "tpm_batch_create failed")
+        self.h = h
+        self._keep = []
+
+    def _rc(self, rc):
+        if rc != TPM_OK:
+            raise TreePMError(rc, lib().tpm_batch_last_error(self.h).decode())
+
+    def add(self, ctx: Context, active_idx, opening="bh", a_old_norm=None, acc=None,
+            n_interactions=None):
+        na = active_idx.numel()
+        if acc is None:
+            acc = torch.empty((3, na), dtype=ctx.dtype, device=active_idx.device)
+        self._rc(lib().tpm_batch_add(self.h, ctx.h, OPEN[opening], na, _ptr(active_idx),
+                                     _ptr(a_old_norm), _ptr(acc), _ptr(n_interactions)))
+        self._keep.append((active_idx, a_old_norm, acc, n_interactions))
+        return acc
+
+    def launch(self):
+        self._rc(lib().tpm_batch_launch(self.h))
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tpm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -14,6 +14,11 @@
 // last bits of erfc/exp.
 #include "tpm_internal.h"
 
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
 namespace tpm {
 namespace {
 
@@ -102,10 +107,10 @@ __device__ __forceinline__ double wrap64(double d, double box, double half) {
     return d;
 }
 
+// One wavefront walks group `wave` (slots 64 wave .. 64 wave + 63).
 template <bool PER, bool TPM, int OPEN, bool POT>
-__global__ __launch_bounds__(kBlock) void k_walk64(const WalkArgs A) {
+__device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
     const int lane = threadIdx.x & 63;
-    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint32_t nu = *A.nuniq;
     if (wave * 64u >= nu)
         return;  // whole wavefront
@@ -256,9 +261,8 @@ __device__ __forceinline__ int32_t wrapi(int32_t d) {
 }
 
 template <bool PER, bool TPM, int OPEN, bool POT>
-__global__ __launch_bounds__(kBlock) void k_walk32(const WalkArgs A) {
+__device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     const int lane = threadIdx.x & 63;
-    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint32_t nu = *A.nuniq;
     if (wave * 64u >= nu)
         return;
@@ -349,6 +353,16 @@ __global__ __launch_bounds__(kBlock) void k_walk32(const WalkArgs A) {
             ((float *)A.rpot)[slot] = pot;
         A.rnint[slot] = nint;
     }
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT>
+__global__ __launch_bounds__(kBlock) void k_walk64(const WalkArgs A) {
+    walk_group64<PER, TPM, OPEN, POT>(A, (blockIdx.x * kBlock + threadIdx.x) >> 6);
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT>
+__global__ __launch_bounds__(kBlock) void k_walk32(const WalkArgs A) {
+    walk_group32<PER, TPM, OPEN, POT>(A, (blockIdx.x * kBlock + threadIdx.x) >> 6);
 }
 
 // ---- lane-independent walks ------------------------------------------------
@@ -712,22 +726,10 @@ int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
     return TPM_OK;
 }
 
-int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const double *anorm,
-           void *acc, void *pot, uint32_t *nint) {
+static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
     const tpm_params &P = c->P;
     const int64_t n = c->n;
-    hipStream_t st = c->stream;
     const bool fp32 = P.precision == TPM_FP32;
-    const size_t esz = fp32 ? 4 : 8;
-    TPM_TRY(ensure(c, c->res, (size_t)3 * n * esz));
-    TPM_TRY(ensure(c, c->rpot, (size_t)n * esz));
-    TPM_TRY(ensure(c, c->rnint, (size_t)n * 4));
-    TPM_TRY(ensure(c, c->err_flag, 16));
-    if (n_act == 0)
-        return TPM_OK;
-    TPM_TRY(select_active(c, n_act, idx));
-
-    WalkArgs A{};
     A.rec = fp32 ? c->rec32.p : c->rec64.p;
     A.E = (uint32_t)c->E;
     A.n = (uint32_t)n;
@@ -767,6 +769,26 @@ int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const
     A.rpot = c->rpot.p;
     A.rnint = (uint32_t *)c->rnint.p;
 
+}
+
+int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const double *anorm,
+           void *acc, void *pot, uint32_t *nint) {
+    const tpm_params &P = c->P;
+    const int64_t n = c->n;
+    hipStream_t st = c->stream;
+    const bool fp32 = P.precision == TPM_FP32;
+    const size_t esz = fp32 ? 4 : 8;
+    TPM_TRY(ensure(c, c->res, (size_t)3 * n * esz));
+    TPM_TRY(ensure(c, c->rpot, (size_t)n * esz));
+    TPM_TRY(ensure(c, c->rnint, (size_t)n * 4));
+    TPM_TRY(ensure(c, c->err_flag, 16));
+    if (n_act == 0)
+        return TPM_OK;
+    TPM_TRY(select_active(c, n_act, idx));
+
+    WalkArgs A{};
+    fill_args(c, anorm, A);
+    const bool tpm_on = P.pm_grid > 0;
     const int64_t groups = (std::min<int64_t>(n_act, n) + 63) / 64;
     Launch LA;
     LA.fp32 = fp32;
@@ -814,3 +836,262 @@ int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const
 }
 
 }  // namespace tpm
+
+// ---- batched walks over many systems (continuous batching) -------------------
+//
+// One persistent launch per precision walks the groups of every request staged
+// in a batch: wavefronts pop work items (one group of one request) from a
+// device counter until the finite item list is exhausted.  A work item runs
+// the same per-group code as a single-system launch, so each result is the
+// same whether its request runs alone or in a mix.
+
+namespace tpm {
+namespace {
+
+struct BatchReq {
+    WalkArgs A;
+    uint32_t variant;  // bit 0: relative criterion, bit 1: periodic TreePM
+    uint32_t first;    // first work item of the request
+};
+
+template <bool FP32, bool PER, bool TPM, int OPEN>
+__device__ __forceinline__ void batch_group(const WalkArgs &A, uint32_t g) {
+    if (FP32)
+        walk_group32<PER, TPM, OPEN, false>(A, g);
+    else
+        walk_group64<PER, TPM, OPEN, false>(A, g);
+}
+
+template <bool FP32>
+__global__ __launch_bounds__(kBlock) void k_walk_batch(const BatchReq *__restrict__ reqs,
+                                                       uint32_t nreq, uint32_t nitems,
+                                                       uint32_t *__restrict__ counter) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0)
+            item = atomicAdd(counter, 1u);
+        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
+        if (item >= nitems)
+            break;  // every wavefront reaches this once the items are exhausted
+        uint32_t lo = 0, hi = nreq;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (reqs[mid].first <= item)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const BatchReq &R = reqs[lo];
+        const uint32_t g = item - R.first;
+        switch (R.variant) {
+        case 0: batch_group<FP32, false, false, TPM_OPEN_BH>(R.A, g); break;
+        case 1: batch_group<FP32, false, false, TPM_OPEN_REL>(R.A, g); break;
+        case 2: batch_group<FP32, true, true, TPM_OPEN_BH>(R.A, g); break;
+        default: batch_group<FP32, true, true, TPM_OPEN_REL>(R.A, g); break;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace tpm
+
+struct tpm_batch {
+    hipStream_t stream = nullptr;
+    std::string err;
+    struct Pending {
+        tpm_ctx *c;
+        int32_t opening;
+        int64_t n_act;
+        const int32_t *idx;
+        const double *anorm;
+        void *acc;
+        uint32_t *nint;
+    };
+    std::vector<Pending> pend;
+    tpm::BatchReq *host = nullptr;  // pinned staging of the request table
+    size_t host_cap = 0;
+    void *dev = nullptr;            // device request table
+    size_t dev_cap = 0;
+    uint32_t *counter = nullptr;    // two work counters
+    hipEvent_t done = nullptr;      // last launch finished: staging reusable
+    bool launched = false;
+};
+
+using namespace tpm;
+
+static int bfail(tpm_batch *b, int code, const std::string &m) {
+    b->err = m;
+    return code;
+}
+
+#define BHIP(b, expr)                                                        \
+    do {                                                                     \
+        hipError_t _e = (expr);                                              \
+        if (_e != hipSuccess)                                                \
+            return bfail((b), _e == hipErrorOutOfMemory ? TPM_ENOMEM : TPM_EDEVICE, \
+                         std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+extern "C" {
+
+int tpm_batch_create(void *hip_stream, tpm_batch **out) {
+    if (!out)
+        return TPM_EINVAL;
+    *out = nullptr;
+    tpm_batch *b = new (std::nothrow) tpm_batch();
+    if (!b)
+        return TPM_ENOMEM;
+    b->stream = (hipStream_t)hip_stream;
+    if (hipMalloc((void **)&b->counter, 16) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        if (b->counter)
+            (void)hipFree(b->counter);
+        delete b;
+        return TPM_ENOMEM;
+    }
+    *out = b;
+    return TPM_OK;
+}
+
+int tpm_batch_destroy(tpm_batch *b) {
+    if (!b)
+        return TPM_EINVAL;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->host)
+        (void)hipHostFree(b->host);
+    if (b->dev)
+        (void)hipFree(b->dev);
+    if (b->counter)
+        (void)hipFree(b->counter);
+    if (b->done)
+        (void)hipEventDestroy(b->done);
+    delete b;
+    return TPM_OK;
+}
+
+const char *tpm_batch_last_error(const tpm_batch *b) { return b ? b->err.c_str() : "NULL batch"; }
+
+int tpm_batch_add(tpm_batch *b, tpm_ctx *c, int32_t opening, int64_t n_act,
+                  const int32_t *idx, const double *anorm, void *acc, uint32_t *nint) {
+    if (!b)
+        return TPM_EINVAL;
+    if (!c || !c->built)
+        return bfail(b, TPM_ESTATE, "context missing or not built");
+    if (opening != TPM_OPEN_BH && opening != TPM_OPEN_REL)
+        return bfail(b, TPM_EINVAL, "opening must be TPM_OPEN_BH or TPM_OPEN_REL");
+    if (n_act < 0 || n_act > (int64_t(1) << 31) - 1)
+        return bfail(b, TPM_EINVAL, "n_act out of range");
+    if (n_act > 0 && (!idx || !acc))
+        return bfail(b, TPM_EINVAL, "active_idx and acc must not be NULL");
+    if (opening == TPM_OPEN_REL && n_act > 0 && !anorm)
+        return bfail(b, TPM_EINVAL, "the relative criterion needs a_old_norm");
+    for (const auto &p : b->pend)
+        if (p.c == c)
+            return bfail(b, TPM_EINVAL, "a context may appear once per batch");
+    b->pend.push_back({c, opening, n_act, idx, anorm, acc, nint});
+    return TPM_OK;
+}
+
+int tpm_batch_launch(tpm_batch *b) {
+    if (!b)
+        return TPM_EINVAL;
+    if (b->pend.empty())
+        return TPM_OK;
+    if (b->launched)
+        BHIP(b, hipEventSynchronize(b->done));  // the staging table is free again
+    const size_t np = b->pend.size();
+    if (b->host_cap < np) {
+        if (b->host)
+            BHIP(b, hipHostFree(b->host));
+        b->host = nullptr;
+        BHIP(b, hipHostMalloc((void **)&b->host, 2 * np * sizeof(BatchReq), hipHostMallocDefault));
+        b->host_cap = 2 * np;
+    }
+    if (b->dev_cap < np * sizeof(BatchReq)) {
+        if (b->dev)
+            BHIP(b, hipFree(b->dev));
+        b->dev = nullptr;
+        BHIP(b, hipMalloc(&b->dev, 2 * np * sizeof(BatchReq)));
+        b->dev_cap = 2 * np * sizeof(BatchReq);
+    }
+    // stage: active sets of every request on the batch stream, FP32 first
+    uint32_t items[2] = {0, 0}, nreq[2] = {0, 0};
+    std::vector<size_t> order;
+    for (int pass = 0; pass < 2; pass++)
+        for (size_t k = 0; k < np; k++)
+            if ((b->pend[k].c->P.precision == TPM_FP32) == (pass == 0))
+                order.push_back(k);
+    for (size_t o = 0; o < np; o++) {
+        const auto &p = b->pend[order[o]];
+        tpm_ctx *c = p.c;
+        const int which = c->P.precision == TPM_FP32 ? 0 : 1;
+        hipStream_t saved = c->stream;
+        c->stream = b->stream;
+        const size_t esz = which == 0 ? 4 : 8;
+        int rc = ensure(c, c->res, (size_t)3 * c->n * esz);
+        if (rc == TPM_OK)
+            rc = ensure(c, c->rpot, (size_t)c->n * esz);
+        if (rc == TPM_OK)
+            rc = ensure(c, c->rnint, (size_t)c->n * 4);
+        if (rc == TPM_OK && p.n_act > 0)
+            rc = select_active(c, p.n_act, p.idx);
+        c->stream = saved;
+        if (rc != TPM_OK)
+            return bfail(b, rc, c->err);
+        BatchReq &R = b->host[o];
+        R = BatchReq{};
+        fill_args(c, p.anorm, R.A);
+        R.variant = (p.opening == TPM_OPEN_REL ? 1u : 0u) | (c->P.pm_grid > 0 ? 2u : 0u);
+        R.first = items[which];
+        const int64_t groups = p.n_act > 0 ? (std::min<int64_t>(p.n_act, c->n) + 63) / 64 : 0;
+        items[which] += (uint32_t)groups;
+        nreq[which]++;
+    }
+    BHIP(b, hipMemcpyAsync(b->dev, b->host, np * sizeof(BatchReq), hipMemcpyHostToDevice,
+                           b->stream));
+    {
+        tpm_ctx tmp;  // fill kernels only need a stream
+        tmp.stream = b->stream;
+        if (fill_u32(&tmp, b->counter, 0u, 2) != TPM_OK)
+            return bfail(b, TPM_EDEVICE, tmp.err);
+    }
+    const BatchReq *dreq = (const BatchReq *)b->dev;
+    const uint32_t max_blocks = 2048;
+    if (items[0]) {
+        const uint32_t blocks = std::min<uint32_t>(max_blocks, (items[0] + 3) / 4);
+        k_walk_batch<true><<<blocks, kBlock, 0, b->stream>>>(dreq, nreq[0], items[0], b->counter);
+        BHIP(b, hipGetLastError());
+    }
+    if (items[1]) {
+        const uint32_t blocks = std::min<uint32_t>(max_blocks, (items[1] + 3) / 4);
+        k_walk_batch<false><<<blocks, kBlock, 0, b->stream>>>(dreq + nreq[0], nreq[1], items[1],
+                                                              b->counter + 1);
+        BHIP(b, hipGetLastError());
+    }
+    // outputs in each request's caller order
+    for (const auto &p : b->pend) {
+        if (p.n_act == 0)
+            continue;
+        tpm_ctx *c = p.c;
+        const unsigned ob = grid_for(p.n_act, kBlock);
+        if (c->P.precision == TPM_FP32)
+            k_output<float><<<ob, kBlock, 0, b->stream>>>(
+                p.idx, p.n_act, c->n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
+                (const float *)c->res.p, (const float *)c->rpot.p, (const uint32_t *)c->rnint.p,
+                (float *)p.acc, nullptr, p.nint, (uint32_t *)c->err_flag.p);
+        else
+            k_output<double><<<ob, kBlock, 0, b->stream>>>(
+                p.idx, p.n_act, c->n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
+                (const double *)c->res.p, (const double *)c->rpot.p,
+                (const uint32_t *)c->rnint.p, (double *)p.acc, nullptr, p.nint,
+                (uint32_t *)c->err_flag.p);
+        BHIP(b, hipGetLastError());
+    }
+    BHIP(b, hipEventRecord(b->done, b->stream));
+    b->launched = true;
+    b->pend.clear();
+    return TPM_OK;
+}
+
+}  // extern "C"

@@ -270,39 +270,63 @@ def make_config(cfg: int, scale: int = 1) -> Particles:
 # --------------------------------------------------------------------------
 
 @dataclass
-class Request:
-    rid: int
-    t_arrival: float
-    kind: str
+class SystemSpec:
+    sid: int
+    kind: str          # plummer | hernquist | periodic
     n: int
-    f_active: float
-    precision: str
     seed: int
 
 
-def request_stream(n_requests: int, rate: float, seed: int = 5,
-                   log2n=(10, 21), log10f=(-3.0, 0.0)):
-    """Poisson arrivals; each request names a system and an active fraction.
+@dataclass
+class Request:
+    rid: int
+    t_arrival: float   # seconds after the start of the stream
+    sid: int           # index into the system pool
+    f_active: float
+    precision: str     # fp32 | fp64
+    seed: int          # draws the active subset
 
-    kind uniform over {plummer, hernquist, periodic}; N = 2^U(log2n) rounded;
-    f_active = 10^U(log10f); precision uniform over {fp32, fp64}.
-    """
+
+def system_pool(n_systems: int, seed: int = 5, log2n=(10, 21)):
+    """Systems of uneven size: kind uniform over {plummer, hernquist,
+    periodic}, N = 2^U(log2n) rounded (periodic: the nearest cube)."""
     rng = _rng(seed)
-    t = np.cumsum(rng.exponential(1.0 / rate, n_requests))
-    kinds = rng.choice(["plummer", "hernquist", "periodic"], n_requests)
-    ns = np.rint(2.0 ** rng.uniform(*log2n, n_requests)).astype(np.int64)
+    kinds = rng.choice(["plummer", "hernquist", "periodic"], n_systems)
+    ns = np.rint(2.0 ** rng.uniform(*log2n, n_systems)).astype(np.int64)
+    seeds = rng.integers(0, 2 ** 31, n_systems)
+    out = []
+    for i in range(n_systems):
+        n = int(ns[i])
+        if kinds[i] == "periodic":
+            n = max(8, int(round(n ** (1.0 / 3.0)))) ** 3
+        out.append(SystemSpec(i, str(kinds[i]), n, int(seeds[i])))
+    return out
+
+
+def request_stream(n_requests: int, rate: float, n_systems: int, seed: int = 5,
+                   log10f=(-3.0, 0.0)):
+    """Poisson arrivals at ``rate`` per second over a pool of systems; each
+    request picks a system, an active fraction 10^U(log10f) (the share of
+    particles in the time-step bins due at that moment) and a precision."""
+    rng = _rng(seed + 1)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_requests)) if rate > 0 else np.zeros(n_requests)
+    sids = rng.integers(0, n_systems, n_requests)
     fs = 10.0 ** rng.uniform(*log10f, n_requests)
     prec = rng.choice(["fp32", "fp64"], n_requests)
     seeds = rng.integers(0, 2 ** 31, n_requests)
-    return [Request(i, float(t[i]), str(kinds[i]), int(ns[i]), float(fs[i]),
-                    str(prec[i]), int(seeds[i])) for i in range(n_requests)]
+    return [Request(i, float(t[i]), int(sids[i]), float(fs[i]), str(prec[i]), int(seeds[i]))
+            for i in range(n_requests)]
 
 
-def system_for_request(req: Request) -> Particles:
-    if req.kind == "plummer":
-        return plummer(req.n, req.seed)
-    if req.kind == "hernquist":
-        return hernquist(req.n, req.seed)
-    ng = max(8, int(round(req.n ** (1.0 / 3.0))))
-    p = zeldovich_box(ng, 100.0, req.seed)
-    return p
+def system_particles(spec: SystemSpec) -> Particles:
+    if spec.kind == "plummer":
+        return plummer(spec.n, spec.seed)
+    if spec.kind == "hernquist":
+        return hernquist(spec.n, spec.seed)
+    ng = int(round(spec.n ** (1.0 / 3.0)))
+    return zeldovich_box(ng, 100.0, spec.seed)
+
+
+def request_active(req: Request, n: int) -> np.ndarray:
+    """The request's active set: a seeded random subset of size f_active N."""
+    return random_active(n, req.f_active, req.seed)
