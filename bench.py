@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--precision", default="both", choices=["both", "fp32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the local-timestep and serving legs")
     return ap.parse_args()
 
 
@@ -123,6 +125,100 @@ def run_gpu(p, kw, prec, steps, warmup):
                acc=total.double().cpu(), entries=ctx.tree_info()[1])
     ctx.close()
     return out
+
+
+def run_local_timestep(steps, prec="fp32"):
+    """Clustered 256^3 box: one build (+ PM solve) reused by every active set;
+    per set the PM interpolation and the relative-criterion walk with |a| of
+    a full geometric pass (the previous step's accelerations)."""
+    import numpy as np
+    import torch
+    from paper_1909_04667_amd import binding as B
+    from paper_1909_04667_amd import workloads as W
+    c, p, kw = workload(4)
+    sets, bins = W.time_bin_active_sets(p.meta["rho"])
+    dev = torch.device("cuda:0")
+    t = lambda a, dt=torch.float64: torch.as_tensor(a, dtype=dt, device=dev).contiguous()
+    x, y, z = t(p.x), t(p.y), t(p.z)
+    ctx = B.Context(precision=prec, **kw)
+    ctx.timing(True)
+    ctx.build_tree(x, y, z)
+    all_idx = torch.arange(p.n, dtype=torch.int32, device=dev)
+    apm, _ = ctx.pm_long_range(all_idx)
+    a0, _ = ctx.compute_forces(all_idx, "bh")
+    anorm = ctx.accel_norm(all_idx, a0, apm)
+    torch.cuda.synchronize()
+    for k in ctx.TIMERS:
+        ctx.timing_read(k)
+    # rebuild timing (the tree is rebuilt per step in the paper's scheme)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        ctx.build_tree(x, y, z)
+        ctx.pm_long_range(all_idx[:0])
+    ev[1].record()
+    torch.cuda.synchronize()
+    build_ms = ctx.timing_read("build")[0] / steps
+    solve_ms = ctx.timing_read("pm_solve")[0] / steps
+    out = {"workload": c["name"], "n_particles": p.n, "build_ms": build_ms,
+           "pm_solve_ms": solve_ms, "tree_entries": ctx.tree_info()[1], "sets": {}}
+    for f, ids in sets.items():
+        idx = t(ids, torch.int32)
+        acc = torch.empty((3, idx.numel()), dtype=ctx.dtype, device=dev)
+        accl = torch.empty_like(acc)
+        for _ in range(2):
+            ctx.pm_long_range(idx, acc=accl)
+            ctx.compute_forces(idx, "rel", a_old_norm=anorm, acc=acc)
+        for k in ctx.TIMERS:
+            ctx.timing_read(k)  # drop the warm-up records
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(steps):
+            ctx.pm_long_range(idx, acc=accl)
+            ctx.compute_forces(idx, "rel", a_old_norm=anorm, acc=acc)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / steps
+        walk_ms = ctx.timing_read("walk_rel")[0] / steps
+        interp_ms = ctx.timing_read("pm_interp")[0] / steps
+        out["sets"][str(f)] = {"n_active": int(idx.numel()), "forces_ms": ms, "walk_ms": walk_ms,
+                               "pm_interp_ms": interp_ms,
+                               "force_evals_per_s": idx.numel() / (ms * 1e-3),
+                               "with_rebuild_evals_per_s":
+                                   idx.numel() / ((ms + build_ms + solve_ms) * 1e-3)}
+    ctx.check()
+    ctx.close()
+    return out
+
+
+def run_serving(n_requests=300, n_systems=16, seed=5):
+    """Continuous batching over a pool of resident systems: capacity from a
+    run where every request is present at t = 0, then Poisson arrivals at
+    0.7 of that capacity; p50/p99 latency from GPU events."""
+    from paper_1909_04667_amd import serve as S
+    from paper_1909_04667_amd import workloads as W
+    pool = W.system_pool(n_systems, seed=seed)
+    burst = W.request_stream(n_requests, rate=0.0, n_systems=n_systems, seed=seed)
+    srv = S.Server(pool, budget_bytes=64 << 30)
+    srv.run(burst[:n_systems * 2])  # warm-up: builds every resident system
+    st, _ = srv.run(burst)
+    cap = st.summary()
+    req_rate = cap["requests"] / (st.span_ms * 1e-3)
+    stream = W.request_stream(n_requests, rate=0.7 * req_rate, n_systems=n_systems,
+                              seed=seed + 100)
+    st2, _ = srv.run(stream)
+    srv.close()
+    s2 = st2.summary()
+    return {"systems": n_systems, "n_range": [min(s.n for s in pool), max(s.n for s in pool)],
+            "requests": n_requests, "precisions": "fp32+fp64 mix",
+            "capacity": {"force_evals_per_s": cap["throughput_evals_per_s"],
+                         "requests_per_s": req_rate, "p50_ms": cap["p50_ms"],
+                         "p99_ms": cap["p99_ms"]},
+            "poisson_0.7": {"force_evals_per_s": s2["throughput_evals_per_s"],
+                            "p50_ms": s2["p50_ms"], "p99_ms": s2["p99_ms"],
+                            "max_ms": s2["max_ms"], "batches": s2["batches"],
+                            "mean_stages_per_batch": s2["mean_stages_per_batch"],
+                            "rejected": s2["rejected"]}}
 
 
 def pct(v, q):
@@ -254,6 +350,11 @@ def main():
                                     "p99": float(np.percentile(e, 99)),
                                     "max": float(e.max())}
         line["fp32_speedup_vs_fp64"] = out_prec["fp64"]["ms_per_step"] / h["ms_per_step"]
+    if not args.no_extra:
+        log("local time-stepping workload (256^3 clustered box)")
+        line["local_timestep"] = run_local_timestep(max(3, args.steps // 2))
+        log("serving stream")
+        line["serving"] = run_serving()
     if not args.no_cpu:
         log("timing the CPU oracle on a sample")
         cb = cpu_baseline(p, kw, args.cpu_sample, args.config)

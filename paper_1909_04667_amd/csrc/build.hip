@@ -214,15 +214,15 @@ __device__ __forceinline__ int common_levels(uint64_t a, uint64_t b) {
 }
 
 // Per particle: depth shared with the right neighbour, entries it starts
-// (nodes at levels (dL, dR] plus itself) and a per-level node histogram.
+// (nodes at levels (dL, dR] plus itself), and per block and level the number
+// of nodes its particles start: hist[level * nb + block] (a counting sort by
+// level, so node lists come out in particle order without global atomics).
 __global__ __launch_bounds__(kBlock) void k_count(const uint64_t *__restrict__ key, int64_t n,
                                                   int8_t *__restrict__ dR,
                                                   uint32_t *__restrict__ cnt,
-                                                  uint32_t *__restrict__ lvl_count) {
-    __shared__ uint32_t h[kLevels];
-    if (threadIdx.x < kLevels)
-        h[threadIdx.x] = 0;
-    __syncthreads();
+                                                  uint32_t *__restrict__ hist, uint32_t nb) {
+    __shared__ uint32_t h[kLevels][kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int r = -1, l = -1;
     if (s < n) {
@@ -233,60 +233,75 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint64_t *__restrict__ k
         const int nn = r > l ? r - l : 0;
         cnt[s] = (uint32_t)nn + 1u;
     }
-    // one LDS add per wavefront and level
-    const int lane = threadIdx.x & 63;
     for (int lev = 0; lev < kLevels; lev++) {
         const uint64_t m = __ballot(lev > l && lev <= r);
-        if (m && lane == __ffsll((long long)m) - 1)
-            atomicAdd(&h[lev], (uint32_t)__popcll(m));
+        if (lane == 0)
+            h[lev][w] = (uint32_t)__popcll(m);
     }
     __syncthreads();
-    if (threadIdx.x < kLevels && h[threadIdx.x])
-        atomicAdd(&lvl_count[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < kLevels) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int q = 0; q < kBlock / 64; q++)
+            t += h[threadIdx.x][q];
+        hist[(size_t)threadIdx.x * nb + blockIdx.x] = t;
+    }
+}
+
+// Start offset of every level's node list (the scanned histogram's first
+// block) into out[0..21].
+__global__ void k_level_starts(const uint32_t *__restrict__ off, uint32_t nb,
+                               uint32_t *__restrict__ out) {
+    if (threadIdx.x < kLevels)
+        out[threadIdx.x] = off[(size_t)threadIdx.x * nb];
 }
 
 __device__ __forceinline__ uint64_t prefix_at(uint64_t k, int lev) {
     return k >> (3 * (kMaxLevel - lev));
 }
 
-// Emit the particle entry and the node entries a particle starts, deepest
-// first so that each run end is searched from the previous one.
+// Emit the particle entry and the node entries a particle starts.  Skip
+// pointers and counts of nodes are filled bottom-up by k_moments: every
+// entry carries a depth (nodes: their level; a particle: the level of the
+// cell it occupies alone, one below its deepest shared prefix), and the
+// subtree of a node of level l ends at the first later entry of depth <= l.
 __global__ __launch_bounds__(kBlock) void k_emit(
     const uint64_t *__restrict__ key, int64_t n, const int8_t *__restrict__ dR,
-    const uint32_t *__restrict__ base, uint32_t E, const Frame *__restrict__ Fp,
+    const uint32_t *__restrict__ base, const Frame *__restrict__ Fp,
     const double *__restrict__ ps, const double *__restrict__ ms,
     const uint64_t *__restrict__ qs, Rec64 *__restrict__ rec, uint32_t *__restrict__ efirst,
-    uint32_t *__restrict__ ecount, uint32_t *__restrict__ pe, uint32_t *__restrict__ cursor,
-    uint32_t *__restrict__ lvl_list) {
-    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    uint32_t *__restrict__ ecount, uint32_t *__restrict__ pe,
+    const uint32_t *__restrict__ loff, uint32_t nb, uint32_t *__restrict__ lvl_list) {
+    __shared__ uint32_t h[kLevels][kBlock / 64];
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool live = s < n;
     const int r = live ? (int)dR[s] : -1;
     const int l = (live && s > 0) ? (int)dR[s - 1] : -1;
     const uint32_t b = live ? base[s] : 0u;
     const int nn = r > l ? r - l : 0;
-    // level lists: one cursor atomic per wavefront and level (nodes of level
-    // lev started by this particle sit at entry b + lev - l - 1)
-    {
-        const int lane = threadIdx.x & 63;
-        const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-        for (int lev = 0; lev < kLevels; lev++) {
-            const bool has = lev > l && lev <= r;
-            const uint64_t m = __ballot(has);
-            if (!m)
-                continue;
-            const int leader = __ffsll((long long)m) - 1;
-            uint32_t at = 0;
-            if (lane == leader)
-                at = atomicAdd(&cursor[lev], (uint32_t)__popcll(m));
-            at = __shfl(at, leader, 64);
-            if (has)
-                lvl_list[at + (uint32_t)__popcll(m & lt)] = b + (uint32_t)(lev - l - 1);
+    // level lists in particle order: block offset (scanned histogram) +
+    // preceding wavefronts of the block + preceding lanes of the wavefront
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int lev = 0; lev < kLevels; lev++) {
+        const uint64_t m = __ballot(lev > l && lev <= r);
+        if (lane == 0)
+            h[lev][w] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    for (int lev = 0; lev < kLevels; lev++) {
+        const bool has = lev > l && lev <= r;
+        const uint64_t m = __ballot(has);
+        if (has) {
+            uint32_t at = loff[(size_t)lev * nb + blockIdx.x];
+            for (int q = 0; q < w; q++)
+                at += h[lev][q];
+            lvl_list[at + (uint32_t)__popcll(m & lt)] = b + (uint32_t)(lev - l - 1);
         }
     }
     if (!live)
         return;
     const Frame F = *Fp;
-    // particle entry
     const uint32_t ep = b + (uint32_t)nn;
     {
         Rec64 R;
@@ -298,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(
         R.cen[1] = R.com[1];
         R.cen[2] = R.com[2];
         R.skip = ep + 1u;
-        R.meta = kParticleFlag | (uint32_t)kMaxLevel;
+        R.meta = kParticleFlag | (uint32_t)((r > l ? r : l) + 1);
         rec[ep] = R;
         efirst[ep] = (uint32_t)s;
         ecount[ep] = 1u;
@@ -306,30 +321,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     }
     if (nn == 0)
         return;
-    const uint64_t k = key[s];
     const uint64_t qq = qs[s];
     const uint32_t q[3] = {(uint32_t)(qq >> 42) & 0x1fffffu, (uint32_t)(qq >> 21) & 0x1fffffu,
                            (uint32_t)qq & 0x1fffffu};
-    int64_t end = s;
-    for (int lev = r; lev > l; --lev) {
-        const uint64_t P = prefix_at(k, lev);
-        // gallop: key[end] carries prefix P; find the last index that does
-        int64_t lo = end, hi = end + 1, step = 1;
-        while (hi < n && prefix_at(key[hi], lev) == P) {
-            lo = hi;
-            step <<= 1;
-            hi = lo + step;
-        }
-        if (hi > n)
-            hi = n;
-        while (hi - lo > 1) {
-            int64_t mid = lo + ((hi - lo) >> 1);
-            if (prefix_at(key[mid], lev) == P)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        end = lo;
+    for (int lev = l + 1; lev <= r; ++lev) {
         const uint32_t e = b + (uint32_t)(lev - l - 1);
         Rec64 R;
         const double len = ldexp(F.L, -lev);
@@ -340,36 +335,42 @@ __global__ __launch_bounds__(kBlock) void k_emit(
             R.com[a] = 0.0;
         }
         R.mass = 0.0;
-        R.skip = (end + 1 < n) ? base[end + 1] : E;
+        R.skip = 0u;  // set by k_moments
         R.meta = (uint32_t)lev;
         rec[e] = R;
         efirst[e] = (uint32_t)s;
-        ecount[e] = (uint32_t)(end - s + 1);
     }
 }
 
-// Monopole moments of the nodes of one level, children in curve order:
-// M = (M1 + M2) + ..., X = fma(M_k, s_k, X), s = X / M.
-__global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec,
+// Nodes of one level (deepest level first): walk the children through their
+// skip pointers (all deeper, so already final), sum the monopole moments in
+// curve order -- M = (M1 + M2) + ..., X = fma(M_k, s_k, X), s = X / M -- and
+// set the node's particle count and skip pointer.
+__global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uint32_t E,
+                                                    uint32_t *__restrict__ ecount,
                                                     const uint32_t *__restrict__ list,
-                                                    uint32_t count) {
+                                                    uint32_t count, uint32_t lev) {
     uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= count)
         return;
     const uint32_t e = list[i];
-    const uint32_t end = rec[e].skip;
     double M = 0.0, X0 = 0.0, X1 = 0.0, X2 = 0.0;
-    for (uint32_t k = e + 1; k < end; k = rec[k].skip) {
+    uint32_t cnt = 0, k = e + 1;
+    while (k < E && (rec[k].meta & 0xffu) > lev) {
         const double mk = rec[k].mass;
         M = M + mk;
         X0 = fma(mk, rec[k].com[0], X0);
         X1 = fma(mk, rec[k].com[1], X1);
         X2 = fma(mk, rec[k].com[2], X2);
+        cnt += ecount[k];
+        k = rec[k].skip;
     }
     rec[e].mass = M;
     rec[e].com[0] = X0 / M;
     rec[e].com[1] = X1 / M;
     rec[e].com[2] = X2 / M;
+    rec[e].skip = k;
+    ecount[e] = cnt;
 }
 
 // FP32 records: exact integer centres, float offsets of the centre of mass.
@@ -384,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_pack32(const Rec64 *__restrict__ rec
     const Frame F = *Fp;
     const Rec64 R = rec[e];
     const bool part = (R.meta & kParticleFlag) != 0;
-    const int lev = (int)(R.meta & 0xffu);
+    const int lev = part ? kMaxLevel : (int)(R.meta & 0xffu);
     const uint64_t qq = qs[efirst[e]];
     const uint32_t q[3] = {(uint32_t)(qq >> 42) & 0x1fffffu, (uint32_t)(qq >> 21) & 0x1fffffu,
                            (uint32_t)qq & 0x1fffffu};
@@ -466,48 +467,42 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
     TPM_LAUNCHED(c, "k_gather");
     // 4. topology: counts, scan, one readback of the sizes
     const uint64_t *key = (const uint64_t *)c->key[0].p;
-    uint32_t *lvl_count = (uint32_t *)c->counters.p;  // [0..21] level counts, [32] total
-    TPM_TRY(fill_u32(c, lvl_count, 0u, 64));
-    k_count<<<grid_for(n, kBlock), kBlock, 0, st>>>(key, n, (int8_t *)c->dR.p,
-                                                    (uint32_t *)c->cnt.p, lvl_count);
+    uint32_t *lvl_count = (uint32_t *)c->counters.p;  // [0..21] level starts, [32] E, [33] nodes
+    const uint32_t nb = grid_for(n, kBlock);
+    TPM_TRY(ensure(c, c->hist, (size_t)2 * kLevels * nb * sizeof(uint32_t)));
+    uint32_t *lhist = (uint32_t *)c->hist.p;
+    uint32_t *loff = lhist + (size_t)kLevels * nb;
+    k_count<<<nb, kBlock, 0, st>>>(key, n, (int8_t *)c->dR.p, (uint32_t *)c->cnt.p, lhist, nb);
     TPM_LAUNCHED(c, "k_count");
     TPM_TRY(scan_u32(c, (const uint32_t *)c->cnt.p, (uint32_t *)c->base.p, n, lvl_count + 32));
+    TPM_TRY(scan_u32(c, lhist, loff, (int64_t)kLevels * nb, lvl_count + 33));
+    k_level_starts<<<1, 64, 0, st>>>(loff, nb, lvl_count);
+    TPM_LAUNCHED(c, "k_level_starts");
     TPM_HIP(c, hipMemcpyAsync(c->hpin, lvl_count, 64 * sizeof(uint32_t), hipMemcpyDeviceToHost,
                               st));
     if (!P.periodic)
         TPM_HIP(c, hipMemcpyAsync(&c->frame_host, F, sizeof(Frame), hipMemcpyDeviceToHost, st));
     TPM_HIP(c, hipStreamSynchronize(st));
     const uint32_t E = c->hpin[32];
-    if ((uint64_t)E != (uint64_t)n + [&] {
-            uint64_t s = 0;
-            for (int l = 0; l < kLevels; l++)
-                s += c->hpin[l];
-            return s;
-        }())
+    const uint32_t nodes = c->hpin[33];
+    if ((uint64_t)E != (uint64_t)n + nodes)
         return fail(c, TPM_EDEVICE, "tree build: entry count mismatch");
-    // cursor starts go through the upload half of the pinned buffer, which is
-    // rewritten only after the next build's readback synchronisation
-    uint32_t *up = c->hpin + 64;
-    uint32_t off = 0;
-    for (int l = 0; l < kLevels; l++) {
-        c->level_count[l] = c->hpin[l];
-        c->level_off[l] = off;
-        up[l] = off;
-        off += c->level_count[l];
-    }
-    c->level_off[kLevels] = off;
+    for (int l = 0; l < kLevels; l++)
+        c->level_off[l] = c->hpin[l];
+    c->level_off[kLevels] = nodes;
+    for (int l = 0; l < kLevels; l++)
+        c->level_count[l] = c->level_off[l + 1] - c->level_off[l];
+    const uint32_t off = nodes;
     TPM_TRY(ensure(c, c->rec64, (size_t)E * sizeof(Rec64)));
     TPM_TRY(ensure(c, c->efirst, (size_t)E * 4));
     TPM_TRY(ensure(c, c->ecount, (size_t)E * 4));
     TPM_TRY(ensure(c, c->lvl_list, (size_t)(off > 0 ? off : 1) * 4));
-    TPM_HIP(c, hipMemcpyAsync(c->lvl_cursor.p, up, kLevels * sizeof(uint32_t),
-                              hipMemcpyHostToDevice, st));
     Rec64 *rec = (Rec64 *)c->rec64.p;
     k_emit<<<grid_for(n, kBlock), kBlock, 0, st>>>(
-        key, n, (const int8_t *)c->dR.p, (const uint32_t *)c->base.p, E, F,
+        key, n, (const int8_t *)c->dR.p, (const uint32_t *)c->base.p, F,
         (const double *)c->ps.p, (const double *)c->ms.p, (const uint64_t *)c->qs.p, rec,
-        (uint32_t *)c->efirst.p, (uint32_t *)c->ecount.p, (uint32_t *)c->pe.p,
-        (uint32_t *)c->lvl_cursor.p, (uint32_t *)c->lvl_list.p);
+        (uint32_t *)c->efirst.p, (uint32_t *)c->ecount.p, (uint32_t *)c->pe.p, loff, nb,
+        (uint32_t *)c->lvl_list.p);
     TPM_LAUNCHED(c, "k_emit");
     // 5. moments, deepest level first
     for (int l = kMaxLevel; l >= 0; l--) {
@@ -515,7 +510,8 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
         if (!cnt)
             continue;
         k_moments<<<grid_for(cnt, kBlock), kBlock, 0, st>>>(
-            rec, (const uint32_t *)c->lvl_list.p + c->level_off[l], cnt);
+            rec, E, (uint32_t *)c->ecount.p, (const uint32_t *)c->lvl_list.p + c->level_off[l],
+            cnt, (uint32_t)l);
         TPM_LAUNCHED(c, "k_moments");
     }
     if (P.precision == TPM_FP32) {

@@ -13,6 +13,7 @@
 // The gradient is taken inside the interpolation kernel from the potential.
 #include "tpm_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -32,17 +33,18 @@ __global__ __launch_bounds__(kBlock) void k_deposit(const double *__restrict__ p
                                                     const Rec64 *__restrict__ rec, double box,
                                                     double h, int ng,
                                                     unsigned long long *__restrict__ mesh) {
-    int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= n)
-        return;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool live = s < n;
+    const int lane = threadIdx.x & 63;
+    const uint64_t le = ~0ull >> (63 - lane);  // lanes 0..lane
     int ex;
     frexp(rec[0].mass, &ex);  // total mass < 2^ex
     const double scale = ldexp(1.0, 62 - ex);
-    int i0[3];
-    double w[3];
+    int i0[3] = {0, 0, 0};
+    double w[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        double u = ps[(size_t)a * n + s];
+        double u = live ? ps[(size_t)a * n + s] : 0.0;
         if (u < 0.0)
             u += box;
         if (u >= box)
@@ -56,7 +58,10 @@ __global__ __launch_bounds__(kBlock) void k_deposit(const double *__restrict__ p
             i += ng;
         i0[a] = i;
     }
-    const double m = ms[s];
+    const double m = live ? ms[s] : 0.0;
+    // Particles are in curve order, so neighbouring lanes often hit the same
+    // cells: sum equal cells across the wavefront first (integers, so the
+    // result does not depend on the grouping) and issue one atomic per run.
 #pragma unroll
     for (int c = 0; c < 8; c++) {
         double wt = 1.0;
@@ -67,8 +72,22 @@ __global__ __launch_bounds__(kBlock) void k_deposit(const double *__restrict__ p
             wt *= up ? w[a] : 1.0 - w[a];
             t[a] = up ? (i0[a] + 1 == ng ? 0 : i0[a] + 1) : i0[a];
         }
-        const unsigned long long q = __double2ull_rn(m * wt * scale);
-        atomicAdd(&mesh[((size_t)t[0] * ng + t[1]) * ng + t[2]], q);
+        const uint32_t cell =
+            live ? (uint32_t)(((size_t)t[0] * ng + t[1]) * ng + t[2]) : 0xffffffffu;
+        unsigned long long q = live ? __double2ull_rn(m * wt * scale) : 0ull;
+        const uint32_t prev = __shfl_up(cell, 1, 64);
+        const bool head = lane == 0 || prev != cell;
+        const uint64_t heads = __ballot(head);
+        const uint32_t seg = (uint32_t)__popcll(heads & le);  // run id of this lane
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {  // suffix sums within each run
+            const unsigned long long oq = __shfl_down(q, off, 64);
+            const uint32_t os = __shfl_down(seg, off, 64);
+            if (lane + off < 64 && os == seg)
+                q += oq;
+        }
+        if (live && head)
+            atomicAdd(&mesh[cell], q);
     }
 }
 
@@ -215,24 +234,20 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int ng, int logn, in
     }
 }
 
-// Fused four-point difference and CIC interpolation at the targets.
+// Fused four-point difference and CIC interpolation, over the active slots
+// in curve order (neighbouring threads read neighbouring mesh cells); the
+// results go to slot order and are scattered to caller order afterwards.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_interp(
-    const int32_t *__restrict__ idx, int64_t n_act, int64_t n, const int32_t *__restrict__ rank,
-    const double *__restrict__ ps, const T *__restrict__ phi, int ng, double box, double h,
-    T *__restrict__ acc, T *__restrict__ pot, uint32_t *__restrict__ err) {
-    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= n_act)
+__global__ __launch_bounds__(kBlock) void k_interp(const uint32_t *__restrict__ act,
+                                                   const uint32_t *__restrict__ nuniq,
+                                                   int64_t n, const double *__restrict__ ps,
+                                                   const T *__restrict__ phi, int ng, double box,
+                                                   double h, T *__restrict__ res,
+                                                   T *__restrict__ rpot) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= (int64_t)*nuniq)
         return;
-    const int32_t pi = idx[k];
-    if (pi < 0 || (int64_t)pi >= n) {
-        acc[k] = acc[n_act + k] = acc[2 * n_act + k] = (T)NAN;
-        if (pot)
-            pot[k] = (T)NAN;
-        atomicOr(err, 1u);
-        return;
-    }
-    const int64_t s = rank[pi];
+    const int64_t s = act[k];
     int i0[3];
     double w[3];
 #pragma unroll
@@ -287,11 +302,34 @@ __global__ __launch_bounds__(kBlock) void k_interp(
         }
         P += wt * at(t[0], t[1], t[2]);
     }
-    acc[k] = (T)F[0];
-    acc[n_act + k] = (T)F[1];
-    acc[2 * n_act + k] = (T)F[2];
+    res[k] = (T)F[0];
+    res[n + k] = (T)F[1];
+    res[2 * n + k] = (T)F[2];
+    rpot[k] = (T)P;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scatter_out(
+    const int32_t *__restrict__ idx, int64_t n_act, int64_t n, const int32_t *__restrict__ rank,
+    const uint32_t *__restrict__ slot, const T *__restrict__ res, const T *__restrict__ rpot,
+    T *__restrict__ acc, T *__restrict__ pot, uint32_t *__restrict__ err) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n_act)
+        return;
+    const int32_t i = idx[k];
+    if (i < 0 || (int64_t)i >= n) {
+        acc[k] = acc[n_act + k] = acc[2 * n_act + k] = (T)NAN;
+        if (pot)
+            pot[k] = (T)NAN;
+        atomicOr(err, 1u);
+        return;
+    }
+    const uint32_t sl = slot[rank[i]];
+    acc[k] = res[sl];
+    acc[n_act + k] = res[n + sl];
+    acc[2 * n_act + k] = res[2 * n + sl];
     if (pot)
-        pot[k] = (T)P;
+        pot[k] = rpot[sl];
 }
 
 template <typename T>
@@ -370,11 +408,22 @@ template <typename T>
 int interp_t(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, void *pot) {
     const tpm_params &P = c->P;
     const int ng = P.pm_grid;
+    const int64_t n = c->n;
     const double box = P.box_size, h = box / ng;
-    k_interp<T><<<grid_for(n_act, kBlock), kBlock, 0, c->stream>>>(
-        idx, n_act, c->n, (const int32_t *)c->rank.p, (const double *)c->ps.p,
-        (const T *)c->mesh_phi.p, ng, box, h, (T *)acc, (T *)pot, (uint32_t *)c->err_flag.p);
+    TPM_TRY(ensure(c, c->res, (size_t)3 * n * sizeof(T)));
+    TPM_TRY(ensure(c, c->rpot, (size_t)n * sizeof(T)));
+    TPM_TRY(select_active(c, n_act, idx));
+    const unsigned g = grid_for(std::min<int64_t>(n_act, n), kBlock);
+    k_interp<T><<<g, kBlock, 0, c->stream>>>(
+        (const uint32_t *)c->act.p, (const uint32_t *)c->counters.p + 40, n,
+        (const double *)c->ps.p, (const T *)c->mesh_phi.p, ng, box, h, (T *)c->res.p,
+        (T *)c->rpot.p);
     TPM_LAUNCHED(c, "k_interp");
+    k_scatter_out<T><<<grid_for(n_act, kBlock), kBlock, 0, c->stream>>>(
+        idx, n_act, n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
+        (const T *)c->res.p, (const T *)c->rpot.p, (T *)acc, (T *)pot,
+        (uint32_t *)c->err_flag.p);
+    TPM_LAUNCHED(c, "k_scatter_out");
     return TPM_OK;
 }
 

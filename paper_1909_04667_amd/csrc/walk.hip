@@ -376,9 +376,8 @@ __global__ __launch_bounds__(kBlock) void k_walk32(const WalkArgs A) {
 // wave's targets stay spatially close on the curve.
 
 template <bool PER, bool TPM, int OPEN, bool POT>
-__global__ __launch_bounds__(kBlock) void k_walk64i(const WalkArgs A, uint32_t K) {
+__device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, uint32_t K) {
     const int lane = threadIdx.x & 63;
-    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint32_t nu = *A.nuniq;
     const uint32_t base = wave * 64u * K;
     if (base >= nu)
@@ -464,9 +463,8 @@ __global__ __launch_bounds__(kBlock) void k_walk64i(const WalkArgs A, uint32_t K
 }
 
 template <bool PER, bool TPM, int OPEN, bool POT>
-__global__ __launch_bounds__(kBlock) void k_walk32i(const WalkArgs A, uint32_t K) {
+__device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, uint32_t K) {
     const int lane = threadIdx.x & 63;
-    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint32_t nu = *A.nuniq;
     const uint32_t base = wave * 64u * K;
     if (base >= nu)
@@ -550,6 +548,16 @@ __global__ __launch_bounds__(kBlock) void k_walk32i(const WalkArgs A, uint32_t K
             }
         }
     }
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT>
+__global__ __launch_bounds__(kBlock) void k_walk64i(const WalkArgs A, uint32_t K) {
+    walk_lanes64<PER, TPM, OPEN, POT>(A, (blockIdx.x * kBlock + threadIdx.x) >> 6, K);
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT>
+__global__ __launch_bounds__(kBlock) void k_walk32i(const WalkArgs A, uint32_t K) {
+    walk_lanes32<PER, TPM, OPEN, POT>(A, (blockIdx.x * kBlock + threadIdx.x) >> 6, K);
 }
 
 // ---- active set -> slots in curve order --------------------------------------
@@ -726,6 +734,17 @@ int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
     return TPM_OK;
 }
 
+// Walk variant: independent lanes when the 64 targets of a group are far
+// apart (sparse active sets: a shared cursor would visit the union of their
+// walks) or when the interaction is expensive (FP64 with the erfc factor);
+// the shared cursor otherwise.  Both give identical results.
+static bool use_lanes(const tpm_ctx *c, int64_t n_act) {
+    if (c->walk_mode != 0)
+        return c->walk_mode == 2;
+    const bool fp64_tpm = c->P.precision == TPM_FP64 && c->P.pm_grid > 0;
+    return fp64_tpm || 4 * n_act < c->n;
+}
+
 static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
     const tpm_params &P = c->P;
     const int64_t n = c->n;
@@ -794,7 +813,7 @@ int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const
     LA.fp32 = fp32;
     // lane-independent walks pay off where the interaction is expensive and
     // the wavefront's union of cutoff spheres is large: FP64 with TreePM
-    LA.lanes = c->walk_mode == 2 || (c->walk_mode == 0 && !fp32 && tpm_on);
+    LA.lanes = use_lanes(c, n_act);
     LA.K = 1;
     if (LA.lanes) {
         // several slots per lane once there are enough wavefronts to fill the chip
@@ -850,16 +869,23 @@ namespace {
 
 struct BatchReq {
     WalkArgs A;
-    uint32_t variant;  // bit 0: relative criterion, bit 1: periodic TreePM
+    uint32_t variant;  // bit 0: relative criterion, bit 1: periodic TreePM, bit 2: lanes
     uint32_t first;    // first work item of the request
 };
 
 template <bool FP32, bool PER, bool TPM, int OPEN>
-__device__ __forceinline__ void batch_group(const WalkArgs &A, uint32_t g) {
-    if (FP32)
-        walk_group32<PER, TPM, OPEN, false>(A, g);
-    else
-        walk_group64<PER, TPM, OPEN, false>(A, g);
+__device__ __forceinline__ void batch_group(const WalkArgs &A, uint32_t g, bool lanes) {
+    if (lanes) {
+        if (FP32)
+            walk_lanes32<PER, TPM, OPEN, false>(A, g, 1u);
+        else
+            walk_lanes64<PER, TPM, OPEN, false>(A, g, 1u);
+    } else {
+        if (FP32)
+            walk_group32<PER, TPM, OPEN, false>(A, g);
+        else
+            walk_group64<PER, TPM, OPEN, false>(A, g);
+    }
 }
 
 template <bool FP32>
@@ -884,11 +910,12 @@ __global__ __launch_bounds__(kBlock) void k_walk_batch(const BatchReq *__restric
         }
         const BatchReq &R = reqs[lo];
         const uint32_t g = item - R.first;
-        switch (R.variant) {
-        case 0: batch_group<FP32, false, false, TPM_OPEN_BH>(R.A, g); break;
-        case 1: batch_group<FP32, false, false, TPM_OPEN_REL>(R.A, g); break;
-        case 2: batch_group<FP32, true, true, TPM_OPEN_BH>(R.A, g); break;
-        default: batch_group<FP32, true, true, TPM_OPEN_REL>(R.A, g); break;
+        const bool lanes = (R.variant & 4u) != 0;
+        switch (R.variant & 3u) {
+        case 0: batch_group<FP32, false, false, TPM_OPEN_BH>(R.A, g, lanes); break;
+        case 1: batch_group<FP32, false, false, TPM_OPEN_REL>(R.A, g, lanes); break;
+        case 2: batch_group<FP32, true, true, TPM_OPEN_BH>(R.A, g, lanes); break;
+        default: batch_group<FP32, true, true, TPM_OPEN_REL>(R.A, g, lanes); break;
         }
     }
 }
@@ -1042,7 +1069,8 @@ int tpm_batch_launch(tpm_batch *b) {
         BatchReq &R = b->host[o];
         R = BatchReq{};
         fill_args(c, p.anorm, R.A);
-        R.variant = (p.opening == TPM_OPEN_REL ? 1u : 0u) | (c->P.pm_grid > 0 ? 2u : 0u);
+        R.variant = (p.opening == TPM_OPEN_REL ? 1u : 0u) | (c->P.pm_grid > 0 ? 2u : 0u) |
+                    (use_lanes(c, p.n_act) ? 4u : 0u);
         R.first = items[which];
         const int64_t groups = p.n_act > 0 ? (std::min<int64_t>(p.n_act, c->n) + 63) / 64 : 0;
         items[which] += (uint32_t)groups;
