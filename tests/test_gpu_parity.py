@@ -322,3 +322,61 @@ def test_full_zeldovich_128_pm256_sampled():
     rs = 1.25 * 100.0 / 256
     apo, _ = O.pm(p.x, p.y, p.z, None, 100.0, 256, 1.0, rs, targets=samp)
     assert rel_err(apm.cpu().numpy(), apo).max() <= 1e-9
+
+
+@pytest.mark.parametrize("frac", [0.001, 0.01, 0.1])
+def test_clustered_time_bin_subsets(frac):
+    """Workload 4 at 32^3: the tree is built once and reused for nested
+    time-bin active sets; relative pass fed the oracle's own |a|."""
+    p = W.lognormal_box(32, 100.0, 4)
+    sets, _ = W.time_bin_active_sets(p.meta["rho"])
+    sub = sets[frac]
+    kw = dict(eps=100.0 / (50 * 32), periodic=True, box_size=100.0, pm_grid=64)
+    T = O.Tree(p.x, p.y, p.z, periodic=True, box=100.0)
+    Pb = _oracle_params(kw, "bh", kw["eps"])
+    ab, _, _ = T.walk(Pb, targets=sub)
+    apm, _ = O.pm(p.x, p.y, p.z, None, 100.0, 64, 1.0, 1.25 * 100.0 / 64, targets=sub)
+    an = np.zeros(p.n)
+    an[sub] = np.linalg.norm(ab + apm, axis=0)
+    Pr = _oracle_params(kw, "rel", kw["eps"])
+    ar, _, nr = T.walk(Pr, targets=sub, anorm=an)
+    for prec in ("fp64", "fp32"):
+        ctx = _ctx(precision=prec, **kw)
+        _build(ctx, p)
+        idx = _t(sub, torch.int32)
+        nint = torch.empty(sub.size, dtype=torch.int32, device=_dev())
+        acc, _ = ctx.compute_forces(idx, "rel", a_old_norm=_t(an), n_interactions=nint)
+        g_pm, _ = ctx.pm_long_range(idx)
+        ctx.check()
+        e = rel_err(acc.double().cpu().numpy(), ar)
+        if prec == "fp64":
+            assert e.max() <= 1e-10
+            assert np.array_equal(nint.cpu().numpy().astype(np.int64), nr)
+            assert rel_err(g_pm.cpu().numpy(), apm).max() <= 1e-9
+        else:
+            assert np.percentile(e, 99) <= 1e-3
+
+
+@pytest.mark.slow
+def test_full_lognormal_256_sampled():
+    """Workload 4 at full size (256^3 clustered particles): bit-exact tree,
+    FP64 forces of the 0.1 % time-bin set against the oracle."""
+    p = W.lognormal_box(256, 100.0, 4)
+    sets, _ = W.time_bin_active_sets(p.meta["rho"])
+    sub = sets[0.001]
+    samp = sub[np.random.default_rng(2).choice(sub.size, 512, replace=False)]
+    kw = dict(eps=100.0 / (50 * 256), periodic=True, box_size=100.0, pm_grid=256)
+    ctx = _ctx(**kw)
+    _build(ctx, p)
+    n, E, fr = ctx.tree_info()
+    T = O.Tree(p.x, p.y, p.z, periodic=True, box=100.0)
+    assert E == T.E
+    g = ctx.export_tree()
+    o = T.export()
+    for k in ("level", "skip", "count"):
+        assert np.array_equal(g[k], o[k]), k
+    del g, o
+    acc, _ = ctx.compute_forces(_t(samp, torch.int32), "bh")
+    ctx.check()
+    ao, _, _ = T.walk(_oracle_params(kw, "bh", kw["eps"]), targets=samp)
+    assert rel_err(acc.cpu().numpy(), ao).max() <= 1e-10
