@@ -21,7 +21,7 @@ namespace tpm {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr size_t kFftLds = 64 * 1024;  // two ping-pong buffers per block
+constexpr size_t kFftLds = 64 * 1024;  // LDS budget of one FFT block
 
 template <typename T>
 struct Cx {
@@ -91,36 +91,88 @@ __global__ __launch_bounds__(kBlock) void k_deposit(const double *__restrict__ p
     }
 }
 
-// One 1-D transform direction over a block of B lines held in LDS.
-template <typename T>
-__device__ __forceinline__ Cx<T> *stockham(Cx<T> *x, Cx<T> *y, int B, int ng, int logn,
-                                           const Cx<T> *__restrict__ tw, bool inverse) {
-    const int half = ng >> 1;
-    int s = 1;
-    for (int st = 0; st < logn; st++) {
-        const int m = half / s;  // n/2 at this stage
-        for (int id = threadIdx.x; id < B * half; id += kBlock) {
-            const int b = id / half;
-            const int j = id - b * half;
-            const int p = j / s, q = j - p * s;
-            const Cx<T> *xb = x + b * ng;
-            Cx<T> *yb = y + b * ng;
-            const Cx<T> a = xb[q + s * p];
-            const Cx<T> c = xb[q + s * (p + m)];
-            Cx<T> w = tw[p * s];
-            if (inverse)
-                w.im = -w.im;
-            const T dr = a.re - c.re, di = a.im - c.im;
-            yb[q + 2 * s * p] = Cx<T>{a.re + c.re, a.im + c.im};
-            yb[q + 2 * s * p + s] = Cx<T>{dr * w.re - di * w.im, dr * w.im + di * w.re};
-        }
-        __syncthreads();
-        Cx<T> *t = x;
-        x = y;
-        y = t;
-        s <<= 1;
+// ---- FFT: four-step decomposition in registers ------------------------------
+//
+// A line of ng = R1 * R2 points (n = R2 n1 + n2, k = k1 + R1 k2) is handled by
+// R2 threads.  Thread n2 loads x[R2 n1 + n2] (n1 = 0 .. R1-1), takes an R1-point
+// DFT in registers, multiplies by W_ng^(n2 k1), and writes the row to LDS;
+// after one exchange, thread t takes the R2-point DFTs of the columns
+// k1 = t (+ R2) and holds X[k1 + R1 k2].  Small DFTs are radix-2
+// decimation-in-frequency with compile-time twiddles (the output comes out in
+// bit-reversed order, which is only a renaming of registers).
+
+// cos(pi k / 16), k = 0 .. 8 (exact 0, 1 and sqrt(2)/2 where they occur)
+__device__ constexpr double kCosQ[9] = {1.0,
+                                        0.9807852804032304,
+                                        0.9238795325112867,
+                                        0.8314696123025452,
+                                        0.7071067811865476,
+                                        0.5555702330196023,
+                                        0.38268343236508984,
+                                        0.19509032201612833,
+                                        0.0};
+
+// exp(-2 pi i m / 32), compile-time m
+template <int M>
+struct W32 {
+    static constexpr int m = M & 31, q = m / 8, r = m % 8;
+    static constexpr double c = q == 0 ? kCosQ[r] : q == 1 ? -kCosQ[8 - r] : q == 2 ? -kCosQ[r] : kCosQ[8 - r];
+    static constexpr double s = q == 0 ? kCosQ[8 - r] : q == 1 ? kCosQ[r] : q == 2 ? -kCosQ[8 - r] : -kCosQ[r];
+    // W = cos - i sin
+};
+
+template <int R>
+__device__ constexpr int bitrev(int k) {
+    int r = 0;
+    for (int b = 1; b < R; b <<= 1) {
+        r = (r << 1) | (k & 1);
+        k >>= 1;
     }
-    return x;
+    return r;
+}
+
+template <typename T, bool INV, int M>
+__device__ __forceinline__ Cx<T> twiddle_mul(Cx<T> v) {
+    if constexpr ((M & 31) == 0) {
+        return v;
+    } else if constexpr ((M & 31) == 8) {  // -i (forward) / +i (inverse)
+        return INV ? Cx<T>{-v.im, v.re} : Cx<T>{v.im, -v.re};
+    } else if constexpr ((M & 31) == 16) {
+        return Cx<T>{-v.re, -v.im};
+    } else if constexpr ((M & 31) == 24) {
+        return INV ? Cx<T>{v.im, -v.re} : Cx<T>{-v.im, v.re};
+    } else {
+        const T c = (T)W32<M>::c, sn = INV ? (T)W32<M>::s : (T)-W32<M>::s;
+        return Cx<T>{v.re * c - v.im * sn, v.re * sn + v.im * c};
+    }
+}
+
+// One DIF butterfly stage of length LEN on an R-point register array.
+template <typename T, bool INV, int R, int LEN, int J>
+__device__ __forceinline__ void dif_j(Cx<T> *v) {
+    if constexpr (J < LEN / 2) {
+#pragma unroll
+        for (int i = 0; i < R; i += LEN) {
+            const Cx<T> a = v[i + J], b = v[i + J + LEN / 2];
+            v[i + J] = Cx<T>{a.re + b.re, a.im + b.im};
+            v[i + J + LEN / 2] = twiddle_mul<T, INV, J * (32 / LEN)>(Cx<T>{a.re - b.re, a.im - b.im});
+        }
+        dif_j<T, INV, R, LEN, J + 1>(v);
+    }
+}
+
+template <typename T, bool INV, int R, int LEN>
+__device__ __forceinline__ void dif_stages(Cx<T> *v) {
+    if constexpr (LEN >= 2) {
+        dif_j<T, INV, R, LEN, 0>(v);
+        dif_stages<T, INV, R, LEN / 2>(v);
+    }
+}
+
+// In-register R-point DFT; the result X[k] is left in v[bitrev(k)].
+template <typename T, bool INV, int R>
+__device__ __forceinline__ void dft_regs(Cx<T> *v) {
+    dif_stages<T, INV, R, R>(v);
 }
 
 struct FftPass {
@@ -131,106 +183,143 @@ struct FftPass {
     int green;       // forward, multiply by the Green's function, inverse
 };
 
-// Per-axis tables for the Green's function: k_a^2 and sinc^4(k_a h / 2).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int ng, int logn, int B,
-                                                Cx<T> *__restrict__ mesh,
+// One line transform: on entry thread n2 holds a[n1] = x[R2 n1 + n2]; on exit
+// it holds, for column c (k1 = n2 + c R2), X[k1 + R1 k2] in out[c * R2 + k2].
+template <typename T, bool INV, int R1, int R2>
+__device__ __forceinline__ void line_fft(Cx<T> *a, Cx<T> *out, Cx<T> *row, int n2,
+                                         const Cx<T> *__restrict__ tw, bool active) {
+    constexpr int NG = R1 * R2, C = R1 / R2, PAD = R2 + 1;
+    if (active) {
+        dft_regs<T, INV, R1>(a);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; k1++) {
+            Cx<T> v = a[bitrev<R1>(k1)];
+            if (k1 && n2) {
+                Cx<T> w = tw[(n2 * k1) & (NG - 1)];
+                if (INV)
+                    w.im = -w.im;
+                v = Cx<T>{v.re * w.re - v.im * w.im, v.re * w.im + v.im * w.re};
+            }
+            row[k1 * PAD + n2] = v;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < C; c++) {
+            const int k1 = n2 + c * R2;
+            Cx<T> b[R2];
+#pragma unroll
+            for (int m = 0; m < R2; m++)
+                b[m] = row[k1 * PAD + m];
+            dft_regs<T, INV, R2>(b);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; k2++)
+                out[c * R2 + k2] = b[bitrev<R2>(k2)];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int R1, int R2>
+__global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__restrict__ mesh,
                                                 const unsigned long long *__restrict__ mq,
                                                 T *__restrict__ phi, const Cx<T> *__restrict__ tw,
                                                 const double *__restrict__ gk2,
                                                 const double *__restrict__ gdc, double gconst,
                                                 double rs, const Rec64 *__restrict__ rec,
                                                 double vinv, double norm) {
+    constexpr int NG = R1 * R2, C = R1 / R2, PAD = R2 + 1;
     extern __shared__ unsigned char lds_raw[];
-    Cx<T> *buf0 = (Cx<T> *)lds_raw;
-    Cx<T> *buf1 = buf0 + (size_t)B * ng;
-    const size_t ng2 = (size_t)ng * ng;
-    // line base offsets and element stride
-    size_t base0;
-    size_t stride;
-    int lines_contig;  // 1: lines are contiguous (axis z)
+    Cx<T> *lds = (Cx<T> *)lds_raw;  // B rows of R1 x (R2 + 1)
+    const size_t ng2 = (size_t)NG * NG;
+    const int tid = threadIdx.x;
+    int b, n2;
+    if (ps.axis == 2) {  // contiguous lines: a line's threads adjacent
+        b = tid / R2;
+        n2 = tid % R2;
+    } else {  // strided lines: neighbouring lines adjacent (coalesced)
+        n2 = tid / B;
+        b = tid % B;
+    }
+    const bool active = b < B && n2 < R2 && tid < B * R2;
+    size_t base, stride;
+    int jline = 0, kline = 0;  // (y, z) of an x line, for the Green's function
     if (ps.axis == 2) {
-        base0 = (size_t)blockIdx.x * B * ng;
+        base = ((size_t)blockIdx.x * B + b) * NG;
         stride = 1;
-        lines_contig = 1;
     } else {
-        const int per = ng / B;
+        const int per = NG / B;
         const size_t outer = blockIdx.x / per, kb = blockIdx.x % per;
         if (ps.axis == 1)
-            base0 = outer * ng2 + kb * B;
+            base = outer * ng2 + kb * B + b;
         else
-            base0 = outer * ng + kb * B;
-        stride = ps.axis == 1 ? (size_t)ng : ng2;
-        lines_contig = 0;
+            base = outer * NG + kb * B + b;
+        stride = ps.axis == 1 ? (size_t)NG : ng2;
+        jline = (int)outer;
+        kline = (int)(kb * B + b);
     }
+    Cx<T> *row = lds + (size_t)(active ? b : 0) * R1 * PAD;
     double qscale = 0.0;
     if (ps.in_fixed) {
         int ex;
         frexp(rec[0].mass, &ex);
         qscale = ldexp(1.0, ex - 62) * vinv;
     }
-    const int total = B * ng;
-    for (int id = threadIdx.x; id < total; id += kBlock) {
-        int b, k;
-        size_t g;
-        if (lines_contig) {
-            b = id / ng;
-            k = id - b * ng;
-            g = base0 + (size_t)b * ng + k;
-        } else {
-            k = id / B;
-            b = id - k * B;
-            g = base0 + b + (size_t)k * stride;
+    Cx<T> a[R1], o[R1];
+    if (active) {
+#pragma unroll
+        for (int n1 = 0; n1 < R1; n1++) {
+            const size_t g = base + (size_t)(R2 * n1 + n2) * stride;
+            if (ps.in_fixed)
+                a[n1] = Cx<T>{(T)((double)mq[g] * qscale), (T)0};
+            else
+                a[n1] = mesh[g];
         }
-        Cx<T> v;
-        if (ps.in_fixed) {
-            v.re = (T)((double)mq[g] * qscale);
-            v.im = (T)0;
-        } else {
-            v = mesh[g];
-        }
-        buf0[b * ng + k] = v;
     }
-    __syncthreads();
-    Cx<T> *res = stockham<T>(buf0, buf1, B, ng, logn, tw, ps.inverse && !ps.green);
+    if (ps.inverse && !ps.green)
+        line_fft<T, true, R1, R2>(a, o, row, n2, tw, active);
+    else
+        line_fft<T, false, R1, R2>(a, o, row, n2, tw, active);
     if (ps.green) {
-        // x lines: the block fixes (j, k) = (outer, kb * B + b); i runs along the line
-        const int per = ng / B;
-        const int j = blockIdx.x / per, kb = blockIdx.x % per;
-        for (int id = threadIdx.x; id < total; id += kBlock) {
-            const int b = id / ng, i = id - b * ng;
-            const int k = kb * B + b;
-            const double k2 = (gk2[i] + gk2[j]) + gk2[k];
-            const double dc = (gdc[i] * gdc[j]) * gdc[k];
-            double g = 0.0;
-            if (k2 != 0.0)
-                g = gconst * exp(-k2 * rs * rs) / (k2 * dc);
-            Cx<T> v = res[b * ng + i];
-            v.re = (T)(v.re * g);
-            v.im = (T)(v.im * g);
-            res[b * ng + i] = v;
+        // natural order through LDS, Green's function, inverse transform
+        Cx<T> *line = row;  // reuse this line's LDS (NG <= R1 * PAD)
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < C; c++)
+#pragma unroll
+                for (int k2 = 0; k2 < R2; k2++)
+                    line[(n2 + c * R2) + R1 * k2] = o[c * R2 + k2];
         }
         __syncthreads();
-        Cx<T> *other = (res == buf0) ? buf1 : buf0;
-        res = stockham<T>(res, other, B, ng, logn, tw, true);
-    }
-    for (int id = threadIdx.x; id < total; id += kBlock) {
-        int b, k;
-        size_t g;
-        if (lines_contig) {
-            b = id / ng;
-            k = id - b * ng;
-            g = base0 + (size_t)b * ng + k;
-        } else {
-            k = id / B;
-            b = id - k * B;
-            g = base0 + b + (size_t)k * stride;
+        if (active) {
+#pragma unroll
+            for (int n1 = 0; n1 < R1; n1++) {
+                const int i = R2 * n1 + n2;
+                const double k2s = (gk2[i] + gk2[jline]) + gk2[kline];
+                const double dc = (gdc[i] * gdc[jline]) * gdc[kline];
+                double g = 0.0;
+                if (k2s != 0.0)
+                    g = gconst * exp(-k2s * rs * rs) / (k2s * dc);
+                const Cx<T> v = line[i];
+                a[n1] = Cx<T>{(T)(v.re * g), (T)(v.im * g)};
+            }
         }
-        const Cx<T> v = res[b * ng + k];
-        if (ps.out_real)
-            phi[g] = (T)(v.re * norm);
-        else
-            mesh[g] = v;
+        __syncthreads();
+        line_fft<T, true, R1, R2>(a, o, row, n2, tw, active);
+    }
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < C; c++)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; k2++) {
+                const size_t g = base + (size_t)((n2 + c * R2) + R1 * k2) * stride;
+                const Cx<T> v = o[c * R2 + k2];
+                if (ps.out_real)
+                    phi[g] = (T)(v.re * norm);
+                else
+                    mesh[g] = v;
+            }
     }
 }
 
@@ -332,6 +421,26 @@ __global__ __launch_bounds__(kBlock) void k_scatter_out(
         pot[k] = rpot[sl];
 }
 
+template <typename T, int R1, int R2>
+int launch_fft(tpm_ctx *c, const FftPass &fp, Cx<T> *mc, const unsigned long long *mq, T *phi,
+               const Cx<T> *tw, const double *gk2, const double *gdc, double gconst, double rs,
+               const Rec64 *rec, double vinv, double norm) {
+    constexpr int NG = R1 * R2;
+    // lines per block: one wavefront group of R2 threads per line, at most
+    // kBlock threads, the LDS rows within the budget, and B | NG
+    int B = kBlock / R2;
+    while ((size_t)B * R1 * (R2 + 1) * sizeof(Cx<T>) > kFftLds)
+        B >>= 1;
+    if (B > NG)
+        B = NG;
+    const size_t lds = (size_t)B * R1 * (R2 + 1) * sizeof(Cx<T>);
+    const unsigned blocks = (unsigned)((size_t)NG * NG / B);
+    k_fft<T, R1, R2><<<blocks, kBlock, lds, c->stream>>>(fp, B, mc, mq, phi, tw, gk2, gdc,
+                                                         gconst, rs, rec, vinv, norm);
+    TPM_LAUNCHED(c, "k_fft");
+    return TPM_OK;
+}
+
 template <typename T>
 int solve_t(tpm_ctx *c) {
     const tpm_params &P = c->P;
@@ -344,12 +453,12 @@ int solve_t(tpm_ctx *c) {
     TPM_TRY(ensure(c, c->mesh_q, n3 * 8));
     TPM_TRY(ensure(c, c->mesh_c, n3 * sizeof(Cx<T>)));
     TPM_TRY(ensure(c, c->mesh_phi, n3 * sizeof(T)));
-    TPM_TRY(ensure(c, c->twiddle, (size_t)ng / 2 * sizeof(Cx<T>) + 64));
+    TPM_TRY(ensure(c, c->twiddle, (size_t)ng * sizeof(Cx<T>) + 64));
     TPM_TRY(ensure(c, c->green_axis, (size_t)2 * ng * sizeof(double)));
     // tables, computed in double on the host
     {
-        std::vector<Cx<T>> tw(ng / 2);
-        for (int k = 0; k < ng / 2; k++) {
+        std::vector<Cx<T>> tw(ng);
+        for (int k = 0; k < ng; k++) {
             const double a = 2.0 * M_PI * k / ng;
             tw[k] = Cx<T>{(T)std::cos(a), (T)-std::sin(a)};
         }
@@ -377,13 +486,6 @@ int solve_t(tpm_ctx *c) {
         (const double *)c->ps.p, (const double *)c->ms.p, c->n, (const Rec64 *)c->rec64.p, box, h,
         ng, mq);
     TPM_LAUNCHED(c, "k_deposit");
-    int B = (int)(kFftLds / (2 * (size_t)ng * sizeof(Cx<T>)));
-    if (B > ng)
-        B = ng;
-    if (B < 1)
-        return fail(c, TPM_EINVAL, "pm_grid too large for the LDS line block");
-    const size_t lds = 2 * (size_t)B * ng * sizeof(Cx<T>);
-    const unsigned blocks = (unsigned)((size_t)ng * ng / B);
     const double *gk2 = (const double *)c->green_axis.p;
     const double *gdc = gk2 + ng;
     const double gconst = -4.0 * M_PI * P.G;
@@ -397,9 +499,19 @@ int solve_t(tpm_ctx *c) {
     const FftPass passes[5] = {
         {2, 1, 0, 0, 0}, {1, 0, 0, 0, 0}, {0, 0, 0, 0, 1}, {1, 0, 0, 1, 0}, {2, 0, 1, 1, 0}};
     for (const FftPass &fp : passes) {
-        k_fft<T><<<blocks, kBlock, lds, st>>>(fp, ng, logn, B, mc, mq, phi, tw, gk2, gdc, gconst,
-                                              rs, rec, vinv, norm);
-        TPM_LAUNCHED(c, "k_fft");
+        int rc;
+        switch (ng) {
+        case 8: rc = launch_fft<T, 4, 2>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
+        case 16: rc = launch_fft<T, 4, 4>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
+        case 32: rc = launch_fft<T, 8, 4>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
+        case 64: rc = launch_fft<T, 8, 8>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
+        case 128: rc = launch_fft<T, 16, 8>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
+        case 256: rc = launch_fft<T, 16, 16>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
+        case 512: rc = launch_fft<T, 32, 16>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
+        case 1024: rc = launch_fft<T, 32, 32>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
+        default: return fail(c, TPM_EINVAL, "unsupported pm_grid");
+        }
+        TPM_TRY(rc);
     }
     return TPM_OK;
 }
