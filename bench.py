@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the local-timestep and serving legs")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="finish with one plain device copy of MIB MiB (calibrates the "
+                         "profiler's HBM byte counters)")
     return ap.parse_args()
 
 
@@ -370,6 +373,14 @@ def main():
                                             "max": float(e.max())}
         line["cpu_baseline"] = cb
     print(json.dumps(line))
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # reads and writes exactly copy_probe MiB each
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

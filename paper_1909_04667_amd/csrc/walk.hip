@@ -355,14 +355,28 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Remap so that each XCD takes a contiguous eighth of the groups: a
+// compact region of space whose part of the tree stays in that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+    const uint32_t full = nb & ~7u;
+    if (b >= full)
+        return b;
+    return (b & 7u) * (full >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ uint32_t wave_id() {
+    return (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 6;
+}
+
 template <bool PER, bool TPM, int OPEN, bool POT>
 __global__ __launch_bounds__(kBlock) void k_walk64(const WalkArgs A) {
-    walk_group64<PER, TPM, OPEN, POT>(A, (blockIdx.x * kBlock + threadIdx.x) >> 6);
+    walk_group64<PER, TPM, OPEN, POT>(A, wave_id());
 }
 
 template <bool PER, bool TPM, int OPEN, bool POT>
 __global__ __launch_bounds__(kBlock) void k_walk32(const WalkArgs A) {
-    walk_group32<PER, TPM, OPEN, POT>(A, (blockIdx.x * kBlock + threadIdx.x) >> 6);
+    walk_group32<PER, TPM, OPEN, POT>(A, wave_id());
 }
 
 // ---- lane-independent walks ------------------------------------------------
@@ -552,12 +566,12 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
 
 template <bool PER, bool TPM, int OPEN, bool POT>
 __global__ __launch_bounds__(kBlock) void k_walk64i(const WalkArgs A, uint32_t K) {
-    walk_lanes64<PER, TPM, OPEN, POT>(A, (blockIdx.x * kBlock + threadIdx.x) >> 6, K);
+    walk_lanes64<PER, TPM, OPEN, POT>(A, wave_id(), K);
 }
 
 template <bool PER, bool TPM, int OPEN, bool POT>
 __global__ __launch_bounds__(kBlock) void k_walk32i(const WalkArgs A, uint32_t K) {
-    walk_lanes32<PER, TPM, OPEN, POT>(A, (blockIdx.x * kBlock + threadIdx.x) >> 6, K);
+    walk_lanes32<PER, TPM, OPEN, POT>(A, wave_id(), K);
 }
 
 // ---- active set -> slots in curve order --------------------------------------
