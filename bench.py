@@ -49,12 +49,13 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=3, choices=[2, 3, 4])
     ap.add_argument("--precision", default="both", choices=["both", "fp32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 21,
+                    help="targets of the oracle walks (all of the default workload)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the local-timestep and serving legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -224,6 +225,31 @@ def run_serving(n_requests=300, n_systems=16, seed=5):
                             "rejected": s2["rejected"]}}
 
 
+def counted_traffic(workload, kernel):
+    """HBM bytes per launch of the dominant walk kernel from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by a copy probe),
+    or None when the summary is missing, covers another workload, or the
+    kernel's sources changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_walk32_rel_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic: "):
+                rec = json.loads(line[len("traffic: "):])
+    if rec is None or rec.get("workload") != workload or rec.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def pct(v, q):
     v = sorted(v)
     if not v:
@@ -234,7 +260,7 @@ def pct(v, q):
 
 def cpu_baseline(p, kw, sample, cfg):
     """The FP64 oracle on the host: tree build and PM solve of the whole
-    system, both walks on a bounded sample of targets, scaled to N."""
+    system, both walks on up to ``sample`` targets (scaled to N if fewer)."""
     import numpy as np
     import oracle as O
     periodic = bool(kw.get("periodic"))
@@ -272,8 +298,10 @@ def cpu_baseline(p, kw, sample, cfg):
                        f"({t_build:.1f} s)"
                        + (f", PM solve of the full {kw['pm_grid']}^3 mesh ({t_pm:.1f} s)"
                           if periodic else "")
-                       + f", BH + relative walks of {samp.size} sampled targets on "
-                         f"{O.max_threads()} threads ({t_bh + t_rel:.1f} s) scaled to N"),
+                       + (f", BH + relative walks of all {p.n} targets" if samp.size == p.n
+                          else f", BH + relative walks of {samp.size} sampled targets")
+                       + f" on {O.max_threads()} threads ({t_bh + t_rel:.1f} s)"
+                       + ("" if samp.size == p.n else " scaled to N")),
             "seconds": {"build": t_build, "pm": t_pm, "walk_bh_sample": t_bh,
                         "walk_rel_sample": t_rel, "step_estimate": step},
             "acc_sample": (ar + apm), "samp": samp}
@@ -320,6 +348,9 @@ def main():
     h = out_prec[precs[0]]
     walk_ms = h["kernel_ms"]["walk_rel"]
     achieved = res[precs[0]]["inter_rel"] * fl / (walk_ms * 1e-3) / 1e12
+    per, tpm = ("true", "true") if periodic else ("false", "false")
+    walk_kernel = (f"k_walk32<{per}, {tpm}, 1, false>" if precs[0] == "fp32"
+                   else f"k_walk64{'i' if periodic else ''}<{per}, {tpm}, 1, false>")
     line = {
         "metric": METRIC,
         "value": h["value"],
@@ -341,9 +372,11 @@ def main():
         "latency_ms": h["latency_ms"],
         "per_precision": out_prec,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK[precs[0]],
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[precs[0]], "traffic": None,
-                     "kernel": f"k_walk{'32' if precs[0] == 'fp32' else '64'} (relative pass)",
-                     "flops_per_interaction": fl},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[precs[0]],
+                     "traffic": counted_traffic(c["name"], walk_kernel),
+                     "kernel": walk_kernel, "flops_per_interaction": fl,
+                     "interactions_per_launch": res[precs[0]]["inter_rel"],
+                     "launch_ms": walk_ms},
     }
     if len(precs) == 2:
         a32, a64 = res["fp32"]["acc"].numpy(), res["fp64"]["acc"].numpy()
