@@ -483,6 +483,11 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
     if (!P.periodic)
         TPM_HIP(c, hipMemcpyAsync(&c->frame_host, F, sizeof(Frame), hipMemcpyDeviceToHost, st));
     TPM_HIP(c, hipStreamSynchronize(st));
+    // the FP32 walk works in units of L 2^-22 and scales sizes by 2^-level
+    // through the exponent: both need a root size well inside float range
+    if (P.precision == TPM_FP32 &&
+        !(c->frame_host.L >= 0x1p-80 && c->frame_host.L <= 0x1p+80))
+        return fail(c, TPM_EINVAL, "FP32 path: root cube size outside [2^-80, 2^80]");
     const uint32_t E = c->hpin[32];
     const uint32_t nodes = c->hpin[33];
     if ((uint64_t)E != (uint64_t)n + nodes)

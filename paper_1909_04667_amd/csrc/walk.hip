@@ -39,12 +39,21 @@ struct WalkArgs {
     double L;
     double box, half;
     double G, theta2, alpha, h, hinv, h3inv, rc2, inv2rs;
+    // root cube: L^2, 0.6 L (box rule), L/2; a level-l cube's values follow
+    // by exponent arithmetic
+    double L2r, limr, hlr;
     // single-precision copies
     float fu, fL, ftheta2, falpha, fh2, fhinv, fh3inv, frc2, finv2rs;
+    float fL2r, flimr, fhlr;
     void *res;
     void *rpot;
     uint32_t *rnint;
 };
+
+// Wavefront masks: ballot of a lane predicate, and a mask read back as the
+// predicate of each lane.
+__device__ __forceinline__ uint64_t wave_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
 // ---- FP64 arithmetic (fixed operation order, explicit fma) -------------------
 
@@ -107,7 +116,72 @@ __device__ __forceinline__ double wrap64(double d, double box, double half) {
     return d;
 }
 
-// One wavefront walks group `wave` (slots 64 wave .. 64 wave + 63).
+__device__ __forceinline__ double spline_g64_sel(double u) {
+    const double u2 = u * u;
+    const double inner = fma(u2, fma(32.0, u, -38.4), 32.0 / 3.0);
+    const double cubic = fma(fma(fma(-32.0 / 3.0, u, 38.4), u, -48.0), u, 64.0 / 3.0);
+    const double outer = cubic - 1.0 / (15.0 * (u * u * u));
+    return u < 0.5 ? inner : outer;
+}
+
+__device__ __forceinline__ double spline_phi64_sel(double u) {
+    const double u2 = u * u;
+    const double inner = u2 * (16.0 / 3.0 + u2 * (-48.0 / 5.0 + u * (32.0 / 5.0))) - 14.0 / 5.0;
+    const double outer =
+        u2 * (32.0 / 3.0 + u * (-16.0 + u * (48.0 / 5.0 + u * (-32.0 / 15.0)))) - 16.0 / 5.0 +
+        1.0 / (15.0 * u);
+    return u < 0.5 ? inner : outer;
+}
+
+// The interaction of interact64 for the lanes with `inter` set, executed by
+// the whole wavefront (callers branch on "some lane interacts", a uniform
+// condition); per-lane choices are selects, so every interacting lane gets
+// exactly interact64's result.
+template <bool TPM, bool POT>
+__device__ __forceinline__ void interact64_wave(const WalkArgs &A, bool inter, double m, double d0,
+                                                double d1, double d2, double dd, double &a0,
+                                                double &a1, double &a2, double &pot,
+                                                uint32_t &nint) {
+    const double Gm = A.G * m;
+    const double r = sqrt(dd);
+    const double rinv = 1.0 / r;
+    double fac = Gm * rinv * rinv * rinv;
+    double phi = 0.0;
+    if (POT)
+        phi = -Gm * rinv;
+    const bool soft = r < A.h;
+    if (wave_mask(inter && soft)) {
+        const double u = r / A.h;
+        fac = soft ? (Gm * A.h3inv) * spline_g64_sel(u) : fac;
+        if (POT)
+            phi = soft ? (Gm * A.hinv) * spline_phi64_sel(u) : phi;
+    }
+    if (TPM) {
+        // lanes that do not interact take a harmless argument
+        const double x = inter ? r * A.inv2rs : 1.0;
+        const double ec = erfc(x);
+        fac = fac * (ec + (x * 1.1283791670955126) * exp(-(x * x)));
+        if (POT)
+            phi = phi * ec;
+    }
+    fac = inter ? fac : 0.0;
+    a0 = fma(fac, d0, a0);
+    a1 = fma(fac, d1, a1);
+    a2 = fma(fac, d2, a2);
+    if (POT)
+        pot += inter ? phi : 0.0;
+    nint += inter ? 1u : 0u;
+}
+
+// Side of a level-`lev` cube, scaled from the root side through the exponent
+// field (exact: the root side is a normal number and lev <= 21).
+__device__ __forceinline__ double scale_level(double v, uint32_t lev) {
+    return __longlong_as_double(__double_as_longlong(v) - ((long long)lev << 52));
+}
+
+// One wavefront walks group `wave` (slots 64 wave .. 64 wave + 63).  The
+// cursor and the entry are wavefront-uniform; each lane decides for itself
+// (as masks) and only branches on wavefront-uniform conditions are taken.
 template <bool PER, bool TPM, int OPEN, bool POT>
 __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
     const int lane = threadIdx.x & 63;
@@ -122,6 +196,7 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
     double an = 0.0;
     if (OPEN == TPM_OPEN_REL)
         an = A.anorm[A.perm[s]];
+    const double alpha_an = A.alpha * an;
     uint32_t next = valid ? 0u : 0xffffffffu;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, pot = 0.0;
     uint32_t nint = 0;
@@ -130,55 +205,47 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
     while (c < A.E) {
         const uint32_t cu = __builtin_amdgcn_readfirstlane(c);
         const Rec64 r = R[cu];
-        bool desc = false;
-        if (next == cu) {
-            const double d0 = wrap64<PER>(r.com[0] - x0, A.box, A.half);
-            const double d1 = wrap64<PER>(r.com[1] - x1, A.box, A.half);
-            const double d2 = wrap64<PER>(r.com[2] - x2, A.box, A.half);
-            const double dd = fma(d0, d0, fma(d1, d1, d2 * d2));
-            if (r.meta & kParticleFlag) {
-                next = cu + 1u;
-                if (cu != self && (!TPM || dd < A.rc2)) {
-                    interact64<TPM, POT>(A, r.mass, d0, d1, d2, dd, a0, a1, a2, pot);
-                    nint++;
-                }
-            } else {
-                const double L = ldexp(A.L, -(int)(r.meta & 0xffu));
-                const double c0 = wrap64<PER>(r.cen[0] - x0, A.box, A.half);
-                const double c1 = wrap64<PER>(r.cen[1] - x1, A.box, A.half);
-                const double c2 = wrap64<PER>(r.cen[2] - x2, A.box, A.half);
-                bool discard = false;
-                if (TPM) {
-                    const double hl = 0.5 * L;
-                    double e0 = fabs(c0) - hl, e1 = fabs(c1) - hl, e2 = fabs(c2) - hl;
-                    e0 = e0 > 0.0 ? e0 : 0.0;
-                    e1 = e1 > 0.0 ? e1 : 0.0;
-                    e2 = e2 > 0.0 ? e2 : 0.0;
-                    discard = fma(e0, e0, fma(e1, e1, e2 * e2)) > A.rc2;
-                }
-                if (discard) {
-                    next = r.skip;
-                } else {
-                    bool open;
-                    if (OPEN == TPM_OPEN_BH)
-                        open = (L * L) > A.theta2 * dd;
-                    else
-                        open = (A.G * r.mass) * (L * L) > (A.alpha * an) * (dd * dd);
-                    const double lim = 0.6 * L;
-                    if (fabs(c0) < lim && fabs(c1) < lim && fabs(c2) < lim)
-                        open = true;
-                    if (open) {
-                        next = cu + 1u;
-                        desc = true;
-                    } else {
-                        interact64<TPM, POT>(A, r.mass, d0, d1, d2, dd, a0, a1, a2, pot);
-                        nint++;
-                        next = r.skip;
-                    }
-                }
+        const uint64_t mine = wave_mask(next == cu);
+        const double d0 = wrap64<PER>(r.com[0] - x0, A.box, A.half);
+        const double d1 = wrap64<PER>(r.com[1] - x1, A.box, A.half);
+        const double d2 = wrap64<PER>(r.com[2] - x2, A.box, A.half);
+        const double dd = fma(d0, d0, fma(d1, d1, d2 * d2));
+        uint64_t inter, desc;
+        if (r.meta & kParticleFlag) {
+            inter = mine & wave_mask((cu != self) && (!TPM || dd < A.rc2));
+            desc = 0;
+            next = lane_in(mine) ? cu + 1u : next;
+        } else {
+            const uint32_t lev = r.meta & 0xffu;
+            const double c0 = wrap64<PER>(r.cen[0] - x0, A.box, A.half);
+            const double c1 = wrap64<PER>(r.cen[1] - x1, A.box, A.half);
+            const double c2 = wrap64<PER>(r.cen[2] - x2, A.box, A.half);
+            uint64_t keep = ~0ull;
+            if (TPM) {
+                const double hl = scale_level(A.hlr, lev);
+                double e0 = fabs(c0) - hl, e1 = fabs(c1) - hl, e2 = fabs(c2) - hl;
+                e0 = e0 > 0.0 ? e0 : 0.0;
+                e1 = e1 > 0.0 ? e1 : 0.0;
+                e2 = e2 > 0.0 ? e2 : 0.0;
+                keep = wave_mask(!(fma(e0, e0, fma(e1, e1, e2 * e2)) > A.rc2));
             }
+            const double L2 = scale_level(scale_level(A.L2r, lev), lev);
+            bool crit;
+            if (OPEN == TPM_OPEN_BH)
+                crit = L2 > A.theta2 * dd;
+            else
+                crit = (A.G * r.mass) * L2 > alpha_an * (dd * dd);
+            const double lim = scale_level(A.limr, lev);
+            const bool box = fabs(c0) < lim && fabs(c1) < lim && fabs(c2) < lim;
+            const uint64_t open = keep & wave_mask(crit || box);
+            inter = mine & keep & ~open;
+            desc = mine & open;
+            next = lane_in(mine) ? (lane_in(open) ? cu + 1u : r.skip) : next;
         }
-        c = __ballot(desc) ? cu + 1u : r.skip;
+        if (inter)
+            interact64_wave<TPM, POT>(A, lane_in(inter), r.mass, d0, d1, d2, dd, a0, a1, a2, pot,
+                                      nint);
+        c = desc ? cu + 1u : r.skip;
     }
     if (valid) {
         double *res = (double *)A.res;
@@ -260,6 +327,73 @@ __device__ __forceinline__ int32_t wrapi(int32_t d) {
     return d;
 }
 
+__device__ __forceinline__ float spline_g32_sel(float u) {
+    const float u2 = u * u;
+    const float inner = fmaf(u2, fmaf(32.0f, u, -38.4f), 10.6666667f);
+    const float cubic = fmaf(fmaf(fmaf(-10.6666667f, u, 38.4f), u, -48.0f), u, 21.3333333f);
+    const float outer = cubic - __builtin_amdgcn_rcpf(15.0f * u * u * u);
+    return u < 0.5f ? inner : outer;
+}
+
+__device__ __forceinline__ float spline_phi32_sel(float u) {
+    const float u2 = u * u;
+    const float inner = fmaf(u2, fmaf(u2, fmaf(u, 6.4f, -9.6f), 5.33333333f), -2.8f);
+    const float outer =
+        fmaf(u2, fmaf(u, fmaf(u, fmaf(u, -2.13333333f, 9.6f), -16.0f), 10.6666667f), -3.2f) +
+        __builtin_amdgcn_rcpf(15.0f * u);
+    return u < 0.5f ? inner : outer;
+}
+
+// interact32 for the lanes with `inter` set, executed by the whole wavefront
+// (see interact64_wave); identical results for those lanes.
+template <bool TPM, bool POT>
+__device__ __forceinline__ void interact32_wave(const WalkArgs &A, bool inter, float gm, float d0,
+                                                float d1, float d2, float dd, float &a0,
+                                                float &a1, float &a2, float &pot,
+                                                uint32_t &nint) {
+    const float rinv = __builtin_amdgcn_rsqf(dd);
+    float fac = gm * rinv * rinv * rinv;
+    float phi = 0.0f, r = 0.0f;
+    if (POT)
+        phi = -gm * rinv;
+    if (TPM)
+        r = dd * rinv;
+    const bool soft = dd < A.fh2;
+    if (wave_mask(inter && soft)) {
+        const float rr = __builtin_amdgcn_sqrtf(dd);
+        const float u = rr * A.fhinv;
+        fac = soft ? (gm * A.fh3inv) * spline_g32_sel(u) : fac;
+        if (POT)
+            phi = soft ? (gm * A.fhinv) * spline_phi32_sel(u) : phi;
+        if (TPM)
+            r = soft ? rr : r;
+    }
+    if (TPM) {
+        const float x = r * A.finv2rs;
+        const float g = __builtin_amdgcn_exp2f(-(x * x) * 1.44269504f);
+        const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+        const float poly =
+            t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f),
+                             -0.284496736f),
+                     0.254829592f);
+        const float ec = poly * g;
+        fac *= fmaf(x * 1.12837917f, g, ec);
+        if (POT)
+            phi *= ec;
+    }
+    fac = inter ? fac : 0.0f;
+    a0 = fmaf(fac, d0, a0);
+    a1 = fmaf(fac, d1, a1);
+    a2 = fmaf(fac, d2, a2);
+    if (POT)
+        pot += inter ? phi : 0.0f;
+    nint += inter ? 1u : 0u;
+}
+
+__device__ __forceinline__ float scale_level32(float v, uint32_t lev) {
+    return __int_as_float(__float_as_int(v) - (int)(lev << 23));
+}
+
 template <bool PER, bool TPM, int OPEN, bool POT>
 __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     const int lane = threadIdx.x & 63;
@@ -289,60 +423,52 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, pot = 0.0f;
     uint32_t nint = 0;
     const Rec32 *__restrict__ R = (const Rec32 *)A.rec;
+    // level sizes follow from the root's by exponent arithmetic (exact; on
+    // the scalar unit, since the entry is wavefront-uniform)
     uint32_t c = 0;
     while (c < A.E) {
         const uint32_t cu = __builtin_amdgcn_readfirstlane(c);
         const Rec32 r = R[cu];
-        bool desc = false;
-        if (next == cu) {
-            const int32_t cm = r.cx_meta;
-            const float o0 = (float)wrapi<PER>((cm & 0x3fffff) - G0) * A.fu;
-            const float o1 = (float)wrapi<PER>(r.cy - G1) * A.fu;
-            const float o2 = (float)wrapi<PER>(r.cz - G2) * A.fu;
-            // target -> centre of the entry, and target -> centre of mass
-            const float c0 = o0 - xr0, c1 = o1 - xr1, c2 = o2 - xr2;
-            const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
-            const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-            if (cm & (1 << 27)) {
-                next = cu + 1u;
-                if (cu != self && (!TPM || dd < A.frc2)) {
-                    interact32<TPM, POT>(A, r.gm, d0, d1, d2, dd, a0, a1, a2, pot);
-                    nint++;
-                }
-            } else {
-                const float L = __builtin_amdgcn_ldexpf(A.fL, -((cm >> 22) & 31));
-                bool discard = false;
-                if (TPM) {
-                    const float hl = 0.5f * L;
-                    const float e0 = fmaxf(fabsf(c0) - hl, 0.0f);
-                    const float e1 = fmaxf(fabsf(c1) - hl, 0.0f);
-                    const float e2 = fmaxf(fabsf(c2) - hl, 0.0f);
-                    discard = fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) > A.frc2;
-                }
-                if (discard) {
-                    next = r.skip;
-                } else {
-                    const float L2 = L * L;
-                    bool open;
-                    if (OPEN == TPM_OPEN_BH)
-                        open = L2 > A.ftheta2 * dd;
-                    else
-                        open = r.gm * L2 > alpha_an * (dd * dd);
-                    const float lim = 0.6f * L;
-                    if (fabsf(c0) < lim && fabsf(c1) < lim && fabsf(c2) < lim)
-                        open = true;
-                    if (open) {
-                        next = cu + 1u;
-                        desc = true;
-                    } else {
-                        interact32<TPM, POT>(A, r.gm, d0, d1, d2, dd, a0, a1, a2, pot);
-                        nint++;
-                        next = r.skip;
-                    }
-                }
+        const uint64_t mine = wave_mask(next == cu);
+        const int32_t cm = r.cx_meta;
+        // target -> centre of the entry, and target -> centre of mass
+        const float c0 = fmaf((float)wrapi<PER>((cm & 0x3fffff) - G0), A.fu, -xr0);
+        const float c1 = fmaf((float)wrapi<PER>(r.cy - G1), A.fu, -xr1);
+        const float c2 = fmaf((float)wrapi<PER>(r.cz - G2), A.fu, -xr2);
+        const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
+        const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+        uint64_t inter, desc;
+        if (cm & (1 << 27)) {
+            inter = mine & wave_mask((cu != self) && (!TPM || dd < A.frc2));
+            desc = 0;
+            next = lane_in(mine) ? cu + 1u : next;
+        } else {
+            const uint32_t lev = ((uint32_t)cm >> 22) & 31u;
+            uint64_t keep = ~0ull;
+            if (TPM) {
+                const float hl = scale_level32(A.fhlr, lev);
+                const float e0 = fmaxf(fabsf(c0) - hl, 0.0f);
+                const float e1 = fmaxf(fabsf(c1) - hl, 0.0f);
+                const float e2 = fmaxf(fabsf(c2) - hl, 0.0f);
+                keep = wave_mask(!(fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) > A.frc2));
             }
+            const float L2 = scale_level32(scale_level32(A.fL2r, lev), lev);
+            bool crit;
+            if (OPEN == TPM_OPEN_BH)
+                crit = L2 > A.ftheta2 * dd;
+            else
+                crit = r.gm * L2 > alpha_an * (dd * dd);
+            const float lim = scale_level32(A.flimr, lev);
+            const bool box = fabsf(c0) < lim && fabsf(c1) < lim && fabsf(c2) < lim;
+            const uint64_t open = keep & wave_mask(crit || box);
+            inter = mine & keep & ~open;
+            desc = mine & open;
+            next = lane_in(mine) ? (lane_in(open) ? cu + 1u : r.skip) : next;
         }
-        c = __ballot(desc) ? cu + 1u : r.skip;
+        if (inter)
+            interact32_wave<TPM, POT>(A, lane_in(inter), r.gm, d0, d1, d2, dd, a0, a1, a2, pot,
+                                      nint);
+        c = desc ? cu + 1u : r.skip;
     }
     if (valid) {
         float *res = (float *)A.res;
@@ -801,7 +927,12 @@ static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
     A.res = c->res.p;
     A.rpot = c->rpot.p;
     A.rnint = (uint32_t *)c->rnint.p;
-
+    A.L2r = A.L * A.L;
+    A.limr = 0.6 * A.L;
+    A.hlr = 0.5 * A.L;
+    A.fL2r = A.fL * A.fL;
+    A.flimr = 0.6f * A.fL;
+    A.fhlr = 0.5f * A.fL;
 }
 
 int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const double *anorm,

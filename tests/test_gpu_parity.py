@@ -165,6 +165,41 @@ def test_fp64_forces_match_oracle(case):
     assert np.abs(pot.cpu().numpy() - po).max() <= 1e-10 * np.abs(po).max()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", sorted(FORCE_CASES))
+def test_walk_variants_identical(case, prec, monkeypatch):
+    """The shared-cursor walk and the independent-lane walk visit each
+    target's entries in the same depth-first order with the same arithmetic:
+    accelerations, potentials and interaction counts are bit-identical, on
+    the full set and on a sparse subset (ragged last wavefront)."""
+    mk, kw, opening = FORCE_CASES[case]
+    p = mk()
+    an = None
+    if opening == "rel":
+        c0 = _ctx(precision="fp64", **kw)
+        _build(c0, p)
+        a0, _ = c0.compute_forces(_t(np.arange(p.n), torch.int32), "bh")
+        an = torch.linalg.norm(a0, dim=0).contiguous()
+    sets = [np.arange(p.n), np.random.default_rng(17).choice(p.n, max(1, p.n // 7 + 5),
+                                                             replace=False)]
+    out = {}
+    for mode in ("1", "2"):
+        monkeypatch.setenv("TPM_WALK_MODE", mode)
+        ctx = _ctx(precision=prec, want_potential=True, **kw)
+        _build(ctx, p)
+        res = []
+        for ids in sets:
+            idx = _t(ids, torch.int32)
+            nint = torch.empty(ids.size, dtype=torch.int32, device=_dev())
+            acc, pot = ctx.compute_forces(idx, opening, a_old_norm=an, n_interactions=nint)
+            ctx.check()
+            res.append((acc.cpu(), pot.cpu(), nint.cpu()))
+        out[mode] = res
+    for k in range(len(sets)):
+        for a, b in zip(out["1"][k], out["2"][k]):
+            assert torch.equal(a, b), (case, prec, k)
+
+
 @pytest.mark.parametrize("case", ["plummer_bh", "plummer_rel", "box_bh", "box_clustered",
                                   "hernquist_bh"])
 def test_fp32_against_fp64(case):
