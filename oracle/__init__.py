@@ -93,6 +93,8 @@ class Lib:
         L.orc_cic_deposit.argtypes = [C.c_int64, _d, _d, _d, _d, C.c_double, C.c_int, _d]
         L.orc_pm.argtypes = [C.c_int64, _d, _d, _d, _d, C.c_double, C.c_int, C.c_double,
                              C.c_double, C.c_int64, _i64, _d, _d]
+        L.orc_pm_isolated.argtypes = [C.c_int64, _d, _d, _d, _d, _d, C.c_int, C.c_double,
+                                      C.c_double, C.c_int, C.c_int64, _i64, _d, _d]
         L.orc_ewald.argtypes = [C.c_int64, _d, _d, _d, _d, C.c_double, C.c_double,
                                 C.c_double, C.c_double, C.c_int64, _i64, _d]
         L.orc_max_threads.restype = C.c_int
@@ -291,4 +293,27 @@ def pm(x, y, z, mass, box, ng, G, rs, targets=None, want_pot=True):
     lib().L.orc_pm(x.size, _ptr(x, _d), _ptr(y, _d), _ptr(z, _d), _ptr(m, _d), float(box),
                    int(ng), float(G), float(rs), t.size, _ptr(t, _i64), _ptr(acc, _d),
                    _ptr(pot, _d))
+    return acc.reshape(3, t.size), pot
+
+
+def isolated_scale(L_root, ng, asmth):
+    """Mesh spacing and split scale of the isolated mesh: h = L / (ng - 4),
+    r_s = asmth h."""
+    h = float(L_root) / (int(ng) - 4)
+    return h, float(asmth) * h
+
+
+def pm_isolated(x, y, z, mass, frame4, ng, G, asmth, targets=None, want_pot=True,
+                deconv=True):
+    """Long-range force without periodicity (zero-padded (2 ng)^3 mesh over
+    the root cube ``frame4`` = (x0, y0, z0, L)); acc [3][nt], pot [nt]."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    m = None if mass is None else _f64(mass)
+    fr = _f64(frame4)
+    t = _targets(x.size, targets)
+    acc = np.empty(3 * t.size)
+    pot = np.empty(t.size) if want_pot else None
+    lib().L.orc_pm_isolated(x.size, _ptr(x, _d), _ptr(y, _d), _ptr(z, _d), _ptr(m, _d),
+                            _ptr(fr, _d), int(ng), float(G), float(asmth), int(bool(deconv)),
+                            t.size, _ptr(t, _i64), _ptr(acc, _d), _ptr(pot, _d))
     return acc.reshape(3, t.size), pot

@@ -18,6 +18,8 @@
  *   - particle-mesh long-range force: CIC, FFT Poisson
  *     solve with Gaussian filter and deconvolution,
  *     finite differences, interpolation                     (Sec. 3.3, 3.4)
+ *   - the same for isolated systems: zero-padded mesh and the
+ *     real-space long-range Green's function                (Sec. 3.3)
  * plus the exact references the method is judged against: direct O(N^2)
  * summation and an Ewald sum for periodic boxes (Sec. 3.1, Ewald paragraph).
  *
@@ -37,7 +39,9 @@
  *     factor is one minus that;
  *   - softened and truncated force = spline force x short-range factor;
  *   - fourth-order four-point finite differences; deconvolution by
- *     sinc^2 (assignment) x sinc^2 (interpolation) per axis.
+ *     sinc^2 (assignment) x sinc^2 (interpolation) per axis;
+ *   - isolated mesh: ng cells of h = L_root / (ng - 4) cover the root cube
+ *     with two spare cells per side, zero-padded to (2 ng)^3, r_s = asmth h.
  *
  * Floating point: compiled with -ffp-contract=off; fused multiply-adds are
  * written explicitly with fma() where the arithmetic contract uses them.
@@ -1086,6 +1090,147 @@ void orc_pm(int64_t n, const double *x, const double *y, const double *z,
     free(fx);
     free(fy);
     free(fz);
+}
+
+/* ------------------------------------------------------------------ */
+/* Particle-mesh long-range force without periodicity (Sec. 3.3: zero  */
+/* padding and a different Green's function).                          */
+/*                                                                     */
+/* The ng-cell mesh spans the root cube [x0, x0 + L) plus two cells on */
+/* each side: h = L / (ng - 4), mesh origin x0 - 2h.  It is embedded in */
+/* a (2 ng)^3 zero-padded mesh, so the circular convolution equals the */
+/* open one for every mesh point the difference stencil reads.  Green's */
+/* function: the long-range part of the point-mass potential,          */
+/*   G_l(r) = -G erf(r / 2 r_s) / r,  G_l(0) = -G / (sqrt(pi) r_s),     */
+/* sampled at the signed mesh offsets, transformed, and divided by the  */
+/* CIC deconvolution prod_a sinc^4(k_a h / 2) (as in the periodic case).*/
+/* Masses (not densities) are deposited, so                            */
+/*   Phi = IFFT(FFT(M) FFT(G_l) / deconv) / (2 ng)^3.                   */
+/* deconv = 0 skips the deconvolution (a test hook).                   */
+/* ------------------------------------------------------------------ */
+static double isolated_kernel(double r, double G, double rs)
+{
+    if (r == 0.0)
+        return -G / (sqrt(M_PI) * rs);
+    return -G * erf(r * (0.5 / rs)) / r;
+}
+
+void orc_pm_isolated(int64_t n, const double *x, const double *y, const double *z,
+                     const double *mass, const double *frame /* x0, y0, z0, L */, int ng,
+                     double G, double asmth, int deconv, int64_t nt, const int64_t *targets,
+                     double *acc, double *pot)
+{
+    const int M = 2 * ng;
+    const int64_t M3 = (int64_t)M * M * M;
+    const double h = frame[3] / (ng - 4);
+    const double rs = asmth * h;
+    const double lo[3] = {frame[0] - 2.0 * h, frame[1] - 2.0 * h, frame[2] - 2.0 * h};
+    double *re = (double *)calloc((size_t)M3, sizeof(double));
+    double *im = (double *)calloc((size_t)M3, sizeof(double));
+    double *gre = (double *)calloc((size_t)M3, sizeof(double));
+    double *gim = (double *)calloc((size_t)M3, sizeof(double));
+    /* 1. CIC deposit of the masses */
+    const double *c[3] = {x, y, z};
+    for (int64_t p = 0; p < n; p++) {
+        int i0[3];
+        double w[3];
+        for (int a = 0; a < 3; a++) {
+            double f = (c[a][p] - lo[a]) / h;
+            double fl = floor(f);
+            w[a] = f - fl;
+            i0[a] = (int)fl;
+        }
+        double m = mass ? mass[p] : 1.0 / (double)n;
+        for (int s = 0; s < 8; s++) {
+            double wt = 1.0;
+            int t[3];
+            for (int a = 0; a < 3; a++) {
+                int up = (s >> (2 - a)) & 1;
+                wt *= up ? w[a] : 1.0 - w[a];
+                t[a] = i0[a] + up;
+            }
+            re[((int64_t)t[0] * M + t[1]) * M + t[2]] += m * wt;
+        }
+    }
+    /* 2. Green's function at the signed offsets of the padded mesh */
+    for (int i = 0; i < M; i++)
+        for (int j = 0; j < M; j++)
+            for (int k = 0; k < M; k++) {
+#if ORC_MUTATION == 11
+                int o[3] = {i, j, k};
+#else
+                int o[3] = {i < ng ? i : i - M, j < ng ? j : j - M, k < ng ? k : k - M};
+#endif
+                double r = h * sqrt((double)o[0] * o[0] + (double)o[1] * o[1] +
+                                    (double)o[2] * o[2]);
+                gre[((int64_t)i * M + j) * M + k] = isolated_kernel(r, G, rs);
+            }
+    /* 3. forward transforms, product, deconvolution */
+    orc_fft3(M, re, im, -1);
+    orc_fft3(M, gre, gim, -1);
+    for (int i = 0; i < M; i++)
+        for (int j = 0; j < M; j++)
+            for (int k = 0; k < M; k++) {
+                int64_t q = ((int64_t)i * M + j) * M + k;
+                int nn[3] = {i < ng ? i : i - M, j < ng ? j : j - M, k < ng ? k : k - M};
+                double dc = 1.0;
+                if (deconv)
+                    for (int a = 0; a < 3; a++) {
+                        double sarg = M_PI * nn[a] / M; /* k_a h / 2 */
+                        double sc = nn[a] == 0 ? 1.0 : sin(sarg) / sarg;
+                        dc *= sc * sc * sc * sc;
+                    }
+                double ar = re[q], ai = im[q];
+                re[q] = (ar * gre[q] - ai * gim[q]) / dc;
+                im[q] = (ar * gim[q] + ai * gre[q]) / dc;
+            }
+    free(gre);
+    free(gim);
+    /* 4. inverse transform */
+    orc_fft3(M, re, im, +1);
+    for (int64_t q = 0; q < M3; q++)
+        re[q] /= (double)M3;
+    free(im);
+    double *phi = re;
+    /* 5. four-point difference at the mesh points and 6. CIC interpolation */
+#pragma omp parallel for schedule(static)
+    for (int64_t kk = 0; kk < nt; kk++) {
+        int64_t p = targets[kk];
+        int i0[3];
+        double w[3];
+        for (int a = 0; a < 3; a++) {
+            double f = (c[a][p] - lo[a]) / h;
+            double fl = floor(f);
+            w[a] = f - fl;
+            i0[a] = (int)fl;
+        }
+        double F[3] = {0.0, 0.0, 0.0}, P = 0.0;
+        for (int s = 0; s < 8; s++) {
+            double wt = 1.0;
+            int t[3];
+            for (int a = 0; a < 3; a++) {
+                int up = (s >> (2 - a)) & 1;
+                wt *= up ? w[a] : 1.0 - w[a];
+                t[a] = i0[a] + up;
+            }
+            for (int a = 0; a < 3; a++) {
+                double v[5];
+                for (int st = -2; st <= 2; st++) {
+                    int u[3] = {t[0], t[1], t[2]};
+                    u[a] += st;
+                    v[st + 2] = phi[((int64_t)u[0] * M + u[1]) * M + u[2]];
+                }
+                double grad = ((2.0 / 3.0) * (v[3] - v[1]) - (1.0 / 12.0) * (v[4] - v[0])) / h;
+                F[a] += wt * -grad;
+            }
+            P += wt * phi[((int64_t)t[0] * M + t[1]) * M + t[2]];
+        }
+        for (int a = 0; a < 3; a++)
+            acc[a * nt + kk] = F[a];
+        if (pot)
+            pot[kk] = P;
+    }
+    free(re);
 }
 
 /* ------------------------------------------------------------------ */

@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_keys as K
+from tests import test_oracle_isolated as ISO
 from tests import test_oracle_kernels as KN
 from tests import test_oracle_pm as PM
 from tests import test_oracle_tree as TR
@@ -32,6 +33,8 @@ MUTATIONS = {
     9: ("geometric criterion with theta instead of theta^2",
         [lambda o: WK.test_plummer_config_accuracy(o)]),
     10: ("CIC weights swapped", [lambda o: PM.test_cic_mass_and_linear(o)]),
+    11: ("isolated Green's function sampled at unsigned mesh offsets",
+         [lambda o: ISO.test_isolated_solve_is_open_convolution(o)]),
 }
 
 
