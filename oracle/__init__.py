@@ -85,8 +85,9 @@ class Lib:
         L.orc_tree_free.argtypes = [C.c_void_p]
         L.orc_tree_walk.argtypes = [C.c_void_p, _P(OrcParams), C.c_int64, _i64, _d, _d, _d,
                                     _i64]
-        L.orc_direct.argtypes = [C.c_int64, _d, _d, _d, _d, _P(OrcParams), C.c_int64, _i64,
-                                 _d, _d]
+        L.orc_direct.argtypes = [C.c_int64, _d, _d, _d, _d, _d, _P(OrcParams), C.c_int64,
+                                 _i64, _d, _d]
+        L.orc_tree_set_softening.argtypes = [C.c_void_p, _d]
         L.orc_fft3.argtypes = [C.c_int, _d, _d, C.c_int]
         L.orc_pm_mesh.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _d, _d, _d,
                                   _d, _d]
@@ -174,7 +175,7 @@ class Tree:
     """Insertion-built octree with its canonical depth-first entry list."""
 
     def __init__(self, x, y, z, mass=None, periodic=False, box=0.0,
-                 shift=(0.0, 0.0, 0.0), insert_order=None):
+                 shift=(0.0, 0.0, 0.0), insert_order=None, eps=None):
         self.x, self.y, self.z = _f64(x), _f64(y), _f64(z)
         self.n = self.x.size
         self.mass = None if mass is None else _f64(mass)
@@ -189,6 +190,9 @@ class Tree:
         self.E = L.orc_tree_entries(self.h)
         self.frame = np.empty(4)
         L.orc_tree_frame(self.h, _ptr(self.frame, _d))
+        if eps is not None:  # individual softening lengths (Sec. 3.2)
+            self.eps = _f64(eps)
+            L.orc_tree_set_softening(self.h, _ptr(self.eps, _d))
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -234,14 +238,18 @@ class Tree:
 
 # ---- exact references ---------------------------------------------------
 
-def direct(x, y, z, mass, params: OrcParams, targets=None):
+def direct(x, y, z, mass, params: OrcParams, targets=None, eps=None):
+    """Direct pair sum; ``eps`` gives individual softening lengths (a pair
+    uses the larger), else params.eps for all."""
     x, y, z = _f64(x), _f64(y), _f64(z)
     m = None if mass is None else _f64(mass)
+    e = None if eps is None else _f64(eps)
     t = _targets(x.size, targets)
     acc = np.empty(3 * t.size)
     pot = np.empty(t.size)
     lib().L.orc_direct(x.size, _ptr(x, _d), _ptr(y, _d), _ptr(z, _d), _ptr(m, _d),
-                       C.byref(params), t.size, _ptr(t, _i64), _ptr(acc, _d), _ptr(pot, _d))
+                       _ptr(e, _d), C.byref(params), t.size, _ptr(t, _i64), _ptr(acc, _d),
+                       _ptr(pot, _d))
     return acc.reshape(3, t.size), pot
 
 

@@ -41,7 +41,11 @@
  *   - fourth-order four-point finite differences; deconvolution by
  *     sinc^2 (assignment) x sinc^2 (interpolation) per axis;
  *   - isolated mesh: ng cells of h = L_root / (ng - 4) cover the root cube
- *     with two spare cells per side, zero-padded to (2 ng)^3, r_s = asmth h.
+ *     with two spare cells per side, zero-padded to (2 ng)^3, r_s = asmth h;
+ *   - individual softening: spline supports 2.8 eps_i, a pair uses the larger,
+ *     a node carries the largest of its particles and, when that exceeds the
+ *     target's, is opened for distances to its centre of mass below it and
+ *     otherwise interacts with the larger of the target's and its own.
  *
  * Floating point: compiled with -ffp-contract=off; fused multiply-adds are
  * written explicitly with fma() where the arithmetic contract uses them.
@@ -260,6 +264,9 @@ typedef struct orc_tree {
     double *emass, *com, *cen; /* com, cen: [a*Ecap + e] */
     int64_t *entry_of; /* particle index -> its entry */
     int64_t nemitted;  /* particles emitted so far */
+    /* individual softening (Sec. 3.2), NULL when all particles share eps:
+     * hsoft[i] = 2.8 eps_i, eh[e] = largest hsoft in entry e */
+    double *hsoft, *eh;
 } orc_tree;
 
 static int32_t new_inode(orc_tree *T, int level, const uint32_t corner[3])
@@ -551,10 +558,34 @@ void orc_tree_positions(const orc_tree *T, double *p, uint32_t *q, uint64_t *key
         memcpy(key, T->key, (size_t)n * sizeof(uint64_t));
 }
 
+/* Individual softening lengths (Sec. 3.2): each entry carries the largest
+ * spline support of the particles it holds (a particle its own). */
+void orc_tree_set_softening(orc_tree *T, const double *eps)
+{
+    free(T->hsoft);
+    free(T->eh);
+    T->hsoft = (double *)malloc((size_t)T->n * sizeof(double));
+    T->eh = (double *)malloc((size_t)T->E * sizeof(double));
+    for (int64_t i = 0; i < T->n; i++)
+        T->hsoft[i] = 2.8 * eps[i];
+    for (int64_t e = T->E - 1; e >= 0; e--) { /* children follow their node */
+        if (T->level[e] < 0) {
+            T->eh[e] = T->hsoft[T->pidx[e]];
+            continue;
+        }
+        double m = 0.0;
+        for (int64_t k = e + 1; k < T->skip[e]; k = T->skip[k])
+            m = T->eh[k] > m ? T->eh[k] : m;
+        T->eh[e] = m;
+    }
+}
+
 void orc_tree_free(orc_tree *T)
 {
     if (!T)
         return;
+    free(T->hsoft);
+    free(T->eh);
     free(T->p);
     free(T->q);
     free(T->key);
@@ -687,6 +718,7 @@ typedef struct {
     double x[3];
     double anorm;
     double h, hinv, h3inv, rc2;
+    double hself; /* the target's own spline support */
     double acc[3];
     double pot;
     int64_t nint;
@@ -706,7 +738,17 @@ static void visit(walk_state *W, int64_t e)
             return;
         if (P->treepm && !(d2 < W->rc2))
             return;
-        interact(P, W->h, W->hinv, W->h3inv, T->emass[e], d, d2, W->acc, &W->pot);
+        if (T->eh) { /* pair softening: the larger of the two (Sec. 3.2) */
+#if ORC_MUTATION == 12
+            double h = W->hself;
+#else
+            double h = W->hself > T->eh[e] ? W->hself : T->eh[e];
+#endif
+            double hinv = 1.0 / h;
+            interact(P, h, hinv, hinv * hinv * hinv, T->emass[e], d, d2, W->acc, &W->pot);
+        } else {
+            interact(P, W->h, W->hinv, W->h3inv, T->emass[e], d, d2, W->acc, &W->pot);
+        }
         W->nint++;
         return;
     }
@@ -740,12 +782,24 @@ static void visit(walk_state *W, int64_t e)
     if (fabs(dc[0]) < lim && fabs(dc[1]) < lim && fabs(dc[2]) < lim)
         open = 1;
 #endif
+    /* a node holding larger softenings than the target's is opened when the
+     * target lies within that softening of its centre of mass (Sec. 3.2) */
+#if ORC_MUTATION != 13
+    if (T->eh && W->hself < T->eh[e] && d2 < T->eh[e] * T->eh[e])
+        open = 1;
+#endif
     if (open) {
         for (int64_t k = e + 1; k < T->skip[e]; k = T->skip[k])
             visit(W, k);
         return;
     }
-    interact(P, W->h, W->hinv, W->h3inv, T->emass[e], d, d2, W->acc, &W->pot);
+    if (T->eh) {
+        double h = W->hself > T->eh[e] ? W->hself : T->eh[e];
+        double hinv = 1.0 / h;
+        interact(P, h, hinv, hinv * hinv * hinv, T->emass[e], d, d2, W->acc, &W->pot);
+    } else {
+        interact(P, W->h, W->hinv, W->h3inv, T->emass[e], d, d2, W->acc, &W->pot);
+    }
     W->nint++;
 }
 
@@ -772,6 +826,7 @@ void orc_tree_walk(const orc_tree *T, const orc_params *P, int64_t nt,
         W.h = h;
         W.hinv = hinv;
         W.h3inv = h3inv;
+        W.hself = T->hsoft ? T->hsoft[i] : h;
         W.rc2 = rc2;
         W.acc[0] = W.acc[1] = W.acc[2] = 0.0;
         W.pot = 0.0;
@@ -792,10 +847,10 @@ void orc_tree_walk(const orc_tree *T, const orc_params *P, int64_t nt,
 /* part of the nearest image inside the cutoff.                        */
 /* ------------------------------------------------------------------ */
 void orc_direct(int64_t n, const double *x, const double *y, const double *z,
-                const double *mass, const orc_params *P, int64_t nt,
-                const int64_t *targets, double *acc, double *pot)
+                const double *mass, const double *eps /* per particle or NULL */,
+                const orc_params *P, int64_t nt, const int64_t *targets, double *acc,
+                double *pot)
 {
-    double h = 2.8 * P->eps;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < nt; k++) {
         int64_t i = targets[k];
@@ -811,6 +866,8 @@ void orc_direct(int64_t n, const double *x, const double *y, const double *z,
             if (P->treepm && r >= P->rcut)
                 continue;
             double m = mass ? mass[j] : 1.0 / (double)n;
+            /* individual softening: symmetrised by the larger one (Sec. 3.2) */
+            double h = 2.8 * (eps ? (eps[i] > eps[j] ? eps[i] : eps[j]) : P->eps);
             double f, phi;
             double u = r / h;
             if (u >= 1.0) {

@@ -13,6 +13,7 @@ from tests import test_oracle_keys as K
 from tests import test_oracle_isolated as ISO
 from tests import test_oracle_kernels as KN
 from tests import test_oracle_pm as PM
+from tests import test_oracle_softening_mixed as MS
 from tests import test_oracle_tree as TR
 from tests import test_oracle_walk as WK
 
@@ -35,6 +36,10 @@ MUTATIONS = {
     10: ("CIC weights swapped", [lambda o: PM.test_cic_mass_and_linear(o)]),
     11: ("isolated Green's function sampled at unsigned mesh offsets",
          [lambda o: ISO.test_isolated_solve_is_open_convolution(o)]),
+    12: ("pair softening from the target alone",
+         [lambda o: MS.test_open_all_equals_direct_mixed(o, False)]),
+    13: ("no opening of nodes with larger softening",
+         [lambda o: MS.test_softening_node_rule(o)]),
 }
 
 
