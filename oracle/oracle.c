@@ -1164,7 +1164,19 @@ void orc_pm(int64_t n, const double *x, const double *y, const double *z,
 /* Masses (not densities) are deposited, so                            */
 /*   Phi = IFFT(FFT(M) FFT(G_l) / deconv) / (2 ng)^3.                   */
 /* deconv = 0 skips the deconvolution (a test hook).                   */
+/* Mesh indices are taken modulo 2 ng (the padded transform is         */
+/* circular): a particle on the lower face of the root cube may round   */
+/* into cell 1, and its stencil then reads index -1, which the spare    */
+/* cells keep free of wrapped images.                                   */
 /* ------------------------------------------------------------------ */
+static int64_t pad_index(int M, int i, int j, int k)
+{
+    i = ((i % M) + M) % M;
+    j = ((j % M) + M) % M;
+    k = ((k % M) + M) % M;
+    return ((int64_t)i * M + j) * M + k;
+}
+
 static double isolated_kernel(double r, double G, double rs)
 {
     if (r == 0.0)
@@ -1206,7 +1218,7 @@ void orc_pm_isolated(int64_t n, const double *x, const double *y, const double *
                 wt *= up ? w[a] : 1.0 - w[a];
                 t[a] = i0[a] + up;
             }
-            re[((int64_t)t[0] * M + t[1]) * M + t[2]] += m * wt;
+            re[pad_index(M, t[0], t[1], t[2])] += m * wt;
         }
     }
     /* 2. Green's function at the signed offsets of the padded mesh */
@@ -1275,12 +1287,12 @@ void orc_pm_isolated(int64_t n, const double *x, const double *y, const double *
                 for (int st = -2; st <= 2; st++) {
                     int u[3] = {t[0], t[1], t[2]};
                     u[a] += st;
-                    v[st + 2] = phi[((int64_t)u[0] * M + u[1]) * M + u[2]];
+                    v[st + 2] = phi[pad_index(M, u[0], u[1], u[2])];
                 }
                 double grad = ((2.0 / 3.0) * (v[3] - v[1]) - (1.0 / 12.0) * (v[4] - v[0])) / h;
                 F[a] += wt * -grad;
             }
-            P += wt * phi[((int64_t)t[0] * M + t[1]) * M + t[2]];
+            P += wt * phi[pad_index(M, t[0], t[1], t[2])];
         }
         for (int a = 0; a < 3; a++)
             acc[a * nt + kk] = F[a];
