@@ -75,7 +75,7 @@ def workload(cfg):
     return c, p, kw
 
 
-def run_gpu(p, kw, prec, steps, warmup):
+def run_gpu(p, kw, prec, steps, warmup, eps=None):
     import torch
     from paper_1909_04667_amd import binding as B
     dev = torch.device("cuda:0")
@@ -91,14 +91,14 @@ def run_gpu(p, kw, prec, steps, warmup):
     anorm = torch.zeros(n, dtype=torch.float64, device=dev)
     nint_bh = torch.empty(n, dtype=torch.int32, device=dev)
     nint = torch.empty(n, dtype=torch.int32, device=dev)
-    periodic = bool(kw.get("periodic"))
+    has_pm = kw.get("pm_grid", 0) > 0
 
     def step():
-        ctx.build_tree(x, y, z)
-        if periodic:
+        ctx.build_tree(x, y, z, eps=eps)
+        if has_pm:
             ctx.pm_long_range(idx, acc=acc_pm)
         ctx.compute_forces(idx, "bh", acc=acc_bh, n_interactions=nint_bh)
-        ctx.accel_norm(idx, acc_bh, acc_pm if periodic else None, out=anorm)
+        ctx.accel_norm(idx, acc_bh, acc_pm if has_pm else None, out=anorm)
         ctx.compute_forces(idx, "rel", a_old_norm=anorm, acc=acc, n_interactions=nint)
 
     for _ in range(warmup):
@@ -123,7 +123,7 @@ def run_gpu(p, kw, prec, steps, warmup):
     ctx.check()
     inter_bh = int(nint_bh.to(torch.int64).sum())
     inter_rel = int(nint.to(torch.int64).sum())
-    total = (acc + acc_pm) if periodic else acc
+    total = (acc + acc_pm) if has_pm else acc
     out = dict(prec=prec, ms_per_step=sum(per_step) / steps, per_step=per_step, wall=wall,
                timers=timers, inter_bh=inter_bh, inter_rel=inter_rel, n=n,
                acc=total.double().cpu(), entries=ctx.tree_info()[1])
@@ -192,6 +192,78 @@ def run_local_timestep(steps, prec="fp32"):
                                    idx.numel() / ((ms + build_ms + solve_ms) * 1e-3)}
     ctx.check()
     ctx.close()
+    return out
+
+
+def run_isolated(steps, warmup, pm_grid=128):
+    """TreePM for an isolated system (Sec. 3.3 zero-padded mesh): the
+    Hernquist 2^20 sphere with a pm_grid mesh over its root cube, padded to
+    (2 pm_grid)^3; the same step as the headline (build, PM, BH, |a|,
+    relative), FP32 and FP64."""
+    c, p, kw = workload(2)
+    kw = dict(kw, pm_grid=pm_grid, asmth=1.25, rcut=4.5)
+    out = {"workload": f"{c['name']}_isolated_pm{pm_grid}", "n_particles": p.n,
+           "pm_grid": pm_grid, "padded_fft": 2 * pm_grid}
+    for prec in ("fp32", "fp64"):
+        r = run_gpu(p, kw, prec, steps, warmup)
+        t = r["timers"]
+        out[prec] = {"ms_per_step": r["ms_per_step"],
+                     "force_evals_per_s": r["n"] / (r["ms_per_step"] * 1e-3),
+                     "kernel_ms": {k: t[k][0] / max(t[k][1], 1) for k in
+                                   ("walk", "walk_rel", "build", "pm_solve", "pm_interp")},
+                     "interactions_per_particle_rel": r["inter_rel"] / r["n"]}
+    return out
+
+
+def run_mixed_softening(steps, warmup):
+    """Individual softening lengths (Sec. 3.2) on the Hernquist 2^20 step
+    (build, BH, |a|, relative walk): log-normal spread around eps, against
+    the uniform-softening step on the same positions."""
+    import numpy as np
+    import torch
+    c, p, kw = workload(2)
+    eps_arr = kw["eps"] * np.exp(np.random.default_rng(21).normal(0.0, 0.7, p.n))
+    out = {"workload": f"{c['name']}_individual_softening", "n_particles": p.n,
+           "eps_spread": "log-normal, sigma 0.7 (natural log)"}
+    for prec in ("fp32", "fp64"):
+        r = run_gpu(p, kw, prec, steps, warmup,
+                    eps=torch.as_tensor(eps_arr, dtype=torch.float64, device="cuda:0"))
+        out[prec] = {"ms_per_step": r["ms_per_step"],
+                     "force_evals_per_s": r["n"] / (r["ms_per_step"] * 1e-3),
+                     "interactions_per_particle_rel": r["inter_rel"] / r["n"]}
+    return out
+
+
+def run_integrators():
+    """Sec. 7.2-7.3 on a 2^18 Hernquist sphere: one longest step dt_max of the
+    block-step leapfrog and of the split-Hamiltonian integration, FP32 walks,
+    time-step parameter C = 0.025 with six bins."""
+    import numpy as np
+    import torch
+    from paper_1909_04667_amd import integrate as GI
+    from paper_1909_04667_amd import workloads as W
+    p = W.hernquist(1 << 18, 31)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    rng = np.random.default_rng(32)
+    r = np.sqrt(p.x ** 2 + p.y ** 2 + p.z ** 2)
+    vc = np.sqrt(r) / (1.0 + r)  # circular speed of a Hernquist sphere (G = M = a = 1)
+    v = rng.normal(0.0, 1.0, (3, p.n)) * (vc / np.sqrt(3.0))
+    out = {"workload": "hernquist_2p18_kdk", "n_particles": p.n, "C": 0.025,
+           "dt_max": 0.05, "max_bin": 6}
+    for name, cls in (("block_leapfrog", GI.BlockLeapfrog), ("hierarchical", GI.Hierarchical)):
+        integ = cls((t(p.x), t(p.y), t(p.z)), (t(v[0]), t(v[1]), t(v[2])), C=0.025,
+                    dt_max=0.05, max_bin=6, precision="fp32", eps=0.005)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = integ.run(1)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        occ = np.bincount(integ.bins.cpu().numpy(), minlength=7).tolist()
+        out[name] = {"wall_ms": wall * 1e3, "force_evals": st["force_evals"],
+                     "force_evals_per_s": st["force_evals"] / wall, "final_bins": occ,
+                     **{k: v for k, v in st.items() if k != "force_evals"}}
+        integ.ctx.close()
     return out
 
 
@@ -389,6 +461,12 @@ def main():
     if not args.no_extra:
         log("local time-stepping workload (256^3 clustered box)")
         line["local_timestep"] = run_local_timestep(max(3, args.steps // 2))
+        log("isolated TreePM (Hernquist 2^20, zero-padded mesh)")
+        line["isolated_treepm"] = run_isolated(max(3, args.steps // 2), 2)
+        log("individual softening (Hernquist 2^20)")
+        line["mixed_softening"] = run_mixed_softening(max(3, args.steps // 2), 2)
+        log("time integration (block steps, hierarchical split)")
+        line["integration"] = run_integrators()
         log("serving stream")
         line["serving"] = run_serving()
     if not args.no_cpu:

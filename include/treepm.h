@@ -18,12 +18,20 @@
  *   tpm_pm_long_range   Sec. 3.3/3.4  CIC deposit, FFT Poisson solve with the
  *                                 long-range Gaussian filter and CIC
  *                                 deconvolution, four-point finite difference,
- *                                 CIC interpolation
+ *                                 CIC interpolation; periodic boxes, or
+ *                                 isolated systems on a zero-padded mesh
+ *   tpm_build_tree_eps  Sec. 3.2  individual softening lengths
+ *   tpm_kick, tpm_drift, tpm_time_bins, tpm_select_bins, tpm_gather
+ *                       Sec. 7    leapfrog with power-of-two time bins and
+ *                                 the split-Hamiltonian variant
+ *   tpm_batch_*         many systems' walks in one persistent launch
  *
  * Conventions for every entry point:
  *   - All particle arrays are DEVICE pointers (HIP global memory), borrowed
  *     for the duration of the stream work the call enqueues; the library never
- *     frees or writes caller inputs.  Outputs are written by kernels on the
+ *     frees or writes caller inputs (the integration kernels update the
+ *     velocity, position and bin arrays they are given).  Outputs are
+ *     written by kernels on the
  *     context's stream; they are valid once that stream has reached the call.
  *   - Returns TPM_OK (0) or a negative error code.  Arguments are validated on
  *     the host before anything is enqueued: on an error no output is written.
@@ -61,13 +69,20 @@ typedef struct tpm_params {
     int32_t periodic;       /* 1: periodic cube of side box_size (requires pm_grid > 0) */
     int32_t precision;      /* TPM_FP64 or TPM_FP32 (walk and mesh arithmetic) */
     int32_t want_potential; /* 1: compute potentials too */
-    int32_t pm_grid;        /* PM mesh cells per side (power of two, 8..1024); 0: no PM */
+    int32_t pm_grid;        /* PM mesh cells per side; 0: no PM.  Periodic: power of two,
+                               8..1024, the mesh tiles the box.  Isolated (periodic == 0,
+                               Sec. 3.3 zero padding): power of two, 16..256; the mesh
+                               spans the root cube in pm_grid - 4 cells with two spare
+                               cells per side and is transformed zero-padded at
+                               (2 pm_grid)^3 */
     double box_size;        /* periodic box side (ignored when periodic == 0) */
     double G;               /* gravitational constant (> 0) */
     double eps;             /* softening length; spline support 2.8 eps (> 0) */
     double theta;           /* ErrTolTheta (>= 0) */
     double alpha;           /* ErrTolForceAcc (> 0) */
-    double asmth;           /* ASMTH: r_s = asmth * box_size / pm_grid (> 0 with PM) */
+    double asmth;           /* ASMTH: r_s = asmth * mesh spacing (> 0 with PM): periodic
+                               box_size / pm_grid, isolated L_root / (pm_grid - 4) with
+                               L_root the root cube of the last build */
     double rcut;            /* RCUT: short-range cutoff r_cut = rcut * r_s (> 0 with PM) */
     double shift[3];        /* root placement in [0,1)^3: non-periodic, fraction of the
                                slack of the power-of-two root cube; periodic, box shift
@@ -111,6 +126,20 @@ int64_t tpm_bytes_held(const tpm_ctx *ctx);
 int tpm_build_tree(tpm_ctx *ctx, int64_t n, const double *x, const double *y,
                    const double *z, const double *mass);
 
+/* As tpm_build_tree, with an individual softening length per particle
+ * (Sec. 3.2: softening set per particle or per type).
+ * eps: device double[n] (> 0, finite; build order), or NULL for params.eps
+ *      for all (then identical to tpm_build_tree).
+ * A pair interacts with the larger of its two spline supports 2.8 eps; every
+ * tree entry carries the largest support of its particles; a node whose
+ * support exceeds the target's is opened when the target lies within that
+ * support of the node's centre of mass, and otherwise interacts with the
+ * larger of the two supports.  A non-positive or non-finite value is found
+ * during the build: TPM_EINVAL, no tree.  The setting holds until the next
+ * build. */
+int tpm_build_tree_eps(tpm_ctx *ctx, int64_t n, const double *x, const double *y,
+                       const double *z, const double *mass, const double *eps);
+
 /* Tree force on the active particles (Sec. 3.1, 3.2, 3.4).
  * opening:     TPM_OPEN_BH or TPM_OPEN_REL.
  * n_act:       number of active particles (>= 0).
@@ -130,9 +159,13 @@ int tpm_compute_forces(tpm_ctx *ctx, int32_t opening, int64_t n_act, const int32
                        uint32_t *n_interactions);
 
 /* Long-range PM acceleration at the active particles (Sec. 3.3, 3.4).
- * Requires pm_grid > 0 and a periodic box (else TPM_EINVAL).  The mesh is
- * solved from ALL particles of the last build on first use after that build
- * and cached; every call interpolates.  acc: device [3][n_act], pot: device
+ * Requires pm_grid > 0 (else TPM_EINVAL).  Periodic box: Green's function
+ * -4 pi G exp(-k^2 r_s^2) / k^2, mean density removed.  Isolated system:
+ * zero-padded mesh, Green's function = the transform of the sampled
+ * long-range kernel -G erf(r / 2 r_s) / r (built once per context).  Both
+ * divide by the CIC deconvolution.  The mesh is solved from ALL particles
+ * of the last build on first use after that build and cached; every call
+ * interpolates.  acc: device [3][n_act], pot: device
  * [n_act] or NULL, dtype as in tpm_compute_forces.  Does not synchronise. */
 int tpm_pm_long_range(tpm_ctx *ctx, int64_t n_act, const int32_t *active_idx, void *acc,
                       void *pot);
@@ -211,6 +244,57 @@ int tpm_batch_add(tpm_batch *batch, tpm_ctx *ctx, int32_t opening, int64_t n_act
  * stage.  Does not synchronise (except to reuse its pinned staging table
  * after the previous launch). */
 int tpm_batch_launch(tpm_batch *batch);
+
+/* ---- time integration (Sec. 7.1-7.3) --------------------------------------
+ *
+ * Kernels for a leapfrog driver with the power-of-two time-step hierarchy
+ * (Sec. 7.2) and the split-Hamiltonian variant (Sec. 7.3).  They run on the
+ * context's stream and use its error word for out-of-range indices (reported
+ * by tpm_check); positions, velocities, bins and indices are caller-owned
+ * device arrays of the n particles in build order.  FP64 arithmetic, products
+ * rounded before sums: a kick is v + a dt, a drift x + v dt. */
+
+/* Kick: v[idx[k]] += (acc[k] + b_sign acc_b[k]) * h for k < n_act, with
+ * h = 0.5 dt_max 2^-bins[idx[k]] (half the particle's step) if bins is not
+ * NULL, else h = dt.  acc, acc_b: device [3][n_act] of the given precision
+ * (acc_b may be NULL; b_sign = +1 adds it, e.g. the PM force, -1 subtracts
+ * it, e.g. a part's own force to leave the mutual one). */
+int tpm_kick(tpm_ctx *ctx, int64_t n, int64_t n_act, const int32_t *idx, int32_t precision,
+             const void *acc, const void *acc_b, int32_t b_sign, const int32_t *bins,
+             double dt_max, double dt, double *vx, double *vy, double *vz);
+
+/* Drift: x[i] += v[i] dt for i = idx[k] (k < n_act), or for i < n_act when
+ * idx is NULL; box > 0 folds the result back into [0, box) by one length. */
+int tpm_drift(tpm_ctx *ctx, int64_t n, int64_t n_act, const int32_t *idx, double *x,
+              double *y, double *z, const double *vx, const double *vy, const double *vz,
+              double dt, double box);
+
+/* Time bins (Sec. 7.1, 7.2) of the listed particles from their acceleration
+ * acc (+ acc_b, may be NULL): the largest step dt_max 2^-b, b <= max_bin, not
+ * above sqrt(2 C eps / |a|) (eps[i], or eps0 when eps is NULL); a step longer
+ * than the current bins[i] only if the tick t (in units of dt_max 2^-max_bin)
+ * is a multiple of it, else the longest such step.  Writes bins[i]; adds the
+ * count of each new bin to hist[0..max_bin] (device uint32, caller-zeroed).
+ * t = 0 (every step synchronised) assigns fresh bins. */
+int tpm_time_bins(tpm_ctx *ctx, int64_t n, int64_t n_act, const int32_t *idx,
+                  int32_t precision, const void *acc, const void *acc_b, const double *eps,
+                  double eps0, double C, double dt_max, int32_t max_bin, int64_t t,
+                  int32_t *bins, uint32_t *hist);
+
+/* Order-preserving selection from a list of m particles (list, or 0..m-1
+ * when NULL) by their bins: mode 0, those closing a step at tick t (t a
+ * multiple of 2^(max_bin - bin)); mode 1, bin <= level; mode 2, bin > level.
+ * out (device int32[m]) receives the selected particles (local = 0) or their
+ * positions in the list (local = 1); *n_out (host) their number.
+ * Synchronises the stream (the count is needed on the host). */
+int tpm_select_bins(tpm_ctx *ctx, int64_t m, const int32_t *list, const int32_t *bins,
+                    int32_t mode, int64_t t, int32_t level, int32_t max_bin, int32_t local,
+                    int32_t *out, int64_t *n_out);
+
+/* dst[k] = src[idx[k]], k < m (device FP64 arrays): positions, masses or
+ * softenings of a subset, contiguous for a build over that subset. */
+int tpm_gather(tpm_ctx *ctx, int64_t n, int64_t m, const int32_t *idx, const double *src,
+               double *dst);
 
 #ifdef __cplusplus
 }

@@ -57,6 +57,7 @@ def lib():
         L.tpm_bytes_held.argtypes = [vp]
         L.tpm_bytes_held.restype = i64
         L.tpm_build_tree.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.tpm_build_tree_eps.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.tpm_compute_forces.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp]
         L.tpm_pm_long_range.argtypes = [vp, i64, vp, vp, vp]
         L.tpm_check.argtypes = [vp]
@@ -71,6 +72,12 @@ def lib():
         L.tpm_batch_last_error.restype = C.c_char_p
         L.tpm_batch_add.argtypes = [vp, vp, i32, i64, vp, vp, vp, vp]
         L.tpm_batch_launch.argtypes = [vp]
+        L.tpm_kick.argtypes = [vp, i64, i64, vp, i32, vp, vp, i32, vp, d, d, vp, vp, vp]
+        L.tpm_drift.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, d, d]
+        L.tpm_time_bins.argtypes = [vp, i64, i64, vp, i32, vp, vp, vp, d, d, d, i32, i64, vp,
+                                    vp]
+        L.tpm_select_bins.argtypes = [vp, i64, vp, vp, i32, i64, i32, i32, i32, vp, P(i64)]
+        L.tpm_gather.argtypes = [vp, i64, i64, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -149,13 +156,16 @@ class Context:
         self._rc(lib().tpm_set_stream(self.h, _stream_handle(stream)))
 
     # -- the three operations of the hot path ---------------------------------
-    def build_tree(self, x, y, z, mass=None):
-        for t in (x, y, z) + ((mass,) if mass is not None else ()):
+    def build_tree(self, x, y, z, mass=None, eps=None):
+        """eps: optional individual softening lengths (float64, build order)."""
+        extra = tuple(t for t in (mass, eps) if t is not None)
+        for t in (x, y, z) + extra:
             if t.dtype != torch.float64:
-                raise ValueError("positions and masses must be float64")
+                raise ValueError("positions, masses and softenings must be float64")
         n = x.numel()
-        self._keep = (x, y, z, mass)  # inputs stay alive while the stream uses them
-        self._rc(lib().tpm_build_tree(self.h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(mass)))
+        self._keep = (x, y, z, mass, eps)  # inputs stay alive while the stream uses them
+        self._rc(lib().tpm_build_tree_eps(self.h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(mass),
+                                          _ptr(eps)))
         self.n = n
 
     def compute_forces(self, active_idx, opening="bh", a_old_norm=None, acc=None, pot=None,

@@ -53,7 +53,8 @@ size_t bytes_held(const tpm_ctx *c) {
                          &c->dR, &c->cnt, &c->base, &c->lvl_cursor, &c->lvl_list, &c->rec64,
                          &c->rec32, &c->efirst, &c->ecount, &c->pe, &c->mark, &c->act, &c->slot,
                          &c->counters, &c->res, &c->rpot, &c->rnint, &c->err_flag, &c->mesh_q,
-                         &c->mesh_c, &c->mesh_phi, &c->twiddle, &c->green_axis};
+                         &c->mesh_c, &c->mesh_phi, &c->twiddle, &c->green_axis, &c->green_tab,
+                         &c->hs, &c->eh64, &c->eh32, &c->ig_flag, &c->ig_off};
     size_t s = 0;
     for (const DBuf *b : all)
         s += b->cap;
@@ -112,13 +113,15 @@ static void free_all(tpm_ctx *c) {
                    &c->dR, &c->cnt, &c->base, &c->lvl_cursor, &c->lvl_list, &c->rec64,
                    &c->rec32, &c->efirst, &c->ecount, &c->pe, &c->mark, &c->act, &c->slot,
                    &c->counters, &c->res, &c->rpot, &c->rnint, &c->err_flag, &c->mesh_q,
-                   &c->mesh_c, &c->mesh_phi, &c->twiddle, &c->green_axis};
+                   &c->mesh_c, &c->mesh_phi, &c->twiddle, &c->green_axis, &c->green_tab,
+                   &c->hs, &c->eh64, &c->eh32, &c->ig_flag, &c->ig_off};
     for (DBuf *b : all) {
         if (b->p)
             (void)hipFree(b->p);
         b->p = nullptr;
         b->cap = 0;
     }
+    c->green_tab_ng = 0;
     if (c->hpin)
         (void)hipHostFree(c->hpin);
     c->hpin = nullptr;
@@ -149,15 +152,20 @@ static const char *validate(const tpm_params *p) {
             return "a periodic box needs the PM mesh (pm_grid > 0)";
     }
     if (p->pm_grid != 0) {
-        if (!p->periodic)
-            return "the PM mesh is implemented for periodic boxes only";
-        if (!is_pow2(p->pm_grid) || p->pm_grid < 8 || p->pm_grid > 1024)
-            return "pm_grid must be a power of two in [8, 1024]";
-        if (!(p->asmth > 0.0) || !(p->rcut > 0.0))
+        if (!(p->asmth > 0.0) || !(p->rcut > 0.0) || !std::isfinite(p->asmth) ||
+            !std::isfinite(p->rcut))
             return "asmth and rcut must be positive";
-        const double rs = p->asmth * p->box_size / p->pm_grid;
-        if (!(p->rcut * rs < 0.5 * p->box_size))
-            return "cutoff radius must be below half the box";
+        if (p->periodic) {
+            if (!is_pow2(p->pm_grid) || p->pm_grid < 8 || p->pm_grid > 1024)
+                return "pm_grid must be a power of two in [8, 1024]";
+            const double rs = p->asmth * p->box_size / p->pm_grid;
+            if (!(p->rcut * rs < 0.5 * p->box_size))
+                return "cutoff radius must be below half the box";
+        } else {
+            // isolated: zero-padded (2 pm_grid)^3 transform
+            if (!is_pow2(p->pm_grid) || p->pm_grid < 16 || p->pm_grid > 256)
+                return "isolated pm_grid must be a power of two in [16, 256]";
+        }
     }
     if (p->want_potential != 0 && p->want_potential != 1)
         return "want_potential must be 0 or 1";
@@ -227,8 +235,13 @@ int64_t tpm_bytes_needed(const tpm_params *p, int64_t n) {
     const int64_t per_entry = 64 + (p->precision == TPM_FP32 ? 32 : 0) + 12;
     int64_t b = n * per_part + (n * 5 / 2 + 64) * per_entry + (1 << 20);
     if (p->pm_grid > 0) {
-        const int64_t n3 = (int64_t)p->pm_grid * p->pm_grid * p->pm_grid;
+        const int64_t m = p->periodic ? p->pm_grid : 2 * (int64_t)p->pm_grid;
+        const int64_t n3 = m * m * m;
         b += n3 * (8 + (p->precision == TPM_FP32 ? 12 : 24));
+        if (!p->periodic) {  // Green's function octant
+            const int64_t g = p->pm_grid + 1;
+            b += g * g * g * 8;
+        }
     }
     return b + b / 8;
 }
@@ -237,6 +250,11 @@ int64_t tpm_bytes_held(const tpm_ctx *c) { return c ? (int64_t)bytes_held(c) : -
 
 int tpm_build_tree(tpm_ctx *c, int64_t n, const double *x, const double *y, const double *z,
                    const double *mass) {
+    return tpm_build_tree_eps(c, n, x, y, z, mass, nullptr);
+}
+
+int tpm_build_tree_eps(tpm_ctx *c, int64_t n, const double *x, const double *y,
+                       const double *z, const double *mass, const double *eps) {
     if (!c)
         return TPM_EINVAL;
     if (n < 1 || n > (int64_t(1) << 30))
@@ -252,7 +270,7 @@ int tpm_build_tree(tpm_ctx *c, int64_t n, const double *x, const double *y, cons
         TPM_TRY(fill_u32(c, (uint32_t *)c->err_flag.p, 0u, 4));
     }
     TPM_TRY(timer_begin(c, TPM_TIMER_BUILD));
-    TPM_TRY(build(c, n, x, y, z, mass));
+    TPM_TRY(build(c, n, x, y, z, mass, eps));
     TPM_TRY(timer_end(c, TPM_TIMER_BUILD));
     c->built = 1;
     return TPM_OK;
@@ -279,7 +297,7 @@ int tpm_compute_forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t
 int tpm_pm_long_range(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, void *pot) {
     if (!c)
         return TPM_EINVAL;
-    if (c->P.pm_grid <= 0 || !c->P.periodic)
+    if (c->P.pm_grid <= 0)
         return fail(c, TPM_EINVAL, "no PM mesh configured");
     if (!c->built)
         return fail(c, TPM_ESTATE, "pm_long_range before build_tree");

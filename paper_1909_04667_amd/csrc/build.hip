@@ -182,7 +182,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     const double *__restrict__ mass, int64_t n, const Frame *__restrict__ Fp,
     const uint32_t *__restrict__ sidx, int32_t *__restrict__ perm, int32_t *__restrict__ rank,
-    double *__restrict__ ps, double *__restrict__ ms, uint64_t *__restrict__ qs) {
+    double *__restrict__ ps, double *__restrict__ ms, uint64_t *__restrict__ qs,
+    const double *__restrict__ eps, double *__restrict__ hs, uint32_t *__restrict__ bad_eps) {
     int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= n)
         return;
@@ -200,6 +201,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     ps[2 * n + s] = p2;
     ms[s] = mass ? mass[i] : 1.0 / (double)n;
     qs[s] = ((uint64_t)q0 << 42) | ((uint64_t)q1 << 21) | (uint64_t)q2;
+    if (eps) {  // individual softening: spline support 2.8 eps, in curve order
+        const double e = eps[i];
+        if (!(e > 0.0) || !isfinite(e))
+            atomicOr(bad_eps, 1u);
+        hs[s] = 2.8 * e;
+    }
 }
 
 // ---- topology ----------------------------------------------------------------
@@ -271,7 +278,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     const double *__restrict__ ps, const double *__restrict__ ms,
     const uint64_t *__restrict__ qs, Rec64 *__restrict__ rec, uint32_t *__restrict__ efirst,
     uint32_t *__restrict__ ecount, uint32_t *__restrict__ pe,
-    const uint32_t *__restrict__ loff, uint32_t nb, uint32_t *__restrict__ lvl_list) {
+    const uint32_t *__restrict__ loff, uint32_t nb, uint32_t *__restrict__ lvl_list,
+    const double *__restrict__ hs, double *__restrict__ eh) {
     __shared__ uint32_t h[kLevels][kBlock / 64];
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool live = s < n;
@@ -318,6 +326,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(
         efirst[ep] = (uint32_t)s;
         ecount[ep] = 1u;
         pe[s] = ep;
+        if (eh)
+            eh[ep] = hs[s];
     }
     if (nn == 0)
         return;
@@ -345,18 +355,22 @@ __global__ __launch_bounds__(kBlock) void k_emit(
 // Nodes of one level (deepest level first): walk the children through their
 // skip pointers (all deeper, so already final), sum the monopole moments in
 // curve order -- M = (M1 + M2) + ..., X = fma(M_k, s_k, X), s = X / M -- and
-// set the node's particle count and skip pointer.
+// set the node's particle count and skip pointer.  With individual
+// softening the node also takes the largest spline support of its children.
 __global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uint32_t E,
                                                     uint32_t *__restrict__ ecount,
                                                     const uint32_t *__restrict__ list,
-                                                    uint32_t count, uint32_t lev) {
+                                                    uint32_t count, uint32_t lev,
+                                                    double *__restrict__ eh) {
     uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= count)
         return;
     const uint32_t e = list[i];
-    double M = 0.0, X0 = 0.0, X1 = 0.0, X2 = 0.0;
+    double M = 0.0, X0 = 0.0, X1 = 0.0, X2 = 0.0, hmax = 0.0;
     uint32_t cnt = 0, k = e + 1;
     while (k < E && (rec[k].meta & 0xffu) > lev) {
+        if (eh)
+            hmax = eh[k] > hmax ? eh[k] : hmax;
         const double mk = rec[k].mass;
         M = M + mk;
         X0 = fma(mk, rec[k].com[0], X0);
@@ -371,6 +385,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uin
     rec[e].com[2] = X2 / M;
     rec[e].skip = k;
     ecount[e] = cnt;
+    if (eh)
+        eh[e] = hmax;
 }
 
 // FP32 records: exact integer centres, float offsets of the centre of mass.
@@ -378,10 +394,14 @@ __global__ __launch_bounds__(kBlock) void k_pack32(const Rec64 *__restrict__ rec
                                                    const uint32_t *__restrict__ efirst,
                                                    const uint64_t *__restrict__ qs,
                                                    const Frame *__restrict__ Fp, double G,
-                                                   Rec32 *__restrict__ out) {
+                                                   Rec32 *__restrict__ out,
+                                                   const double *__restrict__ eh,
+                                                   float *__restrict__ eh32) {
     uint32_t e = blockIdx.x * kBlock + threadIdx.x;
     if (e >= E)
         return;
+    if (eh)
+        eh32[e] = (float)eh[e];
     const Frame F = *Fp;
     const Rec64 R = rec[e];
     const bool part = (R.meta & kParticleFlag) != 0;
@@ -414,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_pack32(const Rec64 *__restrict__ rec
 }  // namespace
 
 int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double *z,
-          const double *mass) {
+          const double *mass, const double *eps) {
     hipStream_t st = c->stream;
     const tpm_params &P = c->P;
     // per-particle buffers
@@ -461,9 +481,16 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
                                                    (uint32_t *)c->idx[0].p);
     TPM_LAUNCHED(c, "k_keys");
     TPM_TRY(radix_sort_pairs(c, n));
+    // individual softening: spline supports in curve order; a bad value
+    // sets the second error word, read back with the sizes below
+    c->mixed = eps != nullptr;
+    uint32_t *bad_eps = (uint32_t *)c->err_flag.p + 1;
+    if (c->mixed)
+        TPM_TRY(ensure(c, c->hs, (size_t)n * 8));
     k_gather<<<grid_for(n, kBlock), kBlock, 0, st>>>(
         x, y, z, mass, n, F, (const uint32_t *)c->idx[0].p, (int32_t *)c->perm.p,
-        (int32_t *)c->rank.p, (double *)c->ps.p, (double *)c->ms.p, (uint64_t *)c->qs.p);
+        (int32_t *)c->rank.p, (double *)c->ps.p, (double *)c->ms.p, (uint64_t *)c->qs.p, eps,
+        c->mixed ? (double *)c->hs.p : nullptr, bad_eps);
     TPM_LAUNCHED(c, "k_gather");
     // 4. topology: counts, scan, one readback of the sizes
     const uint64_t *key = (const uint64_t *)c->key[0].p;
@@ -482,7 +509,13 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
                               st));
     if (!P.periodic)
         TPM_HIP(c, hipMemcpyAsync(&c->frame_host, F, sizeof(Frame), hipMemcpyDeviceToHost, st));
+    TPM_HIP(c, hipMemcpyAsync(c->hpin + 128, bad_eps, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                              st));
     TPM_HIP(c, hipStreamSynchronize(st));
+    if (c->hpin[128]) {
+        TPM_TRY(fill_u32(c, bad_eps, 0u, 1));
+        return fail(c, TPM_EINVAL, "softening lengths must be positive and finite");
+    }
     // the FP32 walk works in units of L 2^-22 and scales sizes by 2^-level
     // through the exponent: both need a root size well inside float range
     if (P.precision == TPM_FP32 &&
@@ -503,11 +536,16 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
     TPM_TRY(ensure(c, c->ecount, (size_t)E * 4));
     TPM_TRY(ensure(c, c->lvl_list, (size_t)(off > 0 ? off : 1) * 4));
     Rec64 *rec = (Rec64 *)c->rec64.p;
+    double *eh = nullptr;
+    if (c->mixed) {
+        TPM_TRY(ensure(c, c->eh64, (size_t)E * 8));
+        eh = (double *)c->eh64.p;
+    }
     k_emit<<<grid_for(n, kBlock), kBlock, 0, st>>>(
         key, n, (const int8_t *)c->dR.p, (const uint32_t *)c->base.p, F,
         (const double *)c->ps.p, (const double *)c->ms.p, (const uint64_t *)c->qs.p, rec,
         (uint32_t *)c->efirst.p, (uint32_t *)c->ecount.p, (uint32_t *)c->pe.p, loff, nb,
-        (uint32_t *)c->lvl_list.p);
+        (uint32_t *)c->lvl_list.p, (const double *)c->hs.p, eh);
     TPM_LAUNCHED(c, "k_emit");
     // 5. moments, deepest level first
     for (int l = kMaxLevel; l >= 0; l--) {
@@ -516,14 +554,16 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
             continue;
         k_moments<<<grid_for(cnt, kBlock), kBlock, 0, st>>>(
             rec, E, (uint32_t *)c->ecount.p, (const uint32_t *)c->lvl_list.p + c->level_off[l],
-            cnt, (uint32_t)l);
+            cnt, (uint32_t)l, eh);
         TPM_LAUNCHED(c, "k_moments");
     }
     if (P.precision == TPM_FP32) {
         TPM_TRY(ensure(c, c->rec32, (size_t)E * sizeof(Rec32)));
-        k_pack32<<<grid_for(E, kBlock), kBlock, 0, st>>>(rec, E, (const uint32_t *)c->efirst.p,
-                                                         (const uint64_t *)c->qs.p, F, P.G,
-                                                         (Rec32 *)c->rec32.p);
+        if (c->mixed)
+            TPM_TRY(ensure(c, c->eh32, (size_t)E * 4));
+        k_pack32<<<grid_for(E, kBlock), kBlock, 0, st>>>(
+            rec, E, (const uint32_t *)c->efirst.p, (const uint64_t *)c->qs.p, F, P.G,
+            (Rec32 *)c->rec32.p, eh, c->mixed ? (float *)c->eh32.p : nullptr);
         TPM_LAUNCHED(c, "k_pack32");
     }
     c->n = n;

@@ -28,11 +28,22 @@ struct Cx {
     T re, im;
 };
 
+// Mesh geometry: point i of an axis sits at lo + i h; `box` > 0 wraps
+// positions periodically into [0, box) (lo = 0 then), `box` = 0 leaves them
+// (the isolated mesh, where every position lies well inside the mesh).
+struct MeshGeom {
+    double lo[3];
+    double box;
+    double h;
+    int ng;  // points per axis of the transformed mesh
+};
+
 __global__ __launch_bounds__(kBlock) void k_deposit(const double *__restrict__ ps,
                                                     const double *__restrict__ ms, int64_t n,
-                                                    const Rec64 *__restrict__ rec, double box,
-                                                    double h, int ng,
+                                                    const Rec64 *__restrict__ rec, MeshGeom mg,
                                                     unsigned long long *__restrict__ mesh) {
+    const double box = mg.box, h = mg.h;
+    const int ng = mg.ng;
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool live = s < n;
     const int lane = threadIdx.x & 63;
@@ -44,11 +55,13 @@ __global__ __launch_bounds__(kBlock) void k_deposit(const double *__restrict__ p
     double w[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        double u = live ? ps[(size_t)a * n + s] : 0.0;
-        if (u < 0.0)
-            u += box;
-        if (u >= box)
-            u -= box;
+        double u = live ? ps[(size_t)a * n + s] - mg.lo[a] : 0.0;
+        if (box > 0.0) {
+            if (u < 0.0)
+                u += box;
+            if (u >= box)
+                u -= box;
+        }
         const double f = u / h;
         const double fl = floor(f);
         w[a] = f - fl;
@@ -227,8 +240,9 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__rest
                                                 T *__restrict__ phi, const Cx<T> *__restrict__ tw,
                                                 const double *__restrict__ gk2,
                                                 const double *__restrict__ gdc, double gconst,
-                                                double rs, const Rec64 *__restrict__ rec,
-                                                double vinv, double norm) {
+                                                double rs, const double *__restrict__ gtab,
+                                                const Rec64 *__restrict__ rec, double vinv,
+                                                double norm) {
     constexpr int NG = R1 * R2, C = R1 / R2, PAD = R2 + 1;
     extern __shared__ unsigned char lds_raw[];
     Cx<T> *lds = (Cx<T> *)lds_raw;  // B rows of R1 x (R2 + 1)
@@ -296,11 +310,21 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__rest
 #pragma unroll
             for (int n1 = 0; n1 < R1; n1++) {
                 const int i = R2 * n1 + n2;
-                const double k2s = (gk2[i] + gk2[jline]) + gk2[kline];
-                const double dc = (gdc[i] * gdc[jline]) * gdc[kline];
                 double g = 0.0;
-                if (k2s != 0.0)
-                    g = gconst * exp(-k2s * rs * rs) / (k2s * dc);
+                if (gtab) {
+                    // isolated: the table holds one octant of the (even)
+                    // transformed kernel, (NG/2 + 1)^3 values
+                    constexpr int GH = NG / 2 + 1;
+                    const int ii = i <= NG / 2 ? i : NG - i;
+                    const int jj = jline <= NG / 2 ? jline : NG - jline;
+                    const int kk = kline <= NG / 2 ? kline : NG - kline;
+                    g = gconst * gtab[((size_t)ii * GH + jj) * GH + kk];
+                } else {
+                    const double k2s = (gk2[i] + gk2[jline]) + gk2[kline];
+                    const double dc = (gdc[i] * gdc[jline]) * gdc[kline];
+                    if (k2s != 0.0)
+                        g = gconst * exp(-k2s * rs * rs) / (k2s * dc);
+                }
                 const Cx<T> v = line[i];
                 a[n1] = Cx<T>{(T)(v.re * g), (T)(v.im * g)};
             }
@@ -330,9 +354,10 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_interp(const uint32_t *__restrict__ act,
                                                    const uint32_t *__restrict__ nuniq,
                                                    int64_t n, const double *__restrict__ ps,
-                                                   const T *__restrict__ phi, int ng, double box,
-                                                   double h, T *__restrict__ res,
-                                                   T *__restrict__ rpot) {
+                                                   const T *__restrict__ phi, MeshGeom mg,
+                                                   T *__restrict__ res, T *__restrict__ rpot) {
+    const double box = mg.box, h = mg.h;
+    const int ng = mg.ng;
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= (int64_t)*nuniq)
         return;
@@ -341,11 +366,13 @@ __global__ __launch_bounds__(kBlock) void k_interp(const uint32_t *__restrict__ 
     double w[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        double u = ps[(size_t)a * n + s];
-        if (u < 0.0)
-            u += box;
-        if (u >= box)
-            u -= box;
+        double u = ps[(size_t)a * n + s] - mg.lo[a];
+        if (box > 0.0) {
+            if (u < 0.0)
+                u += box;
+            if (u >= box)
+                u -= box;
+        }
         const double f = u / h;
         const double fl = floor(f);
         w[a] = f - fl;
@@ -421,10 +448,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter_out(
         pot[k] = rpot[sl];
 }
 
+struct FftArgs {
+    const double *gk2 = nullptr, *gdc = nullptr, *gtab = nullptr;
+    double gconst = 0.0, rs = 0.0, vinv = 1.0, norm = 1.0;
+    const Rec64 *rec = nullptr;
+};
+
 template <typename T, int R1, int R2>
 int launch_fft(tpm_ctx *c, const FftPass &fp, Cx<T> *mc, const unsigned long long *mq, T *phi,
-               const Cx<T> *tw, const double *gk2, const double *gdc, double gconst, double rs,
-               const Rec64 *rec, double vinv, double norm) {
+               const Cx<T> *tw, const FftArgs &fa) {
     constexpr int NG = R1 * R2;
     // lines per block: one wavefront group of R2 threads per line, at most
     // kBlock threads, the LDS rows within the budget, and B | NG
@@ -435,42 +467,177 @@ int launch_fft(tpm_ctx *c, const FftPass &fp, Cx<T> *mc, const unsigned long lon
         B = NG;
     const size_t lds = (size_t)B * R1 * (R2 + 1) * sizeof(Cx<T>);
     const unsigned blocks = (unsigned)((size_t)NG * NG / B);
-    k_fft<T, R1, R2><<<blocks, kBlock, lds, c->stream>>>(fp, B, mc, mq, phi, tw, gk2, gdc,
-                                                         gconst, rs, rec, vinv, norm);
+    k_fft<T, R1, R2><<<blocks, kBlock, lds, c->stream>>>(fp, B, mc, mq, phi, tw, fa.gk2,
+                                                         fa.gdc, fa.gconst, fa.rs, fa.gtab,
+                                                         fa.rec, fa.vinv, fa.norm);
     TPM_LAUNCHED(c, "k_fft");
     return TPM_OK;
+}
+
+// One pass over an ng^3 mesh with the register decomposition of ng.
+template <typename T>
+int fft_pass(tpm_ctx *c, int ng, const FftPass &fp, Cx<T> *mc, const unsigned long long *mq,
+             T *phi, const Cx<T> *tw, const FftArgs &fa) {
+    switch (ng) {
+    case 8: return launch_fft<T, 4, 2>(c, fp, mc, mq, phi, tw, fa);
+    case 16: return launch_fft<T, 4, 4>(c, fp, mc, mq, phi, tw, fa);
+    case 32: return launch_fft<T, 8, 4>(c, fp, mc, mq, phi, tw, fa);
+    case 64: return launch_fft<T, 8, 8>(c, fp, mc, mq, phi, tw, fa);
+    case 128: return launch_fft<T, 16, 8>(c, fp, mc, mq, phi, tw, fa);
+    case 256: return launch_fft<T, 16, 16>(c, fp, mc, mq, phi, tw, fa);
+    case 512: return launch_fft<T, 32, 16>(c, fp, mc, mq, phi, tw, fa);
+    case 1024: return launch_fft<T, 32, 32>(c, fp, mc, mq, phi, tw, fa);
+    default: return fail(c, TPM_EINVAL, "unsupported mesh size");
+    }
+}
+
+template <typename T>
+std::vector<Cx<T>> twiddles(int ng) {
+    std::vector<Cx<T>> tw(ng);
+    for (int k = 0; k < ng; k++) {
+        const double a = 2.0 * M_PI * k / ng;
+        tw[k] = Cx<T>{(T)std::cos(a), (T)-std::sin(a)};
+    }
+    return tw;
+}
+
+// Isolated mesh: the long-range kernel -erf(rho / 2 a) / rho in units of the
+// mesh spacing (rho = r / h, a = r_s / h), value -1 / (sqrt(pi) a) at rho = 0,
+// at the signed offsets of the padded M^3 mesh.
+__global__ __launch_bounds__(kBlock) void k_green_fill(Cx<double> *__restrict__ mesh, int M,
+                                                       double inv2a) {
+    const size_t q = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const size_t m3 = (size_t)M * M * M;
+    if (q >= m3)
+        return;
+    const int k = (int)(q % M), j = (int)((q / M) % M), i = (int)(q / ((size_t)M * M));
+    const int h = M / 2;
+    const double o0 = i < h ? i : i - M, o1 = j < h ? j : j - M, o2 = k < h ? k : k - M;
+    const double rho = sqrt(o0 * o0 + o1 * o1 + o2 * o2);
+    const double v = rho == 0.0 ? -2.0 * inv2a / sqrt(M_PI) : -erf(rho * inv2a) / rho;
+    mesh[q] = Cx<double>{v, 0.0};
+}
+
+// One octant of the transformed kernel (real: the kernel is even), divided
+// by the CIC deconvolution prod_a sinc^4(pi n_a / M).
+__global__ __launch_bounds__(kBlock) void k_green_table(const Cx<double> *__restrict__ mesh,
+                                                        int M, double *__restrict__ tab) {
+    const int gh = M / 2 + 1;
+    const size_t q = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= (size_t)gh * gh * gh)
+        return;
+    const int idx[3] = {(int)(q / ((size_t)gh * gh)), (int)((q / gh) % gh), (int)(q % gh)};
+    double dc = 1.0;
+    for (int a = 0; a < 3; a++) {
+        const double sarg = M_PI * idx[a] / M;
+        const double sc = idx[a] == 0 ? 1.0 : sin(sarg) / sarg;
+        dc *= sc * sc * sc * sc;
+    }
+    tab[q] = mesh[((size_t)idx[0] * M + idx[1]) * M + idx[2]].re / dc;
+}
+
+// Builds the isolated Green's function table once per context (it depends
+// only on pm_grid and asmth, in units of the mesh spacing).
+int build_green_isolated(tpm_ctx *c) {
+    const int ng = c->P.pm_grid, M = 2 * ng, gh = ng + 1;
+    if (c->green_tab_ng == ng && c->green_tab.p)
+        return TPM_OK;
+    const size_t m3 = (size_t)M * M * M;
+    hipStream_t st = c->stream;
+    DBuf tmp, twb;
+    auto release = [&] {
+        (void)hipStreamSynchronize(st);
+        if (tmp.p)
+            (void)hipFree(tmp.p);
+        if (twb.p)
+            (void)hipFree(twb.p);
+        tmp.p = twb.p = nullptr;
+    };
+    if (hipMalloc(&tmp.p, m3 * sizeof(Cx<double>)) != hipSuccess ||
+        hipMalloc(&twb.p, (size_t)M * sizeof(Cx<double>)) != hipSuccess) {
+        (void)hipGetLastError();
+        release();
+        return fail(c, TPM_ENOMEM, "isolated Green's function: out of device memory");
+    }
+    const std::vector<Cx<double>> tw = twiddles<double>(M);
+    int rc = TPM_OK;
+    if (hipMemcpyAsync(twb.p, tw.data(), tw.size() * sizeof(Cx<double>), hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+        rc = fail(c, TPM_EDEVICE, "isolated Green's function: copy failed");
+    if (rc == TPM_OK)
+        rc = ensure(c, c->green_tab, (size_t)gh * gh * gh * sizeof(double));
+    if (rc == TPM_OK) {
+        k_green_fill<<<(unsigned)((m3 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+            (Cx<double> *)tmp.p, M, 0.5 / c->P.asmth);
+        if (hipGetLastError() != hipSuccess)
+            rc = fail(c, TPM_EDEVICE, "k_green_fill launch failed");
+    }
+    const FftPass fwd[3] = {{2, 0, 0, 0, 0}, {1, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+    for (int k = 0; k < 3 && rc == TPM_OK; k++)
+        rc = fft_pass<double>(c, M, fwd[k], (Cx<double> *)tmp.p, nullptr, nullptr,
+                              (const Cx<double> *)twb.p, FftArgs{});
+    if (rc == TPM_OK) {
+        const size_t g3 = (size_t)gh * gh * gh;
+        k_green_table<<<(unsigned)((g3 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+            (const Cx<double> *)tmp.p, M, (double *)c->green_tab.p);
+        if (hipGetLastError() != hipSuccess)
+            rc = fail(c, TPM_EDEVICE, "k_green_table launch failed");
+    }
+    release();  // waits for the stream: the table is complete
+    if (rc == TPM_OK)
+        c->green_tab_ng = ng;
+    return rc;
+}
+
+// Mesh geometry of the current build: periodic box of ng cells, or the
+// isolated ng-cell mesh of spacing L_root / (ng - 4) starting two cells
+// below the root cube, zero-padded to (2 ng)^3.
+MeshGeom mesh_geom(const tpm_ctx *c) {
+    const tpm_params &P = c->P;
+    MeshGeom g{};
+    if (P.periodic) {
+        g.box = P.box_size;
+        g.h = P.box_size / P.pm_grid;
+        g.ng = P.pm_grid;
+    } else {
+        g.box = 0.0;
+        g.h = c->frame_host.L / (P.pm_grid - 4);
+        for (int a = 0; a < 3; a++)
+            g.lo[a] = c->frame_host.x0[a] - 2.0 * g.h;
+        g.ng = 2 * P.pm_grid;
+    }
+    return g;
 }
 
 template <typename T>
 int solve_t(tpm_ctx *c) {
     const tpm_params &P = c->P;
-    const int ng = P.pm_grid;
-    int logn = 0;
-    while ((1 << logn) < ng)
-        logn++;
-    const size_t n3 = (size_t)ng * ng * ng;
+    const bool iso = !P.periodic;
+    const MeshGeom mg = mesh_geom(c);
+    const int M = mg.ng;  // transformed mesh
+    const size_t n3 = (size_t)M * M * M;
     hipStream_t st = c->stream;
+    if (iso)
+        TPM_TRY(build_green_isolated(c));
     TPM_TRY(ensure(c, c->mesh_q, n3 * 8));
     TPM_TRY(ensure(c, c->mesh_c, n3 * sizeof(Cx<T>)));
     TPM_TRY(ensure(c, c->mesh_phi, n3 * sizeof(T)));
-    TPM_TRY(ensure(c, c->twiddle, (size_t)ng * sizeof(Cx<T>) + 64));
-    TPM_TRY(ensure(c, c->green_axis, (size_t)2 * ng * sizeof(double)));
+    TPM_TRY(ensure(c, c->twiddle, (size_t)M * sizeof(Cx<T>) + 64));
+    TPM_TRY(ensure(c, c->green_axis, (size_t)2 * M * sizeof(double)));
     // tables, computed in double on the host
     {
-        std::vector<Cx<T>> tw(ng);
-        for (int k = 0; k < ng; k++) {
-            const double a = 2.0 * M_PI * k / ng;
-            tw[k] = Cx<T>{(T)std::cos(a), (T)-std::sin(a)};
-        }
-        const double box = P.box_size, h = box / ng;
-        std::vector<double> g(2 * ng);
-        for (int i = 0; i < ng; i++) {
-            const int nn = i < ng / 2 ? i : i - ng;
-            const double kv = 2.0 * M_PI * nn / box;
-            const double s = 0.5 * kv * h;
-            const double sc = nn == 0 ? 1.0 : std::sin(s) / s;
-            g[i] = kv * kv;
-            g[ng + i] = sc * sc * sc * sc;
+        const std::vector<Cx<T>> tw = twiddles<T>(M);
+        std::vector<double> g(2 * M, 0.0);
+        if (!iso) {
+            const double box = P.box_size, h = mg.h;
+            for (int i = 0; i < M; i++) {
+                const int nn = i < M / 2 ? i : i - M;
+                const double kv = 2.0 * M_PI * nn / box;
+                const double s = 0.5 * kv * h;
+                const double sc = nn == 0 ? 1.0 : std::sin(s) / s;
+                g[i] = kv * kv;
+                g[M + i] = sc * sc * sc * sc;
+            }
         }
         TPM_HIP(c, hipMemcpyAsync(c->twiddle.p, tw.data(), tw.size() * sizeof(Cx<T>),
                                   hipMemcpyHostToDevice, st));
@@ -481,55 +648,46 @@ int solve_t(tpm_ctx *c) {
     }
     unsigned long long *mq = (unsigned long long *)c->mesh_q.p;
     TPM_TRY(fill_u64(c, (uint64_t *)mq, 0ull, (int64_t)n3));
-    const double box = P.box_size, h = box / ng;
     k_deposit<<<grid_for(c->n, kBlock), kBlock, 0, st>>>(
-        (const double *)c->ps.p, (const double *)c->ms.p, c->n, (const Rec64 *)c->rec64.p, box, h,
-        ng, mq);
+        (const double *)c->ps.p, (const double *)c->ms.p, c->n, (const Rec64 *)c->rec64.p, mg,
+        mq);
     TPM_LAUNCHED(c, "k_deposit");
-    const double *gk2 = (const double *)c->green_axis.p;
-    const double *gdc = gk2 + ng;
-    const double gconst = -4.0 * M_PI * P.G;
-    const double rs = P.asmth * P.box_size / P.pm_grid;
-    const double vinv = 1.0 / (h * h * h);
-    const double norm = 1.0 / (double)n3;
+    FftArgs fa;
+    fa.rec = (const Rec64 *)c->rec64.p;
+    fa.norm = 1.0 / (double)n3;
+    if (iso) {
+        // masses on the mesh, Phi = IFFT(FFT(M) T) (G / h) / M^3
+        fa.gtab = (const double *)c->green_tab.p;
+        fa.gconst = P.G / mg.h;
+        fa.vinv = 1.0;
+    } else {
+        fa.gk2 = (const double *)c->green_axis.p;
+        fa.gdc = fa.gk2 + M;
+        fa.gconst = -4.0 * M_PI * P.G;
+        fa.rs = P.asmth * P.box_size / P.pm_grid;
+        fa.vinv = 1.0 / (mg.h * mg.h * mg.h);
+    }
     Cx<T> *mc = (Cx<T> *)c->mesh_c.p;
     T *phi = (T *)c->mesh_phi.p;
     const Cx<T> *tw = (const Cx<T> *)c->twiddle.p;
-    const Rec64 *rec = (const Rec64 *)c->rec64.p;
     const FftPass passes[5] = {
         {2, 1, 0, 0, 0}, {1, 0, 0, 0, 0}, {0, 0, 0, 0, 1}, {1, 0, 0, 1, 0}, {2, 0, 1, 1, 0}};
-    for (const FftPass &fp : passes) {
-        int rc;
-        switch (ng) {
-        case 8: rc = launch_fft<T, 4, 2>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
-        case 16: rc = launch_fft<T, 4, 4>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
-        case 32: rc = launch_fft<T, 8, 4>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
-        case 64: rc = launch_fft<T, 8, 8>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
-        case 128: rc = launch_fft<T, 16, 8>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
-        case 256: rc = launch_fft<T, 16, 16>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
-        case 512: rc = launch_fft<T, 32, 16>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
-        case 1024: rc = launch_fft<T, 32, 32>(c, fp, mc, mq, phi, tw, gk2, gdc, gconst, rs, rec, vinv, norm); break;
-        default: return fail(c, TPM_EINVAL, "unsupported pm_grid");
-        }
-        TPM_TRY(rc);
-    }
+    for (const FftPass &fp : passes)
+        TPM_TRY(fft_pass<T>(c, M, fp, mc, mq, phi, tw, fa));
     return TPM_OK;
 }
 
 template <typename T>
 int interp_t(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, void *pot) {
-    const tpm_params &P = c->P;
-    const int ng = P.pm_grid;
     const int64_t n = c->n;
-    const double box = P.box_size, h = box / ng;
+    const MeshGeom mg = mesh_geom(c);
     TPM_TRY(ensure(c, c->res, (size_t)3 * n * sizeof(T)));
     TPM_TRY(ensure(c, c->rpot, (size_t)n * sizeof(T)));
     TPM_TRY(select_active(c, n_act, idx));
     const unsigned g = grid_for(std::min<int64_t>(n_act, n), kBlock);
     k_interp<T><<<g, kBlock, 0, c->stream>>>(
         (const uint32_t *)c->act.p, (const uint32_t *)c->counters.p + 40, n,
-        (const double *)c->ps.p, (const T *)c->mesh_phi.p, ng, box, h, (T *)c->res.p,
-        (T *)c->rpot.p);
+        (const double *)c->ps.p, (const T *)c->mesh_phi.p, mg, (T *)c->res.p, (T *)c->rpot.p);
     TPM_LAUNCHED(c, "k_interp");
     k_scatter_out<T><<<grid_for(n_act, kBlock), kBlock, 0, c->stream>>>(
         idx, n_act, n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,

@@ -85,13 +85,21 @@ struct tpm_ctx {
     tpm::DBuf pe;               // rank -> entry
     tpm::DBuf mark, act, slot, counters;
     tpm::DBuf res, rpot, rnint; // walk results in slot order
-    tpm::DBuf err_flag;
+    tpm::DBuf err_flag;         // [0] bad active index, [1] bad softening length
+    // individual softening (Sec. 3.2): spline supports per particle in curve
+    // order, and per entry the largest of its particles (FP64, FP32 copy)
+    int mixed = 0;
+    tpm::DBuf hs, eh64, eh32;
+    // time integration: selection flags and offsets
+    tpm::DBuf ig_flag, ig_off;
     // particle mesh
     tpm::DBuf mesh_q;           // fixed-point deposit
     tpm::DBuf mesh_c;           // complex work mesh
     tpm::DBuf mesh_phi;         // real potential
     tpm::DBuf twiddle;          // FFT twiddles
     tpm::DBuf green_axis;       // per-axis k^2 and deconvolution tables
+    tpm::DBuf green_tab;        // isolated mesh: transformed kernel, one octant
+    int green_tab_ng = 0;       // pm_grid the table was built for (0: none)
     // measurement: event pairs per timer class, and a pool of spare events
     int timing = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[8];
@@ -126,7 +134,7 @@ int fill_u64(tpm_ctx *c, uint64_t *p, uint64_t v, int64_t n);
 
 // Build (build.hip) --------------------------------------------------------
 int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double *z,
-          const double *mass);
+          const double *mass, const double *eps);
 
 // Walk (walk.hip) ----------------------------------------------------------
 int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const double *anorm,

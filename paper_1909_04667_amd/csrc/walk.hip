@@ -48,6 +48,10 @@ struct WalkArgs {
     void *res;
     void *rpot;
     uint32_t *rnint;
+    // individual softening (Sec. 3.2): spline support per target (curve
+    // order) and the largest support per entry (double, or float for FP32)
+    const double *hs;
+    const void *eh;
 };
 
 // Wavefront masks: ballot of a lane predicate, and a mask read back as the
@@ -74,23 +78,31 @@ __device__ __forceinline__ double spline_phi64(double u) {
            1.0 / (15.0 * u);
 }
 
-template <bool TPM, bool POT>
+// hp: the pair's spline support with individual softening (MIXED), else
+// the common one of the parameters.
+template <bool TPM, bool POT, bool MIXED>
 __device__ __forceinline__ void interact64(const WalkArgs &A, double m, double d0, double d1,
-                                           double d2, double dd, double &a0, double &a1,
-                                           double &a2, double &pot) {
+                                           double d2, double dd, double hp, double &a0,
+                                           double &a1, double &a2, double &pot) {
     const double Gm = A.G * m;
     const double r = sqrt(dd);
+    const double h = MIXED ? hp : A.h;
     double fac, phi = 0.0;
-    if (r >= A.h) {
+    if (r >= h) {
         const double rinv = 1.0 / r;
         fac = Gm * rinv * rinv * rinv;
         if (POT)
             phi = -Gm * rinv;
     } else {
-        const double u = r / A.h;
-        fac = (Gm * A.h3inv) * spline_g64(u);
+        double hinv = A.hinv, h3inv = A.h3inv;
+        if (MIXED) {
+            hinv = 1.0 / h;
+            h3inv = hinv * hinv * hinv;
+        }
+        const double u = r / h;
+        fac = (Gm * h3inv) * spline_g64(u);
         if (POT)
-            phi = (Gm * A.hinv) * spline_phi64(u);
+            phi = (Gm * hinv) * spline_phi64(u);
     }
     if (TPM) {
         const double x = r * A.inv2rs;
@@ -137,24 +149,30 @@ __device__ __forceinline__ double spline_phi64_sel(double u) {
 // the whole wavefront (callers branch on "some lane interacts", a uniform
 // condition); per-lane choices are selects, so every interacting lane gets
 // exactly interact64's result.
-template <bool TPM, bool POT>
+template <bool TPM, bool POT, bool MIXED>
 __device__ __forceinline__ void interact64_wave(const WalkArgs &A, bool inter, double m, double d0,
-                                                double d1, double d2, double dd, double &a0,
-                                                double &a1, double &a2, double &pot,
+                                                double d1, double d2, double dd, double hp,
+                                                double &a0, double &a1, double &a2, double &pot,
                                                 uint32_t &nint) {
     const double Gm = A.G * m;
     const double r = sqrt(dd);
     const double rinv = 1.0 / r;
+    const double h = MIXED ? hp : A.h;
     double fac = Gm * rinv * rinv * rinv;
     double phi = 0.0;
     if (POT)
         phi = -Gm * rinv;
-    const bool soft = r < A.h;
+    const bool soft = r < h;
     if (wave_mask(inter && soft)) {
-        const double u = r / A.h;
-        fac = soft ? (Gm * A.h3inv) * spline_g64_sel(u) : fac;
+        double hinv = A.hinv, h3inv = A.h3inv;
+        if (MIXED) {
+            hinv = 1.0 / h;
+            h3inv = hinv * hinv * hinv;
+        }
+        const double u = r / h;
+        fac = soft ? (Gm * h3inv) * spline_g64_sel(u) : fac;
         if (POT)
-            phi = soft ? (Gm * A.hinv) * spline_phi64_sel(u) : phi;
+            phi = soft ? (Gm * hinv) * spline_phi64_sel(u) : phi;
     }
     if (TPM) {
         // lanes that do not interact take a harmless argument
@@ -182,7 +200,7 @@ __device__ __forceinline__ double scale_level(double v, uint32_t lev) {
 // One wavefront walks group `wave` (slots 64 wave .. 64 wave + 63).  The
 // cursor and the entry are wavefront-uniform; each lane decides for itself
 // (as masks) and only branches on wavefront-uniform conditions are taken.
-template <bool PER, bool TPM, int OPEN, bool POT>
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
     const int lane = threadIdx.x & 63;
     const uint32_t nu = *A.nuniq;
@@ -197,6 +215,7 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
     if (OPEN == TPM_OPEN_REL)
         an = A.anorm[A.perm[s]];
     const double alpha_an = A.alpha * an;
+    const double hi = MIXED ? A.hs[s] : 0.0;  // the target's own support
     uint32_t next = valid ? 0u : 0xffffffffu;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, pot = 0.0;
     uint32_t nint = 0;
@@ -205,6 +224,8 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
     while (c < A.E) {
         const uint32_t cu = __builtin_amdgcn_readfirstlane(c);
         const Rec64 r = R[cu];
+        const double he = MIXED ? ((const double *)A.eh)[cu] : 0.0;
+        const double hp = hi > he ? hi : he;  // the larger support
         const uint64_t mine = wave_mask(next == cu);
         const double d0 = wrap64<PER>(r.com[0] - x0, A.box, A.half);
         const double d1 = wrap64<PER>(r.com[1] - x1, A.box, A.half);
@@ -237,14 +258,17 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
                 crit = (A.G * r.mass) * L2 > alpha_an * (dd * dd);
             const double lim = scale_level(A.limr, lev);
             const bool box = fabs(c0) < lim && fabs(c1) < lim && fabs(c2) < lim;
-            const uint64_t open = keep & wave_mask(crit || box);
+            // larger softening inside the node, target within it of the
+            // centre of mass: open (Sec. 3.2)
+            const bool soft_open = MIXED && hi < he && dd < he * he;
+            const uint64_t open = keep & wave_mask(crit || box || soft_open);
             inter = mine & keep & ~open;
             desc = mine & open;
             next = lane_in(mine) ? (lane_in(open) ? cu + 1u : r.skip) : next;
         }
         if (inter)
-            interact64_wave<TPM, POT>(A, lane_in(inter), r.mass, d0, d1, d2, dd, a0, a1, a2, pot,
-                                      nint);
+            interact64_wave<TPM, POT, MIXED>(A, lane_in(inter), r.mass, d0, d1, d2, dd, hp, a0,
+                                             a1, a2, pot, nint);
         c = desc ? cu + 1u : r.skip;
     }
     if (valid) {
@@ -277,12 +301,12 @@ __device__ __forceinline__ float spline_phi32(float u) {
            __builtin_amdgcn_rcpf(15.0f * u);
 }
 
-template <bool TPM, bool POT>
+template <bool TPM, bool POT, bool MIXED>
 __device__ __forceinline__ void interact32(const WalkArgs &A, float gm, float d0, float d1,
-                                           float d2, float dd, float &a0, float &a1, float &a2,
-                                           float &pot) {
+                                           float d2, float dd, float hp, float &a0, float &a1,
+                                           float &a2, float &pot) {
     float fac, phi = 0.0f, r = 0.0f;
-    if (dd >= A.fh2) {
+    if (dd >= (MIXED ? hp * hp : A.fh2)) {
         const float rinv = __builtin_amdgcn_rsqf(dd);
         fac = gm * rinv * rinv * rinv;
         if (POT)
@@ -290,11 +314,16 @@ __device__ __forceinline__ void interact32(const WalkArgs &A, float gm, float d0
         if (TPM)
             r = dd * rinv;
     } else {
+        float hinv = A.fhinv, h3inv = A.fh3inv;
+        if (MIXED) {
+            hinv = 1.0f / hp;
+            h3inv = hinv * hinv * hinv;
+        }
         r = __builtin_amdgcn_sqrtf(dd);
-        const float u = r * A.fhinv;
-        fac = (gm * A.fh3inv) * spline_g32(u);
+        const float u = r * hinv;
+        fac = (gm * h3inv) * spline_g32(u);
         if (POT)
-            phi = (gm * A.fhinv) * spline_phi32(u);
+            phi = (gm * hinv) * spline_phi32(u);
     }
     if (TPM) {
         // erfc by Abramowitz & Stegun 7.1.26 (|error| < 1.5e-7), sharing
@@ -346,10 +375,10 @@ __device__ __forceinline__ float spline_phi32_sel(float u) {
 
 // interact32 for the lanes with `inter` set, executed by the whole wavefront
 // (see interact64_wave); identical results for those lanes.
-template <bool TPM, bool POT>
+template <bool TPM, bool POT, bool MIXED>
 __device__ __forceinline__ void interact32_wave(const WalkArgs &A, bool inter, float gm, float d0,
-                                                float d1, float d2, float dd, float &a0,
-                                                float &a1, float &a2, float &pot,
+                                                float d1, float d2, float dd, float hp,
+                                                float &a0, float &a1, float &a2, float &pot,
                                                 uint32_t &nint) {
     const float rinv = __builtin_amdgcn_rsqf(dd);
     float fac = gm * rinv * rinv * rinv;
@@ -358,13 +387,18 @@ __device__ __forceinline__ void interact32_wave(const WalkArgs &A, bool inter, f
         phi = -gm * rinv;
     if (TPM)
         r = dd * rinv;
-    const bool soft = dd < A.fh2;
+    const bool soft = dd < (MIXED ? hp * hp : A.fh2);
     if (wave_mask(inter && soft)) {
+        float hinv = A.fhinv, h3inv = A.fh3inv;
+        if (MIXED) {
+            hinv = 1.0f / hp;
+            h3inv = hinv * hinv * hinv;
+        }
         const float rr = __builtin_amdgcn_sqrtf(dd);
-        const float u = rr * A.fhinv;
-        fac = soft ? (gm * A.fh3inv) * spline_g32_sel(u) : fac;
+        const float u = rr * hinv;
+        fac = soft ? (gm * h3inv) * spline_g32_sel(u) : fac;
         if (POT)
-            phi = soft ? (gm * A.fhinv) * spline_phi32_sel(u) : phi;
+            phi = soft ? (gm * hinv) * spline_phi32_sel(u) : phi;
         if (TPM)
             r = soft ? rr : r;
     }
@@ -394,7 +428,7 @@ __device__ __forceinline__ float scale_level32(float v, uint32_t lev) {
     return __int_as_float(__float_as_int(v) - (int)(lev << 23));
 }
 
-template <bool PER, bool TPM, int OPEN, bool POT>
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     const int lane = threadIdx.x & 63;
     const uint32_t nu = *A.nuniq;
@@ -419,6 +453,7 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     if (OPEN == TPM_OPEN_REL)
         an = (float)A.anorm[A.perm[s]];
     const float alpha_an = A.falpha * an;
+    const float hi = MIXED ? (float)A.hs[s] : 0.0f;
     uint32_t next = valid ? 0u : 0xffffffffu;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, pot = 0.0f;
     uint32_t nint = 0;
@@ -429,6 +464,8 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     while (c < A.E) {
         const uint32_t cu = __builtin_amdgcn_readfirstlane(c);
         const Rec32 r = R[cu];
+        const float he = MIXED ? ((const float *)A.eh)[cu] : 0.0f;
+        const float hp = hi > he ? hi : he;
         const uint64_t mine = wave_mask(next == cu);
         const int32_t cm = r.cx_meta;
         // target -> centre of the entry, and target -> centre of mass
@@ -460,14 +497,15 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
                 crit = r.gm * L2 > alpha_an * (dd * dd);
             const float lim = scale_level32(A.flimr, lev);
             const bool box = fabsf(c0) < lim && fabsf(c1) < lim && fabsf(c2) < lim;
-            const uint64_t open = keep & wave_mask(crit || box);
+            const bool soft_open = MIXED && hi < he && dd < he * he;
+            const uint64_t open = keep & wave_mask(crit || box || soft_open);
             inter = mine & keep & ~open;
             desc = mine & open;
             next = lane_in(mine) ? (lane_in(open) ? cu + 1u : r.skip) : next;
         }
         if (inter)
-            interact32_wave<TPM, POT>(A, lane_in(inter), r.gm, d0, d1, d2, dd, a0, a1, a2, pot,
-                                      nint);
+            interact32_wave<TPM, POT, MIXED>(A, lane_in(inter), r.gm, d0, d1, d2, dd, hp, a0, a1,
+                                             a2, pot, nint);
         c = desc ? cu + 1u : r.skip;
     }
     if (valid) {
@@ -495,14 +533,14 @@ __device__ __forceinline__ uint32_t wave_id() {
     return (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 6;
 }
 
-template <bool PER, bool TPM, int OPEN, bool POT>
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_walk64(const WalkArgs A) {
-    walk_group64<PER, TPM, OPEN, POT>(A, wave_id());
+    walk_group64<PER, TPM, OPEN, POT, MIXED>(A, wave_id());
 }
 
-template <bool PER, bool TPM, int OPEN, bool POT>
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_walk32(const WalkArgs A) {
-    walk_group32<PER, TPM, OPEN, POT>(A, wave_id());
+    walk_group32<PER, TPM, OPEN, POT, MIXED>(A, wave_id());
 }
 
 // ---- lane-independent walks ------------------------------------------------
@@ -515,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_walk32(const WalkArgs A) {
 // the chunk one after the other, which evens out the lanes' work while the
 // wave's targets stay spatially close on the curve.
 
-template <bool PER, bool TPM, int OPEN, bool POT>
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, uint32_t K) {
     const int lane = threadIdx.x & 63;
     const uint32_t nu = *A.nuniq;
@@ -526,7 +564,8 @@ __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, u
     const Rec64 *__restrict__ R = (const Rec64 *)A.rec;
     uint32_t slot = base + lane;
     bool live = slot < chunk_end;
-    double x0 = 0.0, x1 = 0.0, x2 = 0.0, an = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0, pot = 0.0;
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0, an = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0, pot = 0.0,
+           hi = 0.0;
     uint32_t self = 0, nint = 0, e = 0;
     auto start = [&](uint32_t sl) {
         const uint32_t s = A.act[sl];
@@ -536,6 +575,8 @@ __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, u
         self = A.pe[s];
         if (OPEN == TPM_OPEN_REL)
             an = A.anorm[A.perm[s]];
+        if (MIXED)
+            hi = A.hs[s];
         a0 = a1 = a2 = pot = 0.0;
         nint = 0;
         e = 0;
@@ -545,6 +586,7 @@ __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, u
     while (__ballot(live)) {
         if (live) {
             const Rec64 r = R[e];
+            const double he = MIXED ? ((const double *)A.eh)[e] : 0.0;
             const double d0 = wrap64<PER>(r.com[0] - x0, A.box, A.half);
             const double d1 = wrap64<PER>(r.com[1] - x1, A.box, A.half);
             const double d2 = wrap64<PER>(r.com[2] - x2, A.box, A.half);
@@ -576,12 +618,15 @@ __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, u
                     const double lim = 0.6 * L;
                     if (fabs(c0) < lim && fabs(c1) < lim && fabs(c2) < lim)
                         open = true;
+                    if (MIXED && hi < he && dd < he * he)
+                        open = true;
                 }
                 step_in = open;
                 inter = !discard && !open;
             }
             if (inter) {
-                interact64<TPM, POT>(A, r.mass, d0, d1, d2, dd, a0, a1, a2, pot);
+                interact64<TPM, POT, MIXED>(A, r.mass, d0, d1, d2, dd, hi > he ? hi : he, a0, a1,
+                                            a2, pot);
                 nint++;
             }
             e = step_in ? e + 1u : r.skip;
@@ -602,7 +647,7 @@ __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, u
     }
 }
 
-template <bool PER, bool TPM, int OPEN, bool POT>
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, uint32_t K) {
     const int lane = threadIdx.x & 63;
     const uint32_t nu = *A.nuniq;
@@ -616,7 +661,7 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
     bool live = slot < chunk_end;
     int32_t G0 = 0, G1 = 0, G2 = 0;
     float xr0 = 0.f, xr1 = 0.f, xr2 = 0.f, alpha_an = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f,
-          pot = 0.f;
+          pot = 0.f, hi = 0.f;
     uint32_t self = 0, nint = 0, e = 0;
     auto start = [&](uint32_t sl) {
         const uint32_t s = A.act[sl];
@@ -633,6 +678,8 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
         alpha_an = 0.f;
         if (OPEN == TPM_OPEN_REL)
             alpha_an = A.falpha * (float)A.anorm[A.perm[s]];
+        if (MIXED)
+            hi = (float)A.hs[s];
         a0 = a1 = a2 = pot = 0.f;
         nint = 0;
         e = 0;
@@ -642,6 +689,7 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
     while (__ballot(live)) {
         if (live) {
             const Rec32 r = R[e];
+            const float he = MIXED ? ((const float *)A.eh)[e] : 0.0f;
             const int32_t cm = r.cx_meta;
             const float c0 = fmaf((float)wrapi<PER>((cm & 0x3fffff) - G0), A.fu, -xr0);
             const float c1 = fmaf((float)wrapi<PER>(r.cy - G1), A.fu, -xr1);
@@ -666,10 +714,12 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
                 crit = r.gm * L2 > alpha_an * (dd * dd);
             const float lim = 0.6f * L;
             const bool box = fabsf(c0) < lim && fabsf(c1) < lim && fabsf(c2) < lim;
-            const bool open = !part && !discard && (crit || box);
+            const bool soft_open = MIXED && hi < he && dd < he * he;
+            const bool open = !part && !discard && (crit || box || soft_open);
             const bool inter = part ? (e != self && (!TPM || dd < A.frc2)) : (!discard && !open);
             if (inter) {
-                interact32<TPM, POT>(A, r.gm, d0, d1, d2, dd, a0, a1, a2, pot);
+                interact32<TPM, POT, MIXED>(A, r.gm, d0, d1, d2, dd, hi > he ? hi : he, a0, a1,
+                                            a2, pot);
                 nint++;
             }
             e = (part || open) ? e + 1u : r.skip;
@@ -690,14 +740,14 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
     }
 }
 
-template <bool PER, bool TPM, int OPEN, bool POT>
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_walk64i(const WalkArgs A, uint32_t K) {
-    walk_lanes64<PER, TPM, OPEN, POT>(A, wave_id(), K);
+    walk_lanes64<PER, TPM, OPEN, POT, MIXED>(A, wave_id(), K);
 }
 
-template <bool PER, bool TPM, int OPEN, bool POT>
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_walk32i(const WalkArgs A, uint32_t K) {
-    walk_lanes32<PER, TPM, OPEN, POT>(A, wave_id(), K);
+    walk_lanes32<PER, TPM, OPEN, POT, MIXED>(A, wave_id(), K);
 }
 
 // ---- active set -> slots in curve order --------------------------------------
@@ -796,34 +846,43 @@ struct Launch {
     unsigned blocks;
 };
 
-template <bool PER, bool TPM, int OPEN, bool POT>
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 void launch_walk(const WalkArgs &A, const Launch &L, hipStream_t st) {
     if (L.lanes) {
         if (L.fp32)
-            k_walk32i<PER, TPM, OPEN, POT><<<L.blocks, kBlock, 0, st>>>(A, L.K);
+            k_walk32i<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A, L.K);
         else
-            k_walk64i<PER, TPM, OPEN, POT><<<L.blocks, kBlock, 0, st>>>(A, L.K);
+            k_walk64i<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A, L.K);
     } else {
         if (L.fp32)
-            k_walk32<PER, TPM, OPEN, POT><<<L.blocks, kBlock, 0, st>>>(A);
+            k_walk32<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A);
         else
-            k_walk64<PER, TPM, OPEN, POT><<<L.blocks, kBlock, 0, st>>>(A);
+            k_walk64<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A);
+    }
+}
+
+template <bool PER, bool TPM, bool MIXED>
+void dispatch_open_pot(const WalkArgs &A, const Launch &L, int open, bool pot, hipStream_t st) {
+    if (open == TPM_OPEN_BH) {
+        if (pot)
+            launch_walk<PER, TPM, TPM_OPEN_BH, true, MIXED>(A, L, st);
+        else
+            launch_walk<PER, TPM, TPM_OPEN_BH, false, MIXED>(A, L, st);
+    } else {
+        if (pot)
+            launch_walk<PER, TPM, TPM_OPEN_REL, true, MIXED>(A, L, st);
+        else
+            launch_walk<PER, TPM, TPM_OPEN_REL, false, MIXED>(A, L, st);
     }
 }
 
 template <bool PER, bool TPM>
-void dispatch_open_pot(const WalkArgs &A, const Launch &L, int open, bool pot, hipStream_t st) {
-    if (open == TPM_OPEN_BH) {
-        if (pot)
-            launch_walk<PER, TPM, TPM_OPEN_BH, true>(A, L, st);
-        else
-            launch_walk<PER, TPM, TPM_OPEN_BH, false>(A, L, st);
-    } else {
-        if (pot)
-            launch_walk<PER, TPM, TPM_OPEN_REL, true>(A, L, st);
-        else
-            launch_walk<PER, TPM, TPM_OPEN_REL, false>(A, L, st);
-    }
+void dispatch_mixed(const WalkArgs &A, const Launch &L, int open, bool pot, bool mixed,
+                    hipStream_t st) {
+    if (mixed)
+        dispatch_open_pot<PER, TPM, true>(A, L, open, pot, st);
+    else
+        dispatch_open_pot<PER, TPM, false>(A, L, open, pot, st);
 }
 
 }  // namespace
@@ -905,7 +964,12 @@ static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
     A.box = P.periodic ? P.box_size : 0.0;
     A.half = 0.5 * A.box;
     const bool tpm_on = P.pm_grid > 0;
-    const double rs = tpm_on ? P.asmth * P.box_size / P.pm_grid : 1.0;
+    // split scale r_s = asmth x mesh spacing; the isolated mesh spans the
+    // root cube in pm_grid - 4 cells
+    double rs = 1.0;
+    if (tpm_on)
+        rs = P.periodic ? P.asmth * P.box_size / P.pm_grid
+                        : P.asmth * (c->frame_host.L / (P.pm_grid - 4));
     const double rcut = tpm_on ? P.rcut * rs : 0.0;
     A.G = P.G;
     A.theta2 = P.theta * P.theta;
@@ -930,6 +994,8 @@ static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
     A.L2r = A.L * A.L;
     A.limr = 0.6 * A.L;
     A.hlr = 0.5 * A.L;
+    A.hs = c->mixed ? (const double *)c->hs.p : nullptr;
+    A.eh = c->mixed ? (fp32 ? c->eh32.p : c->eh64.p) : nullptr;
     A.fL2r = A.fL * A.fL;
     A.flimr = 0.6f * A.fL;
     A.fhlr = 0.5f * A.fL;
@@ -971,17 +1037,13 @@ int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const
     const bool want_pot = pot != nullptr && P.want_potential;
     const int tkind = opening == TPM_OPEN_REL ? TPM_TIMER_WALK_REL : TPM_TIMER_WALK;
     TPM_TRY(timer_begin(c, tkind));
-    if (P.periodic) {
-        if (tpm_on)
-            dispatch_open_pot<true, true>(A, LA, opening, want_pot, st);
-        else
-            dispatch_open_pot<true, false>(A, LA, opening, want_pot, st);
-    } else {
-        if (tpm_on)
-            dispatch_open_pot<false, true>(A, LA, opening, want_pot, st);
-        else
-            dispatch_open_pot<false, false>(A, LA, opening, want_pot, st);
-    }
+    // periodic boxes always carry the mesh (validated at creation)
+    if (P.periodic)
+        dispatch_mixed<true, true>(A, LA, opening, want_pot, c->mixed, st);
+    else if (tpm_on)
+        dispatch_mixed<false, true>(A, LA, opening, want_pot, c->mixed, st);
+    else
+        dispatch_mixed<false, false>(A, LA, opening, want_pot, c->mixed, st);
     TPM_LAUNCHED(c, "k_walk");
     TPM_TRY(timer_end(c, tkind));
     const unsigned ob = grid_for(n_act, kBlock);
@@ -1014,23 +1076,34 @@ namespace {
 
 struct BatchReq {
     WalkArgs A;
-    uint32_t variant;  // bit 0: relative criterion, bit 1: periodic TreePM, bit 2: lanes
+    uint32_t variant;  // bit 0 relative criterion, 1 TreePM, 2 lanes, 3 periodic,
+                       // 4 individual softening
     uint32_t first;    // first work item of the request
 };
 
-template <bool FP32, bool PER, bool TPM, int OPEN>
+template <bool FP32, bool PER, bool TPM, int OPEN, bool MIXED>
 __device__ __forceinline__ void batch_group(const WalkArgs &A, uint32_t g, bool lanes) {
     if (lanes) {
         if (FP32)
-            walk_lanes32<PER, TPM, OPEN, false>(A, g, 1u);
+            walk_lanes32<PER, TPM, OPEN, false, MIXED>(A, g, 1u);
         else
-            walk_lanes64<PER, TPM, OPEN, false>(A, g, 1u);
+            walk_lanes64<PER, TPM, OPEN, false, MIXED>(A, g, 1u);
     } else {
         if (FP32)
-            walk_group32<PER, TPM, OPEN, false>(A, g);
+            walk_group32<PER, TPM, OPEN, false, MIXED>(A, g);
         else
-            walk_group64<PER, TPM, OPEN, false>(A, g);
+            walk_group64<PER, TPM, OPEN, false, MIXED>(A, g);
     }
+}
+
+template <bool FP32, int OPEN, bool MIXED>
+__device__ __forceinline__ void batch_geometry(const BatchReq &R, uint32_t g, bool lanes) {
+    if (R.variant & 8u)  // periodic box (always with the mesh)
+        batch_group<FP32, true, true, OPEN, MIXED>(R.A, g, lanes);
+    else if (R.variant & 2u)  // isolated TreePM
+        batch_group<FP32, false, true, OPEN, MIXED>(R.A, g, lanes);
+    else
+        batch_group<FP32, false, false, OPEN, MIXED>(R.A, g, lanes);
 }
 
 template <bool FP32>
@@ -1056,11 +1129,17 @@ __global__ __launch_bounds__(kBlock) void k_walk_batch(const BatchReq *__restric
         const BatchReq &R = reqs[lo];
         const uint32_t g = item - R.first;
         const bool lanes = (R.variant & 4u) != 0;
-        switch (R.variant & 3u) {
-        case 0: batch_group<FP32, false, false, TPM_OPEN_BH>(R.A, g, lanes); break;
-        case 1: batch_group<FP32, false, false, TPM_OPEN_REL>(R.A, g, lanes); break;
-        case 2: batch_group<FP32, true, true, TPM_OPEN_BH>(R.A, g, lanes); break;
-        default: batch_group<FP32, true, true, TPM_OPEN_REL>(R.A, g, lanes); break;
+        const bool rel = (R.variant & 1u) != 0, mixed = (R.variant & 16u) != 0;
+        if (rel) {
+            if (mixed)
+                batch_geometry<FP32, TPM_OPEN_REL, true>(R, g, lanes);
+            else
+                batch_geometry<FP32, TPM_OPEN_REL, false>(R, g, lanes);
+        } else {
+            if (mixed)
+                batch_geometry<FP32, TPM_OPEN_BH, true>(R, g, lanes);
+            else
+                batch_geometry<FP32, TPM_OPEN_BH, false>(R, g, lanes);
         }
     }
 }
@@ -1215,7 +1294,8 @@ int tpm_batch_launch(tpm_batch *b) {
         R = BatchReq{};
         fill_args(c, p.anorm, R.A);
         R.variant = (p.opening == TPM_OPEN_REL ? 1u : 0u) | (c->P.pm_grid > 0 ? 2u : 0u) |
-                    (use_lanes(c, p.n_act) ? 4u : 0u);
+                    (use_lanes(c, p.n_act) ? 4u : 0u) | (c->P.periodic ? 8u : 0u) |
+                    (c->mixed ? 16u : 0u);
         R.first = items[which];
         const int64_t groups = p.n_act > 0 ? (std::min<int64_t>(p.n_act, c->n) + 63) / 64 : 0;
         items[which] += (uint32_t)groups;

@@ -37,10 +37,14 @@ def test_parameter_validation_on_host():
     L = B.lib()
     ok = B.make_params(eps=0.01)
     assert L.tpm_bytes_needed(ctypes.byref(ok), 1000) > 0
+    iso = B.make_params(eps=0.01, pm_grid=64)  # isolated TreePM
+    assert L.tpm_bytes_needed(ctypes.byref(iso), 1000) > L.tpm_bytes_needed(ctypes.byref(ok), 1000)
     bad = [dict(eps=0.0), dict(eps=0.01, alpha=0.0), dict(eps=0.01, theta=-1.0),
            dict(eps=0.01, periodic=True, box_size=10.0),                 # no mesh
            dict(eps=0.01, periodic=True, box_size=10.0, pm_grid=48),     # not 2^k
-           dict(eps=0.01, pm_grid=64),                                   # isolated PM
+           dict(eps=0.01, pm_grid=512),                                  # isolated > 256
+           dict(eps=0.01, pm_grid=8),                                    # isolated < 16
+           dict(eps=0.01, pm_grid=64, asmth=0.0),                        # no split scale
            dict(eps=0.01, shift=(1.0, 0.0, 0.0)),
            dict(eps=0.01, periodic=True, box_size=10.0, pm_grid=8, asmth=2.0, rcut=4.5)]
     for kw in bad:

@@ -1,0 +1,148 @@
+"""Time integration on the GPU (Sec. 7.1-7.3) against the oracle's
+integrators driven by the oracle's tree (and mesh) forces: the same event
+sequence, so FP64 trajectories agree to the force parity (1e-10 per
+evaluation) compounded over the steps, and the final time bins are equal."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import integrate as OI
+from paper_1909_04667_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=_dev())
+
+
+def _state(n, seed, vscale=0.3):
+    p = W.plummer(n, seed)
+    x = np.stack([p.x, p.y, p.z])
+    v = vscale * np.random.default_rng(seed + 100).normal(size=x.shape)
+    return x, v
+
+
+def _tree_force(eps, mass=None, eps_arr=None, **kw):
+    P = O.make_params(eps=eps, theta=0.5, **{k: v for k, v in kw.items()
+                                             if k in ("periodic", "box", "treepm", "rs",
+                                                      "rcut")})
+
+    def force(x, targets):
+        T = O.Tree(x[0], x[1], x[2], mass=mass, periodic=kw.get("periodic", False),
+                   box=kw.get("box", 0.0), eps=eps_arr)
+        a, _, _ = T.walk(P, targets=targets)
+        if kw.get("pm_grid"):
+            apm, _ = O.pm(x[0], x[1], x[2], mass, kw["box"], kw["pm_grid"], 1.0, kw["rs"],
+                          targets=targets, want_pot=False)
+            a = a + apm
+        return a
+    return force
+
+
+def _close(g, o, tol):
+    return np.abs(g - o).max() <= tol * np.abs(o).max()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_block_leapfrog_matches_oracle(mixed):
+    from paper_1909_04667_amd import integrate as GI
+    x, v = _state(2048, 1)
+    eps_arr = 0.02 * np.exp(np.random.default_rng(2).normal(0, 0.5, x.shape[1])) if mixed \
+        else None
+    kw = dict(C=0.02, dt_max=0.04, max_bin=4, n_max_steps=2)
+    xo, vo, st = OI.leapfrog_bins(x, v, _tree_force(0.02, eps_arr=eps_arr),
+                                  eps=eps_arr if mixed else 0.02, **kw)
+    integ = GI.BlockLeapfrog((_t(x[0]), _t(x[1]), _t(x[2])), (_t(v[0]), _t(v[1]), _t(v[2])),
+                             None, None if eps_arr is None else _t(eps_arr),  # mass, softening
+                             C=kw["C"], dt_max=kw["dt_max"], max_bin=kw["max_bin"],
+                             precision="fp64", eps=0.02)
+    stats = integ.run(kw["n_max_steps"])
+    assert len(np.unique(st["final_bins"])) >= 3
+    assert np.array_equal(integ.bins.cpu().numpy(), st["final_bins"])
+    xg = np.stack([t.cpu().numpy() for t in (integ.x, integ.y, integ.z)])
+    vg = np.stack([t.cpu().numpy() for t in (integ.vx, integ.vy, integ.vz)])
+    assert _close(xg, xo, 1e-10) and _close(vg, vo, 1e-8), \
+        (np.abs(xg - xo).max(), np.abs(vg - vo).max())
+    assert stats["force_evals"] == st["force_evals"]
+
+
+def test_block_leapfrog_periodic_treepm_matches_oracle():
+    from paper_1909_04667_amd import integrate as GI
+    p = W.zeldovich_box(16, 100.0, 3)
+    x = np.stack([p.x, p.y, p.z])
+    v = np.random.default_rng(4).normal(0, 0.5, x.shape)
+    box, ng = 100.0, 32
+    rs = 1.25 * box / ng
+    eps = box / 800
+    kw = dict(C=0.05, dt_max=0.5, max_bin=3, n_max_steps=1)
+    force = _tree_force(eps, periodic=True, box=box, treepm=True, rs=rs, rcut=4.5 * rs,
+                        pm_grid=ng)
+    xo, vo, st = OI.leapfrog_bins(x, v, force, eps=eps, box=box, **kw)
+    integ = GI.BlockLeapfrog((_t(x[0]), _t(x[1]), _t(x[2])), (_t(v[0]), _t(v[1]), _t(v[2])),
+                             C=kw["C"], dt_max=kw["dt_max"], max_bin=kw["max_bin"],
+                             precision="fp64", eps=eps, periodic=True, box_size=box,
+                             pm_grid=ng)
+    integ.run(kw["n_max_steps"])
+    assert np.array_equal(integ.bins.cpu().numpy(), st["final_bins"])
+    xg = np.stack([t.cpu().numpy() for t in (integ.x, integ.y, integ.z)])
+    vg = np.stack([t.cpu().numpy() for t in (integ.vx, integ.vy, integ.vz)])
+    assert _close(xg, xo, 1e-10) and _close(vg, vo, 1e-8)
+
+
+def test_hierarchical_matches_oracle():
+    from paper_1909_04667_amd import integrate as GI
+    x, v = _state(1024, 5, 0.4)
+    m = np.random.default_rng(6).uniform(0.5, 1.5, x.shape[1]) / x.shape[1]
+    P = O.make_params(eps=0.02, theta=0.5)
+
+    def force_sub(xx, members):
+        T = O.Tree(xx[0, members], xx[1, members], xx[2, members], mass=m[members])
+        a, _, _ = T.walk(P)
+        return a
+    kw = dict(C=0.02, dt_max=0.04, max_bin=3, n_max_steps=1)
+    xo, vo, st = OI.hierarchical(x, v, force_sub, eps=0.02, **kw)
+    integ = GI.Hierarchical((_t(x[0]), _t(x[1]), _t(x[2])), (_t(v[0]), _t(v[1]), _t(v[2])),
+                            _t(m), C=kw["C"], dt_max=kw["dt_max"], max_bin=kw["max_bin"],
+                            precision="fp64", eps=0.02)
+    stats = integ.run(kw["n_max_steps"])
+    assert stats["levels"] == st["levels"] >= 3
+    xg = np.stack([t.cpu().numpy() for t in (integ.x, integ.y, integ.z)])
+    vg = np.stack([t.cpu().numpy() for t in (integ.vx, integ.vy, integ.vz)])
+    assert _close(xg, xo, 1e-10) and _close(vg, vo, 1e-8), \
+        (np.abs(xg - xo).max(), np.abs(vg - vo).max())
+
+
+def test_fp32_integrators_run_and_track_fp64():
+    from paper_1909_04667_amd import integrate as GI
+    x, v = _state(4096, 7)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        integ = GI.BlockLeapfrog((_t(x[0]), _t(x[1]), _t(x[2])),
+                                 (_t(v[0]), _t(v[1]), _t(v[2])), C=1e6, dt_max=0.01,
+                                 max_bin=2, precision=prec, eps=0.02)
+        integ.run(3)
+        out[prec] = np.stack([t.cpu().numpy() for t in (integ.x, integ.y, integ.z)])
+    assert np.isfinite(out["fp32"]).all()
+    assert _close(out["fp32"], out["fp64"], 1e-5)
+
+
+def test_kernel_index_errors_are_reported():
+    from paper_1909_04667_amd import binding as B
+    from paper_1909_04667_amd import integrate as GI
+    x, v = _state(256, 8)
+    integ = GI.BlockLeapfrog((_t(x[0]), _t(x[1]), _t(x[2])), (_t(v[0]), _t(v[1]), _t(v[2])),
+                             C=1e6, dt_max=0.01, max_bin=0, precision="fp64", eps=0.02)
+    bad = torch.tensor([0, 256, -3], dtype=torch.int32, device=_dev())
+    acc = torch.zeros((3, 3), dtype=torch.float64, device=_dev())
+    integ._kick(bad, acc, dt=0.1)
+    with pytest.raises(B.TreePMError) as ei:
+        integ.ctx.check()
+    assert ei.value.code == B.TPM_EINDEX

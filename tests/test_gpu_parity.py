@@ -35,16 +35,28 @@ def _t(a, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=_dev())
 
 
+def _indiv_eps(n, eps, seed):
+    """Individual softening lengths around eps (log-normal spread)."""
+    return eps * np.exp(np.random.default_rng(seed).normal(0.0, 0.7, n))
+
+
 def _ctx(**kw):
     from paper_1909_04667_amd import binding as B
+    kw.pop("indiv_eps", None)
     return B.Context(**kw)
 
 
-def _build(ctx, p):
+def _build(ctx, p, eps=None):
     x, y, z = _t(p.x), _t(p.y), _t(p.z)
     m = None if p.mass is None else _t(p.mass)
-    ctx.build_tree(x, y, z, m)
+    ctx.build_tree(x, y, z, m, eps=None if eps is None else _t(eps))
     return x, y, z, m
+
+
+def _case_eps(p, kw):
+    """The individual softenings a force case asks for (or None)."""
+    seed = kw.get("indiv_eps")
+    return None if seed is None else _indiv_eps(p.n, kw["eps"], seed)
 
 
 def rel_err(a, ref, floor_frac=1e-3):
@@ -106,11 +118,14 @@ def test_tree_bit_exact(case):
     _tree_equal(g, T)
 
 
-def _oracle_params(ctx_kw, opening, eps, theta=0.5, alpha=0.0025, pot=False):
+def _oracle_params(ctx_kw, opening, eps, theta=0.5, alpha=0.0025, pot=False, frame=None):
     periodic = ctx_kw.get("periodic", False)
     box = ctx_kw.get("box_size", 0.0)
     ng = ctx_kw.get("pm_grid", 0)
-    rs = ctx_kw.get("asmth", 1.25) * box / ng if ng else 0.0
+    if ng and not periodic:  # isolated mesh over the root cube of the build
+        _, rs = O.isolated_scale(frame[3], ng, ctx_kw.get("asmth", 1.25))
+    else:
+        rs = ctx_kw.get("asmth", 1.25) * box / ng if ng else 0.0
     return O.make_params(periodic=periodic, box=box, eps=eps, opening=opening, theta=theta,
                          alpha=alpha, treepm=ng > 0, rs=rs,
                          rcut=ctx_kw.get("rcut", 4.5) * rs if ng else 0.0, want_pot=pot)
@@ -131,11 +146,20 @@ FORCE_CASES = {
                            shift=(0.2, 0.6, 0.95)), "rel"),
     "box_clustered": (lambda: W.lognormal_box(16, 100.0, 5),
                       dict(eps=100.0 / 800, periodic=True, box_size=100.0, pm_grid=64), "bh"),
+    "iso_plummer_bh": (lambda: W.plummer(4096, 1), dict(eps=0.01, pm_grid=32), "bh"),
+    "iso_hernquist_rel": (lambda: W.hernquist(1 << 13, 4),
+                          dict(eps=0.005, pm_grid=64, shift=(0.3, 0.1, 0.8)), "rel"),
+    "mixed_plummer_bh": (lambda: W.plummer(4096, 11), dict(eps=0.01, indiv_eps=1), "bh"),
+    "mixed_hernquist_rel": (lambda: W.hernquist(1 << 13, 12),
+                            dict(eps=0.005, theta=0.6, indiv_eps=2), "rel"),
+    "mixed_box_rel": (lambda: W.lognormal_box(16, 100.0, 13),
+                      dict(eps=100.0 / 800, periodic=True, box_size=100.0, pm_grid=32,
+                           indiv_eps=3), "rel"),
 }
 
 
 def _oracle_anorm(p, kw, T):
-    P = _oracle_params(kw, "bh", kw["eps"], kw.get("theta", 0.5))
+    P = _oracle_params(kw, "bh", kw["eps"], kw.get("theta", 0.5), frame=T.frame)
     a, _, _ = T.walk(P)
     return np.linalg.norm(a, axis=0)
 
@@ -144,10 +168,11 @@ def _oracle_anorm(p, kw, T):
 def test_fp64_forces_match_oracle(case):
     mk, kw, opening = FORCE_CASES[case]
     p = mk()
+    eps = _case_eps(p, kw)
     ctx = _ctx(want_potential=True, **kw)
-    _build(ctx, p)
+    _build(ctx, p, eps)
     T = O.Tree(p.x, p.y, p.z, mass=p.mass, periodic=kw.get("periodic", False),
-               box=kw.get("box_size", 0.0), shift=kw.get("shift", (0.0, 0.0, 0.0)))
+               box=kw.get("box_size", 0.0), shift=kw.get("shift", (0.0, 0.0, 0.0)), eps=eps)
     an = _oracle_anorm(p, kw, T) if opening == "rel" else None
     # all particles active, in a shuffled caller order with a ragged tail
     order = np.random.default_rng(11).permutation(p.n)[: p.n - 13 if p.n > 100 else p.n]
@@ -156,7 +181,7 @@ def test_fp64_forces_match_oracle(case):
     acc, pot = ctx.compute_forces(idx, opening, a_old_norm=None if an is None else _t(an),
                                   n_interactions=nint)
     ctx.check()
-    P = _oracle_params(kw, opening, kw["eps"], kw.get("theta", 0.5), pot=True)
+    P = _oracle_params(kw, opening, kw["eps"], kw.get("theta", 0.5), pot=True, frame=T.frame)
     ao, po, no = T.walk(P, targets=order, anorm=an)
     ag = acc.cpu().numpy()
     err = rel_err(ag, ao)
@@ -174,10 +199,11 @@ def test_walk_variants_identical(case, prec, monkeypatch):
     the full set and on a sparse subset (ragged last wavefront)."""
     mk, kw, opening = FORCE_CASES[case]
     p = mk()
+    eps = _case_eps(p, kw)
     an = None
     if opening == "rel":
         c0 = _ctx(precision="fp64", **kw)
-        _build(c0, p)
+        _build(c0, p, eps)
         a0, _ = c0.compute_forces(_t(np.arange(p.n), torch.int32), "bh")
         an = torch.linalg.norm(a0, dim=0).contiguous()
     sets = [np.arange(p.n), np.random.default_rng(17).choice(p.n, max(1, p.n // 7 + 5),
@@ -186,7 +212,7 @@ def test_walk_variants_identical(case, prec, monkeypatch):
     for mode in ("1", "2"):
         monkeypatch.setenv("TPM_WALK_MODE", mode)
         ctx = _ctx(precision=prec, want_potential=True, **kw)
-        _build(ctx, p)
+        _build(ctx, p, eps)
         res = []
         for ids in sets:
             idx = _t(ids, torch.int32)
@@ -201,19 +227,21 @@ def test_walk_variants_identical(case, prec, monkeypatch):
 
 
 @pytest.mark.parametrize("case", ["plummer_bh", "plummer_rel", "box_bh", "box_clustered",
-                                  "hernquist_bh"])
+                                  "hernquist_bh", "mixed_hernquist_rel", "mixed_box_rel",
+                                  "iso_plummer_bh"])
 def test_fp32_against_fp64(case):
     mk, kw, opening = FORCE_CASES[case]
     p = mk()
+    eps = _case_eps(p, kw)
     res = {}
     an = None
     for prec in ("fp64", "fp32"):
         ctx = _ctx(precision=prec, **kw)
-        _build(ctx, p)
+        _build(ctx, p, eps)
         idx = _t(np.arange(p.n), torch.int32)
         if opening == "rel" and an is None:
             c64 = _ctx(precision="fp64", **kw)
-            _build(c64, p)
+            _build(c64, p, eps)
             a0, _ = c64.compute_forces(idx, "bh")
             an = torch.linalg.norm(a0, dim=0).contiguous()
         acc, _ = ctx.compute_forces(idx, opening, a_old_norm=an)
@@ -443,3 +471,129 @@ def test_pm_512_converges_to_ewald_long_range():
         ctx.check()
         err[ng] = np.percentile(rel_err(a.cpu().numpy(), lr), 50)
     assert err[512] < 0.01 and err[512] < 0.5 * err[256], err
+
+
+# ---- isolated systems: zero-padded mesh (Sec. 3.3) ---------------------------
+
+ISO_CASES = {
+    "plummer_32": (lambda: W.plummer(4096, 1), dict(eps=0.01, pm_grid=32)),
+    "masses_16_shift": (lambda: W.Particles(*np.random.default_rng(8).uniform(-1, 1, (3, 3000)),
+                                            mass=np.random.default_rng(9).uniform(0.1, 2, 3000)),
+                        dict(eps=0.01, pm_grid=16, shift=(0.4, 0.9, 0.05))),
+    "hernquist_64": (lambda: W.hernquist(1 << 14, 2), dict(eps=0.005, pm_grid=64)),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", sorted(ISO_CASES))
+def test_isolated_pm_matches_oracle(case, prec):
+    mk, kw = ISO_CASES[case]
+    p = mk()
+    ctx = _ctx(precision=prec, want_potential=True, **kw)
+    _build(ctx, p)
+    fr = ctx.export_tree()["frame"]
+    order = np.random.default_rng(5).permutation(p.n)
+    acc, pot = ctx.pm_long_range(_t(order, torch.int32))
+    ctx.check()
+    ao, po = O.pm_isolated(p.x, p.y, p.z, p.mass, fr, kw["pm_grid"], 1.0, 1.25,
+                           targets=order)
+    e = rel_err(acc.double().cpu().numpy(), ao)
+    ep = np.abs(pot.double().cpu().numpy() - po) / np.abs(po).max()
+    if prec == "fp64":
+        assert e.max() <= 1e-9, e.max()
+        assert ep.max() <= 1e-11, ep.max()
+    else:
+        u = 2.0 ** -24 * math.log2((2 * kw["pm_grid"]) ** 3)
+        assert np.percentile(e, 99) <= 20 * u and e.max() <= 200 * u, np.percentile(e, [99, 100])
+        assert ep.max() <= 20 * u
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_isolated_treepm_total_follows_direct(prec):
+    """Tree (short range, theta = 0.5) plus mesh against the direct Newtonian
+    sum; and the mesh conserves momentum on the GPU too."""
+    p = W.plummer(8192, 3)
+    ctx = _ctx(precision=prec, eps=0.01, pm_grid=64)
+    _build(ctx, p)
+    idx = _t(np.arange(p.n), torch.int32)
+    at, _ = ctx.compute_forces(idx, "bh")
+    apm, _ = ctx.pm_long_range(idx)
+    ctx.check()
+    tot = (at + apm).double().cpu().numpy()
+    ref, _ = O.direct(p.x, p.y, p.z, None, O.make_params(eps=0.01))
+    e = rel_err(tot, ref)
+    assert np.percentile(e, 50) <= 0.005 and np.percentile(e, 99) <= 0.03, \
+        np.percentile(e, [50, 99])
+    a_pm = apm.double().cpu().numpy()
+    mom = np.abs(a_pm.sum(axis=1)).max() / np.linalg.norm(a_pm, axis=0).sum()
+    assert mom <= (1e-12 if prec == "fp64" else 1e-5), mom
+
+
+@pytest.mark.slow
+def test_isolated_hernquist_2p20_sampled():
+    """Full-size isolated TreePM (2^20 particles, 128-cell mesh padded to
+    256^3): mesh and relative-criterion tree walk at sampled targets."""
+    p = W.hernquist(1 << 20, 2)
+    kw = dict(eps=0.005, pm_grid=128)
+    ctx = _ctx(precision="fp64", **kw)
+    _build(ctx, p)
+    fr = ctx.export_tree()["frame"]
+    samp = np.sort(np.random.default_rng(1).choice(p.n, 2048, replace=False))
+    idx = _t(samp, torch.int32)
+    apm, _ = ctx.pm_long_range(idx)
+    ao, _ = O.pm_isolated(p.x, p.y, p.z, None, fr, 128, 1.0, 1.25, targets=samp,
+                          want_pot=False)
+    assert rel_err(apm.cpu().numpy(), ao).max() <= 1e-9
+    T = O.Tree(p.x, p.y, p.z)
+    P = _oracle_params(kw, "bh", 0.005, frame=T.frame)
+    a_bh, _, _ = T.walk(P, targets=samp)
+    an = np.zeros(p.n)
+    an[samp] = np.linalg.norm(a_bh + ao, axis=0)
+    nint = torch.empty(samp.size, dtype=torch.int32, device=_dev())
+    ag, _ = ctx.compute_forces(idx, "rel", a_old_norm=_t(an), n_interactions=nint)
+    ctx.check()
+    Pr = _oracle_params(kw, "rel", 0.005, frame=T.frame)
+    ar, _, nr = T.walk(Pr, targets=samp, anorm=an)
+    assert rel_err(ag.cpu().numpy(), ar).max() <= 1e-10
+    assert np.array_equal(nint.cpu().numpy().astype(np.int64), nr)
+
+
+def test_individual_softening_rejects_bad_values():
+    from paper_1909_04667_amd import binding as B
+    p = W.plummer(1000, 14)
+    ctx = _ctx(eps=0.01)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        e = np.full(p.n, 0.01)
+        e[517] = bad
+        with pytest.raises(B.TreePMError) as ei:
+            _build(ctx, p, e)
+        assert ei.value.code == B.TPM_EINVAL
+    # the context recovers: a good build and a walk succeed afterwards
+    _build(ctx, p, np.full(p.n, 0.01))
+    a, _ = ctx.compute_forces(_t(np.arange(p.n), torch.int32), "bh")
+    ctx.check()
+    ref, _ = ctx.compute_forces(_t(np.arange(p.n), torch.int32), "bh")
+    assert torch.equal(a, ref)
+
+
+def test_equal_individual_softening_is_uniform_on_gpu():
+    """Equal individual softenings take the mixed code path and must give
+    the uniform path's results: bit for bit in FP64 (the same operations on
+    the same support), to FP32 rounding in FP32 (there the uniform path's
+    1/h and h^2 are rounded from double, the mixed path's formed in float)."""
+    p = W.hernquist(1 << 13, 15)
+    idx = None
+    for prec in ("fp64", "fp32"):
+        out = []
+        for eps in (None, np.full(p.n, 0.005)):
+            ctx = _ctx(precision=prec, eps=0.005, want_potential=True)
+            _build(ctx, p, eps)
+            idx = _t(np.arange(p.n), torch.int32)
+            a, pot = ctx.compute_forces(idx, "bh")
+            ctx.check()
+            out.append((a.cpu(), pot.cpu()))
+        if prec == "fp64":
+            assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+        else:
+            e = rel_err(out[1][0].double().numpy(), out[0][0].double().numpy())
+            assert e.max() <= 1e-5, e.max()
