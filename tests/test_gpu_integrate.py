@@ -57,7 +57,7 @@ def test_block_leapfrog_matches_oracle(mixed):
     x, v = _state(2048, 1)
     eps_arr = 0.02 * np.exp(np.random.default_rng(2).normal(0, 0.5, x.shape[1])) if mixed \
         else None
-    kw = dict(C=0.02, dt_max=0.04, max_bin=4, n_max_steps=2)
+    kw = dict(C=0.02, dt_max=0.16, max_bin=4, n_max_steps=1)  # bins 0-3 occupied
     xo, vo, st = OI.leapfrog_bins(x, v, _tree_force(0.02, eps_arr=eps_arr),
                                   eps=eps_arr if mixed else 0.02, **kw)
     integ = GI.BlockLeapfrog((_t(x[0]), _t(x[1]), _t(x[2])), (_t(v[0]), _t(v[1]), _t(v[2])),
@@ -107,7 +107,7 @@ def test_hierarchical_matches_oracle():
         T = O.Tree(xx[0, members], xx[1, members], xx[2, members], mass=m[members])
         a, _, _ = T.walk(P)
         return a
-    kw = dict(C=0.02, dt_max=0.04, max_bin=3, n_max_steps=1)
+    kw = dict(C=0.02, dt_max=0.16, max_bin=3, n_max_steps=1)
     xo, vo, st = OI.hierarchical(x, v, force_sub, eps=0.02, **kw)
     integ = GI.Hierarchical((_t(x[0]), _t(x[1]), _t(x[2])), (_t(v[0]), _t(v[1]), _t(v[2])),
                             _t(m), C=kw["C"], dt_max=kw["dt_max"], max_bin=kw["max_bin"],
