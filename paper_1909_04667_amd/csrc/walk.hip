@@ -13,6 +13,7 @@
 // the FP64 path reproduces a sequential FP64 walk bit for bit apart from the
 // last bits of erfc/exp.
 #include "tpm_internal.h"
+#include "erfc_poly.h"
 
 #include <algorithm>
 #include <new>
@@ -61,6 +62,20 @@ __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_in
 
 // ---- FP64 arithmetic (fixed operation order, explicit fma) -------------------
 
+// Scaled complementary error function exp(x^2) erfc(x) = t g(t), t = 4/(4+x),
+// g a degree-20 polynomial in s = (4 - x)/(4 + x) (coefficients in
+// erfc_poly.h, relative error below 5e-15 for x >= 0): no branches, and
+// exp(-x^2) is shared with the Gaussian term of the short-range factor.
+__device__ __forceinline__ double erfc_scaled64(double x) {
+    const double rd = 1.0 / (4.0 + x);
+    const double sv = (4.0 - x) * rd;
+    double g = kErfcPoly[kErfcDegree];
+#pragma unroll
+    for (int j = kErfcDegree - 1; j >= 0; j--)
+        g = fma(g, sv, kErfcPoly[j]);
+    return (4.0 * rd) * g;
+}
+
 __device__ __forceinline__ double spline_g64(double u) {
     if (u < 0.5) {
         double u2 = u * u;
@@ -106,9 +121,11 @@ __device__ __forceinline__ void interact64(const WalkArgs &A, double m, double d
     }
     if (TPM) {
         const double x = r * A.inv2rs;
-        fac = fac * (erfc(x) + (x * 1.1283791670955126) * exp(-(x * x)));
+        const double gx = exp(-(x * x));
+        const double ec = gx * erfc_scaled64(x);
+        fac = fac * (ec + (x * 1.1283791670955126) * gx);
         if (POT)
-            phi = phi * erfc(x);
+            phi = phi * ec;
     }
     a0 = fma(fac, d0, a0);
     a1 = fma(fac, d1, a1);
@@ -177,8 +194,9 @@ __device__ __forceinline__ void interact64_wave(const WalkArgs &A, bool inter, d
     if (TPM) {
         // lanes that do not interact take a harmless argument
         const double x = inter ? r * A.inv2rs : 1.0;
-        const double ec = erfc(x);
-        fac = fac * (ec + (x * 1.1283791670955126) * exp(-(x * x)));
+        const double gx = exp(-(x * x));
+        const double ec = gx * erfc_scaled64(x);
+        fac = fac * (ec + (x * 1.1283791670955126) * gx);
         if (POT)
             phi = phi * ec;
     }
