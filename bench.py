@@ -421,8 +421,8 @@ def main():
     walk_ms = h["kernel_ms"]["walk_rel"]
     achieved = res[precs[0]]["inter_rel"] * fl / (walk_ms * 1e-3) / 1e12
     per, tpm = ("true", "true") if periodic else ("false", "false")
-    walk_kernel = (f"k_walk32<{per}, {tpm}, 1, false>" if precs[0] == "fp32"
-                   else f"k_walk64{'i' if periodic else ''}<{per}, {tpm}, 1, false>")
+    walk_kernel = (f"k_walk32<{per}, {tpm}, 1, false, false>" if precs[0] == "fp32"
+                   else f"k_walk64{'i' if periodic else ''}<{per}, {tpm}, 1, false, false>")
     line = {
         "metric": METRIC,
         "value": h["value"],
