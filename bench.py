@@ -119,13 +119,14 @@ def run_gpu(p, kw, prec, steps, warmup, eps=None):
     wall = time.perf_counter() - t0
     ctx.timing(False)
     per_step = [ev[s].elapsed_time(ev[s + 1]) for s in range(steps)]
-    timers = {k: ctx.timing_read(k) for k in ctx.TIMERS}
+    durations = {k: ctx.timing_durations(k) for k in ctx.TIMERS}
+    timers = {k: (sum(v), len(v)) for k, v in durations.items()}
     ctx.check()
     inter_bh = int(nint_bh.to(torch.int64).sum())
     inter_rel = int(nint.to(torch.int64).sum())
     total = (acc + acc_pm) if has_pm else acc
     out = dict(prec=prec, ms_per_step=sum(per_step) / steps, per_step=per_step, wall=wall,
-               timers=timers, inter_bh=inter_bh, inter_rel=inter_rel, n=n,
+               timers=timers, durations=durations, inter_bh=inter_bh, inter_rel=inter_rel, n=n,
                acc=total.double().cpu(), entries=ctx.tree_info()[1])
     ctx.close()
     return out
@@ -267,14 +268,14 @@ def run_integrators():
     return out
 
 
-def run_serving(n_requests=300, n_systems=16, seed=5):
+def run_serving(n_requests=10000, n_burst=2000, n_systems=16, seed=5):
     """Continuous batching over a pool of resident systems: capacity from a
-    run where every request is present at t = 0, then Poisson arrivals at
-    0.7 of that capacity; p50/p99 latency from GPU events."""
+    burst of n_burst requests all present at t = 0, then n_requests Poisson
+    arrivals at 0.7 of that capacity; p50/p99 latency from GPU events."""
     from paper_1909_04667_amd import serve as S
     from paper_1909_04667_amd import workloads as W
     pool = W.system_pool(n_systems, seed=seed)
-    burst = W.request_stream(n_requests, rate=0.0, n_systems=n_systems, seed=seed)
+    burst = W.request_stream(n_burst, rate=0.0, n_systems=n_systems, seed=seed)
     srv = S.Server(pool, budget_bytes=64 << 30)
     srv.run(burst[:n_systems * 2])  # warm-up: builds every resident system
     st, _ = srv.run(burst)
@@ -286,7 +287,7 @@ def run_serving(n_requests=300, n_systems=16, seed=5):
     srv.close()
     s2 = st2.summary()
     return {"systems": n_systems, "n_range": [min(s.n for s in pool), max(s.n for s in pool)],
-            "requests": n_requests, "precisions": "fp32+fp64 mix",
+            "requests": n_requests, "burst_requests": n_burst, "precisions": "fp32+fp64 mix",
             "capacity": {"force_evals_per_s": cap["throughput_evals_per_s"],
                          "requests_per_s": req_rate, "p50_ms": cap["p50_ms"],
                          "p99_ms": cap["p99_ms"]},
@@ -411,6 +412,12 @@ def main():
                 "sort": r["timers"]["sort"][0] / max(r["timers"]["sort"][1], 1),
                 "pm_solve": r["timers"]["pm_solve"][0] / max(r["timers"]["pm_solve"][1], 1),
                 "pm_interp": r["timers"]["pm_interp"][0] / max(r["timers"]["pm_interp"][1], 1)},
+            "kernel_ms_p50_p99": {
+                name: [pct(r["durations"][k], 50), pct(r["durations"][k], 99)]
+                for name, k in (("walk_rel", "walk_rel"), ("walk_bh", "walk"),
+                                ("build", "build"), ("sort", "sort"),
+                                ("pm_solve", "pm_solve"), ("pm_interp", "pm_interp"))
+                if r["durations"][k]},
             "interactions_per_step": {"bh": r["inter_bh"], "rel": r["inter_rel"]},
             "interactions_per_particle_rel": r["inter_rel"] / r["n"],
             "tree_entries": r["entries"],

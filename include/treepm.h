@@ -194,6 +194,11 @@ int tpm_accel_norm(tpm_ctx *ctx, int64_t n_act, const int32_t *active_idx, const
 int tpm_timing_enable(tpm_ctx *ctx, int on);
 int tpm_timing_read(tpm_ctx *ctx, int kind, double *ms, int64_t *launches);
 
+/* As tpm_timing_read, but returns each timed launch's milliseconds in launch
+ * order: ms receives min(cap, *launches) values (host array), *launches the
+ * number of launches recorded; the records are reset either way. */
+int tpm_timing_durations(tpm_ctx *ctx, int kind, double *ms, int64_t cap, int64_t *launches);
+
 /* Synchronise the stream and report sticky device-side errors
  * (TPM_EINDEX for an out-of-range active index); clears them. */
 int tpm_check(tpm_ctx *ctx);

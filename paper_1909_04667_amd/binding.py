@@ -66,6 +66,7 @@ def lib():
         L.tpm_accel_norm.argtypes = [vp, i64, vp, vp, vp, vp]
         L.tpm_timing_enable.argtypes = [vp, C.c_int]
         L.tpm_timing_read.argtypes = [vp, C.c_int, P(d), P(i64)]
+        L.tpm_timing_durations.argtypes = [vp, C.c_int, P(d), i64, P(i64)]
         L.tpm_batch_create.argtypes = [vp, P(vp)]
         L.tpm_batch_destroy.argtypes = [vp]
         L.tpm_batch_last_error.argtypes = [vp]
@@ -215,6 +216,13 @@ class Context:
         k = C.c_int64()
         self._rc(lib().tpm_timing_read(self.h, self.TIMERS[kind], C.byref(ms), C.byref(k)))
         return float(ms.value), int(k.value)
+
+    def timing_durations(self, kind: str, cap: int = 1 << 16):
+        """Milliseconds of each timed launch of one class (launch order)."""
+        buf = (C.c_double * cap)()
+        k = C.c_int64()
+        self._rc(lib().tpm_timing_durations(self.h, self.TIMERS[kind], buf, cap, C.byref(k)))
+        return [buf[i] for i in range(min(int(k.value), cap))]
 
     # -- checks and verification --------------------------------------------
     def check(self):

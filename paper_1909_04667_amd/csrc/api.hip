@@ -338,18 +338,18 @@ int tpm_timing_enable(tpm_ctx *c, int on) {
     return TPM_OK;
 }
 
-int tpm_timing_read(tpm_ctx *c, int kind, double *ms, int64_t *launches) {
-    if (!c || kind < 0 || kind >= 8)
-        return TPM_EINVAL;
+// Elapsed milliseconds of every timed launch of one class since the last
+// read, in launch order; the events go back to the pool.
+static int drain_timer(tpm_ctx *c, int kind, std::vector<float> &out) {
     TPM_HIP(c, hipStreamSynchronize(c->stream));
-    double sum = 0.0;
-    int64_t cnt = 0;
+    out.clear();
+    int rc = TPM_OK;
     for (auto &pr : c->timed[kind]) {
-        if (pr.first && pr.second) {
+        if (pr.first && pr.second && rc == TPM_OK) {
             float t = 0.0f;
-            TPM_HIP(c, hipEventElapsedTime(&t, pr.first, pr.second));
-            sum += t;
-            cnt++;
+            if (hipEventElapsedTime(&t, pr.first, pr.second) != hipSuccess)
+                rc = fail(c, TPM_EDEVICE, "hipEventElapsedTime failed");
+            out.push_back(t);
         }
         if (pr.first)
             c->event_pool.push_back(pr.first);
@@ -357,10 +357,33 @@ int tpm_timing_read(tpm_ctx *c, int kind, double *ms, int64_t *launches) {
             c->event_pool.push_back(pr.second);
     }
     c->timed[kind].clear();
+    return rc;
+}
+
+int tpm_timing_read(tpm_ctx *c, int kind, double *ms, int64_t *launches) {
+    if (!c || kind < 0 || kind >= 8)
+        return TPM_EINVAL;
+    std::vector<float> d;
+    TPM_TRY(drain_timer(c, kind, d));
+    double sum = 0.0;
+    for (float t : d)
+        sum += t;
     if (ms)
         *ms = sum;
     if (launches)
-        *launches = cnt;
+        *launches = (int64_t)d.size();
+    return TPM_OK;
+}
+
+int tpm_timing_durations(tpm_ctx *c, int kind, double *ms, int64_t cap, int64_t *launches) {
+    if (!c || kind < 0 || kind >= 8 || cap < 0 || (cap > 0 && !ms))
+        return TPM_EINVAL;
+    std::vector<float> d;
+    TPM_TRY(drain_timer(c, kind, d));
+    for (size_t k = 0; k < d.size() && (int64_t)k < cap; k++)
+        ms[k] = d[k];
+    if (launches)
+        *launches = (int64_t)d.size();
     return TPM_OK;
 }
 
