@@ -58,16 +58,37 @@ __global__ __launch_bounds__(kBlock) void k_bbox_partial(const double *__restric
 
 // Smallest power of two >= ext (1 + 2^-20) (1 when every particle coincides);
 // the corner sits below the minimum by a fraction shift of the slack.
-__global__ void k_frame_final(const double *__restrict__ part, int nparts, Frame *F,
-                              double s0, double s1, double s2) {
-    if (threadIdx.x != 0 || blockIdx.x != 0)
-        return;
+__global__ __launch_bounds__(kBlock) void k_frame_final(const double *__restrict__ part,
+                                                        int nparts, Frame *F, double s0,
+                                                        double s1, double s2) {
+    // min/max of the block partials: strided over the threads, then a tree in
+    // LDS (both exact, so the order does not matter)
+    __shared__ double sh[6][kBlock];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = 0; b < nparts; b++)
+    for (int b = threadIdx.x; b < nparts; b += kBlock)
         for (int a = 0; a < 3; a++) {
             lo[a] = fmin(lo[a], part[b * 6 + a]);
             hi[a] = fmax(hi[a], part[b * 6 + 3 + a]);
         }
+    for (int a = 0; a < 3; a++) {
+        sh[a][threadIdx.x] = lo[a];
+        sh[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int a = 0; a < 3; a++) {
+                sh[a][threadIdx.x] = fmin(sh[a][threadIdx.x], sh[a][threadIdx.x + w]);
+                sh[3 + a][threadIdx.x] = fmax(sh[3 + a][threadIdx.x], sh[3 + a][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0)
+        return;
+    for (int a = 0; a < 3; a++) {
+        lo[a] = sh[a][0];
+        hi[a] = sh[3 + a][0];
+    }
     double ext = 0.0;
     for (int a = 0; a < 3; a++) {
         double e = hi[a] - lo[a];
@@ -80,9 +101,9 @@ __global__ void k_frame_final(const double *__restrict__ part, int nparts, Frame
         double m = frexp(t, &ex);
         L = (m == 0.5) ? ldexp(1.0, ex - 1) : ldexp(1.0, ex);
     }
-    const double sh[3] = {s0, s1, s2};
+    const double shift[3] = {s0, s1, s2};
     for (int a = 0; a < 3; a++)
-        F->x0[a] = lo[a] - sh[a] * (L - (hi[a] - lo[a]));
+        F->x0[a] = lo[a] - shift[a] * (L - (hi[a] - lo[a]));
     F->L = L;
     F->S = 2097152.0 / L;
     F->box = 0.0;
@@ -472,8 +493,8 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
         TPM_TRY(ensure(c, c->bbox, (size_t)nparts * 6 * sizeof(double)));
         k_bbox_partial<<<nparts, kBlock, 0, st>>>(x, y, z, n, (double *)c->bbox.p);
         TPM_LAUNCHED(c, "k_bbox_partial");
-        k_frame_final<<<1, 64, 0, st>>>((const double *)c->bbox.p, nparts, F, P.shift[0],
-                                        P.shift[1], P.shift[2]);
+        k_frame_final<<<1, kBlock, 0, st>>>((const double *)c->bbox.p, nparts, F, P.shift[0],
+                                            P.shift[1], P.shift[2]);
         TPM_LAUNCHED(c, "k_frame_final");
     }
     // 2. keys, 3. sort, gather
