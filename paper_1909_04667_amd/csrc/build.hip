@@ -440,14 +440,15 @@ __global__ __launch_bounds__(kBlock) void k_pack32(const Rec64 *__restrict__ rec
         const double cen = F.x0[a] + ((double)P + 0.5) * len;
         off[a] = R.com[a] - cen;
     }
+    const int sh = F.periodic ? kRecShiftPer : kRecShiftIso;
     Rec32 o;
     o.dx = (float)off[0];
     o.dy = (float)off[1];
     o.dz = (float)off[2];
     o.gm = (float)(G * R.mass);
-    o.cx_meta = C[0] | (lev << 22) | ((part ? 1 : 0) << 27);
-    o.cy = C[1];
-    o.cz = C[2];
+    o.cx_meta = (int32_t)((uint32_t)C[0] << sh) | lev | (part ? kRecParticle : 0);
+    o.cy = (int32_t)((uint32_t)C[1] << sh);
+    o.cz = (int32_t)((uint32_t)C[2] << sh);
     o.skip = R.skip;
     out[e] = o;
 }

@@ -41,10 +41,19 @@ struct alignas(64) Rec64 {
 // cube is C * u with C = (2 P + 1) 2^(21-level), u = L_root 2^-22, P the
 // cube's integer corner at its level; a particle uses its depth-21 cell.
 // dcom = (centre of mass - centre) rounded to float; gm = G * mass.
+// The integer coordinates are stored as C << kRecShift: in a periodic box
+// (10 bits) a 32-bit difference then wraps modulo the box of 2^22 units with
+// no further work; otherwise (9 bits) every difference of two coordinates
+// below 2^22 still fits an int32.  The freed low bits of cx hold the level
+// and the particle flag.
+constexpr int kRecShiftPer = 10;
+constexpr int kRecShiftIso = 9;
+constexpr int32_t kRecLevel = 31;     // level, bits 0-4 of cx_meta
+constexpr int32_t kRecParticle = 32;  // particle flag, bit 5 of cx_meta
 struct alignas(32) Rec32 {
     float dx, dy, dz, gm;
-    int32_t cx_meta;  // C_x (22 bits) | level << 22 | particle << 27
-    int32_t cy, cz;
+    int32_t cx_meta;  // C_x << shift | particle << 5 | level
+    int32_t cy, cz;   // C_y << shift, C_z << shift
     uint32_t skip;
 };
 

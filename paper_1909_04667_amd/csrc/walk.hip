@@ -167,10 +167,11 @@ __device__ __forceinline__ double spline_phi64_sel(double u) {
 // condition); per-lane choices are selects, so every interacting lane gets
 // exactly interact64's result.
 template <bool TPM, bool POT, bool MIXED>
-__device__ __forceinline__ void interact64_wave(const WalkArgs &A, bool inter, double m, double d0,
-                                                double d1, double d2, double dd, double hp,
-                                                double &a0, double &a1, double &a2, double &pot,
-                                                uint32_t &nint) {
+__device__ __forceinline__ void interact64_wave(const WalkArgs &A, uint64_t inter_m, double m,
+                                                double d0, double d1, double d2, double dd,
+                                                double hp, double &a0, double &a1, double &a2,
+                                                double &pot, uint32_t &nint) {
+    const bool inter = lane_in(inter_m);
     const double Gm = A.G * m;
     const double r = sqrt(dd);
     const double rinv = 1.0 / r;
@@ -180,7 +181,7 @@ __device__ __forceinline__ void interact64_wave(const WalkArgs &A, bool inter, d
     if (POT)
         phi = -Gm * rinv;
     const bool soft = r < h;
-    if (wave_mask(inter && soft)) {
+    if (inter_m & wave_mask(soft)) {
         double hinv = A.hinv, h3inv = A.h3inv;
         if (MIXED) {
             hinv = 1.0 / h;
@@ -234,6 +235,8 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
         an = A.anorm[A.perm[s]];
     const double alpha_an = A.alpha * an;
     const double hi = MIXED ? A.hs[s] : 0.0;  // the target's own support
+    // the lane's walk stands at the cursor when next <= cursor (next moves
+    // to the skip pointer only when the lane accepts or discards a cube)
     uint32_t next = valid ? 0u : 0xffffffffu;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, pot = 0.0;
     uint32_t nint = 0;
@@ -244,16 +247,17 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
         const Rec64 r = R[cu];
         const double he = MIXED ? ((const double *)A.eh)[cu] : 0.0;
         const double hp = hi > he ? hi : he;  // the larger support
-        const uint64_t mine = wave_mask(next == cu);
+        const uint64_t mine = wave_mask(next <= cu);
         const double d0 = wrap64<PER>(r.com[0] - x0, A.box, A.half);
         const double d1 = wrap64<PER>(r.com[1] - x1, A.box, A.half);
         const double d2 = wrap64<PER>(r.com[2] - x2, A.box, A.half);
         const double dd = fma(d0, d0, fma(d1, d1, d2 * d2));
         uint64_t inter, desc;
         if (r.meta & kParticleFlag) {
-            inter = mine & wave_mask((cu != self) && (!TPM || dd < A.rc2));
+            inter = mine & wave_mask(cu != self);
+            if (TPM)
+                inter &= wave_mask(dd < A.rc2);
             desc = 0;
-            next = lane_in(mine) ? cu + 1u : next;
         } else {
             const uint32_t lev = r.meta & 0xffu;
             const double c0 = wrap64<PER>(r.cen[0] - x0, A.box, A.half);
@@ -269,24 +273,26 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
                 keep = wave_mask(!(fma(e0, e0, fma(e1, e1, e2 * e2)) > A.rc2));
             }
             const double L2 = scale_level(scale_level(A.L2r, lev), lev);
-            bool crit;
+            uint64_t open;
             if (OPEN == TPM_OPEN_BH)
-                crit = L2 > A.theta2 * dd;
+                open = wave_mask(L2 > A.theta2 * dd);
             else
-                crit = (A.G * r.mass) * L2 > alpha_an * (dd * dd);
+                open = wave_mask((A.G * r.mass) * L2 > alpha_an * (dd * dd));
             const double lim = scale_level(A.limr, lev);
-            const bool box = fabs(c0) < lim && fabs(c1) < lim && fabs(c2) < lim;
+            open |= wave_mask(fabs(c0) < lim) & wave_mask(fabs(c1) < lim) &
+                    wave_mask(fabs(c2) < lim);
             // larger softening inside the node, target within it of the
             // centre of mass: open (Sec. 3.2)
-            const bool soft_open = MIXED && hi < he && dd < he * he;
-            const uint64_t open = keep & wave_mask(crit || box || soft_open);
+            if (MIXED)
+                open |= wave_mask(hi < he) & wave_mask(dd < he * he);
+            open &= keep;
             inter = mine & keep & ~open;
             desc = mine & open;
-            next = lane_in(mine) ? (lane_in(open) ? cu + 1u : r.skip) : next;
+            next = lane_in(mine & ~open) ? r.skip : next;
         }
         if (inter)
-            interact64_wave<TPM, POT, MIXED>(A, lane_in(inter), r.mass, d0, d1, d2, dd, hp, a0,
-                                             a1, a2, pot, nint);
+            interact64_wave<TPM, POT, MIXED>(A, inter, r.mass, d0, d1, d2, dd, hp, a0, a1, a2,
+                                             pot, nint);
         c = desc ? cu + 1u : r.skip;
     }
     if (valid) {
@@ -365,15 +371,6 @@ __device__ __forceinline__ void interact32(const WalkArgs &A, float gm, float d0
         pot += phi;
 }
 
-template <bool PER>
-__device__ __forceinline__ int32_t wrapi(int32_t d) {
-    // the periodic box spans 2^22 units: the nearest image is the difference
-    // modulo 2^22, sign-extended from 22 bits (one bit-field extract)
-    if (PER)
-        d = (int32_t)((uint32_t)d << 10) >> 10;
-    return d;
-}
-
 __device__ __forceinline__ float spline_g32_sel(float u) {
     const float u2 = u * u;
     const float inner = fmaf(u2, fmaf(32.0f, u, -38.4f), 10.6666667f);
@@ -394,10 +391,11 @@ __device__ __forceinline__ float spline_phi32_sel(float u) {
 // interact32 for the lanes with `inter` set, executed by the whole wavefront
 // (see interact64_wave); identical results for those lanes.
 template <bool TPM, bool POT, bool MIXED>
-__device__ __forceinline__ void interact32_wave(const WalkArgs &A, bool inter, float gm, float d0,
-                                                float d1, float d2, float dd, float hp,
+__device__ __forceinline__ void interact32_wave(const WalkArgs &A, uint64_t inter_m, float gm,
+                                                float d0, float d1, float d2, float dd, float hp,
                                                 float &a0, float &a1, float &a2, float &pot,
                                                 uint32_t &nint) {
+    const bool inter = lane_in(inter_m);
     const float rinv = __builtin_amdgcn_rsqf(dd);
     float fac = gm * rinv * rinv * rinv;
     float phi = 0.0f, r = 0.0f;
@@ -406,7 +404,7 @@ __device__ __forceinline__ void interact32_wave(const WalkArgs &A, bool inter, f
     if (TPM)
         r = dd * rinv;
     const bool soft = dd < (MIXED ? hp * hp : A.fh2);
-    if (wave_mask(inter && soft)) {
+    if (inter_m & wave_mask(soft)) {
         float hinv = A.fhinv, h3inv = A.fh3inv;
         if (MIXED) {
             hinv = 1.0f / hp;
@@ -448,6 +446,7 @@ __device__ __forceinline__ float scale_level32(float v, uint32_t lev) {
 
 template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
+    constexpr int SH = PER ? kRecShiftPer : kRecShiftIso;
     const int lane = threadIdx.x & 63;
     const uint32_t nu = *A.nuniq;
     if (wave * 64u >= nu)
@@ -455,13 +454,16 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     const uint32_t slot = wave * 64u + lane;
     const bool valid = slot < nu;
     const uint32_t s = A.act[valid ? slot : wave * 64u];
-    // own depth-21 cell centre (integer, units of u = L_root 2^-22) and the
+    // own depth-21 cell centre (integer, shifted like the records) and the
     // float offset of the particle from it
     const uint64_t qq = A.qs[s];
     const uint32_t q0 = (uint32_t)(qq >> 42) & 0x1fffffu, q1 = (uint32_t)(qq >> 21) & 0x1fffffu,
                    q2 = (uint32_t)qq & 0x1fffffu;
-    const int32_t G0 = (int32_t)(2u * q0 + 1u), G1 = (int32_t)(2u * q1 + 1u),
-                  G2 = (int32_t)(2u * q2 + 1u);
+    int32_t G0 = (int32_t)((2u * q0 + 1u) << SH), G1 = (int32_t)((2u * q1 + 1u) << SH),
+            G2 = (int32_t)((2u * q2 + 1u) << SH);
+    // keep each centre whole in one register: split into (2 q << SH) plus a
+    // constant, it would cost a second subtraction per coordinate and entry
+    asm("" : "+v"(G0), "+v"(G1), "+v"(G2));
     const double len21 = ldexp(A.L, -kMaxLevel);
     const float xr0 = (float)(A.ps[s] - (A.x0[0] + ((double)q0 + 0.5) * len21));
     const float xr1 = (float)(A.ps[A.n + s] - (A.x0[1] + ((double)q1 + 0.5) * len21));
@@ -472,6 +474,10 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
         an = (float)A.anorm[A.perm[s]];
     const float alpha_an = A.falpha * an;
     const float hi = MIXED ? (float)A.hs[s] : 0.0f;
+    // A lane's walk stands at the cursor when next <= cursor: next is only
+    // moved (to the skip pointer) when the lane accepts or discards a cube,
+    // so a lane that opened a cube follows the cursor through its subtree,
+    // particles included, without per-entry bookkeeping.
     uint32_t next = valid ? 0u : 0xffffffffu;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, pot = 0.0f;
     uint32_t nint = 0;
@@ -484,21 +490,23 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
         const Rec32 r = R[cu];
         const float he = MIXED ? ((const float *)A.eh)[cu] : 0.0f;
         const float hp = hi > he ? hi : he;
-        const uint64_t mine = wave_mask(next == cu);
+        const uint64_t mine = wave_mask(next <= cu);
         const int32_t cm = r.cx_meta;
-        // target -> centre of the entry, and target -> centre of mass
-        const float c0 = fmaf((float)wrapi<PER>((cm & 0x3fffff) - G0), A.fu, -xr0);
-        const float c1 = fmaf((float)wrapi<PER>(r.cy - G1), A.fu, -xr1);
-        const float c2 = fmaf((float)wrapi<PER>(r.cz - G2), A.fu, -xr2);
+        // target -> centre of the entry (32-bit differences wrap modulo the
+        // periodic box), and target -> centre of mass
+        const float c0 = fmaf((float)((cm & -(1 << SH)) - G0), A.fu, -xr0);
+        const float c1 = fmaf((float)(r.cy - G1), A.fu, -xr1);
+        const float c2 = fmaf((float)(r.cz - G2), A.fu, -xr2);
         const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
         const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
         uint64_t inter, desc;
-        if (cm & (1 << 27)) {
-            inter = mine & wave_mask((cu != self) && (!TPM || dd < A.frc2));
+        if (cm & kRecParticle) {
+            inter = mine & wave_mask(cu != self);
+            if (TPM)
+                inter &= wave_mask(dd < A.frc2);
             desc = 0;
-            next = lane_in(mine) ? cu + 1u : next;
         } else {
-            const uint32_t lev = ((uint32_t)cm >> 22) & 31u;
+            const uint32_t lev = (uint32_t)cm & kRecLevel;
             uint64_t keep = ~0ull;
             if (TPM) {
                 const float hl = scale_level32(A.fhlr, lev);
@@ -508,22 +516,24 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
                 keep = wave_mask(!(fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) > A.frc2));
             }
             const float L2 = scale_level32(scale_level32(A.fL2r, lev), lev);
-            bool crit;
+            uint64_t open;
             if (OPEN == TPM_OPEN_BH)
-                crit = L2 > A.ftheta2 * dd;
+                open = wave_mask(L2 > A.ftheta2 * dd);
             else
-                crit = r.gm * L2 > alpha_an * (dd * dd);
+                open = wave_mask(r.gm * L2 > alpha_an * (dd * dd));
             const float lim = scale_level32(A.flimr, lev);
-            const bool box = fabsf(c0) < lim && fabsf(c1) < lim && fabsf(c2) < lim;
-            const bool soft_open = MIXED && hi < he && dd < he * he;
-            const uint64_t open = keep & wave_mask(crit || box || soft_open);
+            open |= wave_mask(fabsf(c0) < lim) & wave_mask(fabsf(c1) < lim) &
+                    wave_mask(fabsf(c2) < lim);
+            if (MIXED)
+                open |= wave_mask(hi < he) & wave_mask(dd < he * he);
+            open &= keep;
             inter = mine & keep & ~open;
             desc = mine & open;
-            next = lane_in(mine) ? (lane_in(open) ? cu + 1u : r.skip) : next;
+            next = lane_in(mine & ~open) ? r.skip : next;
         }
         if (inter)
-            interact32_wave<TPM, POT, MIXED>(A, lane_in(inter), r.gm, d0, d1, d2, dd, hp, a0, a1,
-                                             a2, pot, nint);
+            interact32_wave<TPM, POT, MIXED>(A, inter, r.gm, d0, d1, d2, dd, hp, a0, a1, a2, pot,
+                                             nint);
         c = desc ? cu + 1u : r.skip;
     }
     if (valid) {
@@ -677,6 +687,7 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
     const double len21 = ldexp(A.L, -kMaxLevel);
     uint32_t slot = base + lane;
     bool live = slot < chunk_end;
+    constexpr int SH = PER ? kRecShiftPer : kRecShiftIso;
     int32_t G0 = 0, G1 = 0, G2 = 0;
     float xr0 = 0.f, xr1 = 0.f, xr2 = 0.f, alpha_an = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f,
           pot = 0.f, hi = 0.f;
@@ -686,9 +697,9 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
         const uint64_t qq = A.qs[s];
         const uint32_t q0 = (uint32_t)(qq >> 42) & 0x1fffffu,
                        q1 = (uint32_t)(qq >> 21) & 0x1fffffu, q2 = (uint32_t)qq & 0x1fffffu;
-        G0 = (int32_t)(2u * q0 + 1u);
-        G1 = (int32_t)(2u * q1 + 1u);
-        G2 = (int32_t)(2u * q2 + 1u);
+        G0 = (int32_t)((2u * q0 + 1u) << SH);
+        G1 = (int32_t)((2u * q1 + 1u) << SH);
+        G2 = (int32_t)((2u * q2 + 1u) << SH);
         xr0 = (float)(A.ps[s] - (A.x0[0] + ((double)q0 + 0.5) * len21));
         xr1 = (float)(A.ps[A.n + s] - (A.x0[1] + ((double)q1 + 0.5) * len21));
         xr2 = (float)(A.ps[2 * (size_t)A.n + s] - (A.x0[2] + ((double)q2 + 0.5) * len21));
@@ -709,13 +720,13 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
             const Rec32 r = R[e];
             const float he = MIXED ? ((const float *)A.eh)[e] : 0.0f;
             const int32_t cm = r.cx_meta;
-            const float c0 = fmaf((float)wrapi<PER>((cm & 0x3fffff) - G0), A.fu, -xr0);
-            const float c1 = fmaf((float)wrapi<PER>(r.cy - G1), A.fu, -xr1);
-            const float c2 = fmaf((float)wrapi<PER>(r.cz - G2), A.fu, -xr2);
+            const float c0 = fmaf((float)((cm & -(1 << SH)) - G0), A.fu, -xr0);
+            const float c1 = fmaf((float)(r.cy - G1), A.fu, -xr1);
+            const float c2 = fmaf((float)(r.cz - G2), A.fu, -xr2);
             const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
             const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-            const bool part = (cm & (1 << 27)) != 0;
-            const float L = __builtin_amdgcn_ldexpf(A.fL, -((cm >> 22) & 31));
+            const bool part = (cm & kRecParticle) != 0;
+            const float L = __builtin_amdgcn_ldexpf(A.fL, -(cm & kRecLevel));
             bool discard = false;
             if (TPM) {
                 const float hl = 0.5f * L;
@@ -997,7 +1008,8 @@ static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
     A.h3inv = A.hinv * A.hinv * A.hinv;
     A.rc2 = rcut * rcut;
     A.inv2rs = 0.5 / rs;
-    A.fu = (float)ldexp(A.L, -22);
+    // unit of the shifted integer coordinates of the FP32 records
+    A.fu = (float)ldexp(A.L, -22 - (P.periodic ? kRecShiftPer : kRecShiftIso));
     A.fL = (float)A.L;
     A.ftheta2 = (float)A.theta2;
     A.falpha = (float)A.alpha;
