@@ -376,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(
 // Nodes of one level (deepest level first): walk the children through their
 // skip pointers (all deeper, so already final), sum the monopole moments in
 // curve order -- M = (M1 + M2) + ..., X = fma(M_k, s_k, X), s = X / M -- and
-// set the node's particle count and skip pointer.  With individual
+// set the node's particle count, skip pointer and leaf-parent flag.  With individual
 // softening the node also takes the largest spline support of its children.
 __global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uint32_t E,
                                                     uint32_t *__restrict__ ecount,
@@ -406,6 +406,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uin
     rec[e].com[2] = X2 / M;
     rec[e].skip = k;
     ecount[e] = cnt;
+    if (k - e - 1u == cnt)  // no entry below but the particles themselves
+        rec[e].meta |= kLeafParentFlag;
     if (eh)
         eh[e] = hmax;
 }
@@ -446,7 +448,8 @@ __global__ __launch_bounds__(kBlock) void k_pack32(const Rec64 *__restrict__ rec
     o.dy = (float)off[1];
     o.dz = (float)off[2];
     o.gm = (float)(G * R.mass);
-    o.cx_meta = (int32_t)((uint32_t)C[0] << sh) | lev | (part ? kRecParticle : 0);
+    o.cx_meta = (int32_t)((uint32_t)C[0] << sh) | lev | (part ? kRecParticle : 0) |
+                ((R.meta & kLeafParentFlag) ? kRecLeafParent : 0);
     o.cy = (int32_t)((uint32_t)C[1] << sh);
     o.cz = (int32_t)((uint32_t)C[2] << sh);
     o.skip = R.skip;

@@ -16,6 +16,7 @@ constexpr int kBits = 21;          // bits per axis of the integer coordinate
 constexpr int kMaxLevel = 21;      // deepest octree level (63-bit keys)
 constexpr int kLevels = kMaxLevel + 1;
 constexpr uint32_t kParticleFlag = 1u << 8;
+constexpr uint32_t kLeafParentFlag = 1u << 9;  // a cube whose children are all particles
 
 // Root frame of the last build, resident in device memory.
 struct Frame {
@@ -50,9 +51,10 @@ constexpr int kRecShiftPer = 10;
 constexpr int kRecShiftIso = 9;
 constexpr int32_t kRecLevel = 31;     // level, bits 0-4 of cx_meta
 constexpr int32_t kRecParticle = 32;  // particle flag, bit 5 of cx_meta
+constexpr int32_t kRecLeafParent = 64;  // cube with particle children only, bit 6
 struct alignas(32) Rec32 {
     float dx, dy, dz, gm;
-    int32_t cx_meta;  // C_x << shift | particle << 5 | level
+    int32_t cx_meta;  // C_x << shift | leaf parent << 6 | particle << 5 | level
     int32_t cy, cz;   // C_y << shift, C_z << shift
     uint32_t skip;
 };

@@ -46,6 +46,10 @@ struct WalkArgs {
     // single-precision copies
     float fu, fL, ftheta2, falpha, fh2, fhinv, fh3inv, frc2, finv2rs;
     float fL2r, flimr, fhlr;
+    // leaf-run prefilter: (r_cut + tolerance)^2, and the largest group
+    // extent from its reference cell for which the reference cell's nearest
+    // image is every member's (periodic)
+    float fpf2, fpf_ext;
     void *res;
     void *rpot;
     uint32_t *rnint;
@@ -482,59 +486,133 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, pot = 0.0f;
     uint32_t nint = 0;
     const Rec32 *__restrict__ R = (const Rec32 *)A.rec;
+
+    // With a cutoff, the particles below an opened leaf parent are first
+    // tested together, one per lane, against the bounding box of the group's
+    // targets (positions relative to lane 0's cell, r_cut padded by a
+    // tolerance above the rounding); only those that can lie within r_cut of
+    // some target are visited.  The others would interact with no lane, so
+    // results and interaction lists are unchanged.
+    int32_t Gr0 = 0, Gr1 = 0, Gr2 = 0;
+    float lo0 = 0.f, hi0 = 0.f, lo1 = 0.f, hi1 = 0.f, lo2 = 0.f, hi2 = 0.f;
+    bool prefilter = false;
+    if (TPM) {
+        Gr0 = __builtin_amdgcn_readfirstlane(G0);
+        Gr1 = __builtin_amdgcn_readfirstlane(G1);
+        Gr2 = __builtin_amdgcn_readfirstlane(G2);
+        lo0 = hi0 = fmaf((float)(G0 - Gr0), A.fu, xr0);
+        lo1 = hi1 = fmaf((float)(G1 - Gr1), A.fu, xr1);
+        lo2 = hi2 = fmaf((float)(G2 - Gr2), A.fu, xr2);
+        for (int o = 1; o < 64; o <<= 1) {
+            lo0 = fminf(lo0, __shfl_xor(lo0, o));
+            hi0 = fmaxf(hi0, __shfl_xor(hi0, o));
+            lo1 = fminf(lo1, __shfl_xor(lo1, o));
+            hi1 = fmaxf(hi1, __shfl_xor(hi1, o));
+            lo2 = fminf(lo2, __shfl_xor(lo2, o));
+            hi2 = fmaxf(hi2, __shfl_xor(hi2, o));
+        }
+        auto uni = [](float v) {
+            return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+        };
+        lo0 = uni(lo0), hi0 = uni(hi0), lo1 = uni(lo1), hi1 = uni(hi1), lo2 = uni(lo2),
+        hi2 = uni(hi2);
+        // in a periodic box the reference cell's nearest image must be every
+        // target's: a group wider than that walks without the prefilter
+        const float ext = fmaxf(fmaxf(fmaxf(-lo0, hi0), fmaxf(-lo1, hi1)), fmaxf(-lo2, hi2));
+        prefilter = ext < A.fpf_ext;
+    }
+
+    // one particle entry e (wavefront-uniform) for the lanes in m
+    auto particle = [&](const Rec32 &r, uint32_t e, uint64_t m) {
+        const float he = MIXED ? ((const float *)A.eh)[e] : 0.0f;
+        const float hp = hi > he ? hi : he;
+        const float d0 = fmaf((float)((r.cx_meta & -(1 << SH)) - G0), A.fu, -xr0) + r.dx;
+        const float d1 = fmaf((float)(r.cy - G1), A.fu, -xr1) + r.dy;
+        const float d2 = fmaf((float)(r.cz - G2), A.fu, -xr2) + r.dz;
+        const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+        uint64_t inter = m & wave_mask(e != self);
+        if (TPM)
+            inter &= wave_mask(dd < A.frc2);
+        if (inter)
+            interact32_wave<TPM, POT, MIXED>(A, inter, r.gm, d0, d1, d2, dd, hp, a0, a1, a2, pot,
+                                             nint);
+    };
+
     // level sizes follow from the root's by exponent arithmetic (exact; on
     // the scalar unit, since the entry is wavefront-uniform)
     uint32_t c = 0;
     while (c < A.E) {
         const uint32_t cu = __builtin_amdgcn_readfirstlane(c);
         const Rec32 r = R[cu];
-        const float he = MIXED ? ((const float *)A.eh)[cu] : 0.0f;
-        const float hp = hi > he ? hi : he;
         const uint64_t mine = wave_mask(next <= cu);
         const int32_t cm = r.cx_meta;
-        // target -> centre of the entry (32-bit differences wrap modulo the
+        if (cm & kRecParticle) {
+            particle(r, cu, mine);
+            c = cu + 1u;
+            continue;
+        }
+        const float he = MIXED ? ((const float *)A.eh)[cu] : 0.0f;
+        const float hp = hi > he ? hi : he;
+        // target -> centre of the cube (32-bit differences wrap modulo the
         // periodic box), and target -> centre of mass
         const float c0 = fmaf((float)((cm & -(1 << SH)) - G0), A.fu, -xr0);
         const float c1 = fmaf((float)(r.cy - G1), A.fu, -xr1);
         const float c2 = fmaf((float)(r.cz - G2), A.fu, -xr2);
         const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
         const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-        uint64_t inter, desc;
-        if (cm & kRecParticle) {
-            inter = mine & wave_mask(cu != self);
-            if (TPM)
-                inter &= wave_mask(dd < A.frc2);
-            desc = 0;
-        } else {
-            const uint32_t lev = (uint32_t)cm & kRecLevel;
-            uint64_t keep = ~0ull;
-            if (TPM) {
-                const float hl = scale_level32(A.fhlr, lev);
-                const float e0 = fmaxf(fabsf(c0) - hl, 0.0f);
-                const float e1 = fmaxf(fabsf(c1) - hl, 0.0f);
-                const float e2 = fmaxf(fabsf(c2) - hl, 0.0f);
-                keep = wave_mask(!(fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) > A.frc2));
-            }
-            const float L2 = scale_level32(scale_level32(A.fL2r, lev), lev);
-            uint64_t open;
-            if (OPEN == TPM_OPEN_BH)
-                open = wave_mask(L2 > A.ftheta2 * dd);
-            else
-                open = wave_mask(r.gm * L2 > alpha_an * (dd * dd));
-            const float lim = scale_level32(A.flimr, lev);
-            open |= wave_mask(fabsf(c0) < lim) & wave_mask(fabsf(c1) < lim) &
-                    wave_mask(fabsf(c2) < lim);
-            if (MIXED)
-                open |= wave_mask(hi < he) & wave_mask(dd < he * he);
-            open &= keep;
-            inter = mine & keep & ~open;
-            desc = mine & open;
-            next = lane_in(mine & ~open) ? r.skip : next;
+        const uint32_t lev = (uint32_t)cm & kRecLevel;
+        uint64_t keep = ~0ull;
+        if (TPM) {
+            const float hl = scale_level32(A.fhlr, lev);
+            const float e0 = fmaxf(fabsf(c0) - hl, 0.0f);
+            const float e1 = fmaxf(fabsf(c1) - hl, 0.0f);
+            const float e2 = fmaxf(fabsf(c2) - hl, 0.0f);
+            keep = wave_mask(!(fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) > A.frc2));
         }
+        const float L2 = scale_level32(scale_level32(A.fL2r, lev), lev);
+        uint64_t open;
+        if (OPEN == TPM_OPEN_BH)
+            open = wave_mask(L2 > A.ftheta2 * dd);
+        else
+            open = wave_mask(r.gm * L2 > alpha_an * (dd * dd));
+        const float lim = scale_level32(A.flimr, lev);
+        open |= wave_mask(fabsf(c0) < lim) & wave_mask(fabsf(c1) < lim) &
+                wave_mask(fabsf(c2) < lim);
+        if (MIXED)
+            open |= wave_mask(hi < he) & wave_mask(dd < he * he);
+        open &= keep;
+        const uint64_t inter = mine & keep & ~open;
+        const uint64_t desc = mine & open;
+        next = lane_in(mine & ~open) ? r.skip : next;
         if (inter)
             interact32_wave<TPM, POT, MIXED>(A, inter, r.gm, d0, d1, d2, dd, hp, a0, a1, a2, pot,
                                              nint);
-        c = desc ? cu + 1u : r.skip;
+        if (TPM && desc && (cm & kRecLeafParent) && prefilter) {
+            // the children cu + 1 .. skip - 1 are particles, walked by the
+            // lanes that opened the cube; the cursor then moves past them
+            const uint32_t end = r.skip;
+            for (uint32_t base = cu + 1u; base < end; base += 64u) {
+                const uint32_t k = min(64u, end - base);
+                bool near = false;
+                if ((uint32_t)lane < k) {
+                    const Rec32 t = R[base + lane];
+                    const float p0 = fmaf((float)((t.cx_meta & -(1 << SH)) - Gr0), A.fu, t.dx);
+                    const float p1 = fmaf((float)(t.cy - Gr1), A.fu, t.dy);
+                    const float p2 = fmaf((float)(t.cz - Gr2), A.fu, t.dz);
+                    const float g0 = fmaxf(fmaxf(lo0 - p0, p0 - hi0), 0.0f);
+                    const float g1 = fmaxf(fmaxf(lo1 - p1, p1 - hi1), 0.0f);
+                    const float g2 = fmaxf(fmaxf(lo2 - p2, p2 - hi2), 0.0f);
+                    near = fmaf(g0, g0, fmaf(g1, g1, g2 * g2)) < A.fpf2;
+                }
+                for (uint64_t m = wave_mask(near); m; m &= m - 1) {
+                    const uint32_t e = base + (uint32_t)__builtin_ctzll(m);
+                    particle(R[e], e, desc);
+                }
+            }
+            c = end;
+        } else {
+            c = desc ? cu + 1u : r.skip;
+        }
     }
     if (valid) {
         float *res = (float *)A.res;
@@ -1017,6 +1095,13 @@ static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
     A.fhinv = (float)A.hinv;
     A.fh3inv = (float)A.h3inv;
     A.frc2 = (float)A.rc2;
+    {
+        // the prefilter's rounding (positions relative to a group's reference
+        // cell, all below L_root in magnitude) stays far below L_root 2^-16
+        const double tol = ldexp(A.L, -16);
+        A.fpf2 = (float)((rcut + tol) * (rcut + tol));
+        A.fpf_ext = P.periodic ? (float)(0.5 * P.box_size - rcut - 2.0 * tol) : 3.0e38f;
+    }
     A.finv2rs = (float)A.inv2rs;
     A.res = c->res.p;
     A.rpot = c->rpot.p;
