@@ -50,6 +50,7 @@ struct WalkArgs {
     // extent from its reference cell for which the reference cell's nearest
     // image is every member's (periodic)
     float fpf2, fpf_ext;
+    double pf2, pf_ext;
     void *res;
     void *rpot;
     uint32_t *rnint;
@@ -245,59 +246,131 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, pot = 0.0;
     uint32_t nint = 0;
     const Rec64 *__restrict__ R = (const Rec64 *)A.rec;
-    uint32_t c = 0;
-    while (c < A.E) {
-        const uint32_t cu = __builtin_amdgcn_readfirstlane(c);
-        const Rec64 r = R[cu];
-        const double he = MIXED ? ((const double *)A.eh)[cu] : 0.0;
+
+    // leaf-run prefilter (as in the FP32 walk): bounding box of the targets
+    // relative to lane 0's position
+    double xr0 = 0.0, xr1 = 0.0, xr2 = 0.0;
+    double lo0 = 0.0, hi0 = 0.0, lo1 = 0.0, hi1 = 0.0, lo2 = 0.0, hi2 = 0.0;
+    bool prefilter = false;
+    if (TPM) {
+        auto uni = [](double v) {
+            const uint64_t b = (uint64_t)__double_as_longlong(v);
+            const uint32_t l = __builtin_amdgcn_readfirstlane((uint32_t)b);
+            const uint32_t h = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+            return __longlong_as_double((long long)(((uint64_t)h << 32) | l));
+        };
+        xr0 = uni(x0), xr1 = uni(x1), xr2 = uni(x2);
+        lo0 = hi0 = wrap64<PER>(x0 - xr0, A.box, A.half);
+        lo1 = hi1 = wrap64<PER>(x1 - xr1, A.box, A.half);
+        lo2 = hi2 = wrap64<PER>(x2 - xr2, A.box, A.half);
+        for (int o = 1; o < 64; o <<= 1) {
+            lo0 = fmin(lo0, __shfl_xor(lo0, o));
+            hi0 = fmax(hi0, __shfl_xor(hi0, o));
+            lo1 = fmin(lo1, __shfl_xor(lo1, o));
+            hi1 = fmax(hi1, __shfl_xor(hi1, o));
+            lo2 = fmin(lo2, __shfl_xor(lo2, o));
+            hi2 = fmax(hi2, __shfl_xor(hi2, o));
+        }
+        lo0 = uni(lo0), hi0 = uni(hi0), lo1 = uni(lo1), hi1 = uni(hi1), lo2 = uni(lo2),
+        hi2 = uni(hi2);
+        const double ext = fmax(fmax(fmax(-lo0, hi0), fmax(-lo1, hi1)), fmax(-lo2, hi2));
+        prefilter = ext < A.pf_ext;
+    }
+
+    // one particle entry e (wavefront-uniform) for the lanes in m
+    auto particle = [&](const Rec64 &r, uint32_t e, uint64_t m) {
+        const double he = MIXED ? ((const double *)A.eh)[e] : 0.0;
         const double hp = hi > he ? hi : he;  // the larger support
-        const uint64_t mine = wave_mask(next <= cu);
         const double d0 = wrap64<PER>(r.com[0] - x0, A.box, A.half);
         const double d1 = wrap64<PER>(r.com[1] - x1, A.box, A.half);
         const double d2 = wrap64<PER>(r.com[2] - x2, A.box, A.half);
         const double dd = fma(d0, d0, fma(d1, d1, d2 * d2));
-        uint64_t inter, desc;
-        if (r.meta & kParticleFlag) {
-            inter = mine & wave_mask(cu != self);
-            if (TPM)
-                inter &= wave_mask(dd < A.rc2);
-            desc = 0;
-        } else {
-            const uint32_t lev = r.meta & 0xffu;
-            const double c0 = wrap64<PER>(r.cen[0] - x0, A.box, A.half);
-            const double c1 = wrap64<PER>(r.cen[1] - x1, A.box, A.half);
-            const double c2 = wrap64<PER>(r.cen[2] - x2, A.box, A.half);
-            uint64_t keep = ~0ull;
-            if (TPM) {
-                const double hl = scale_level(A.hlr, lev);
-                double e0 = fabs(c0) - hl, e1 = fabs(c1) - hl, e2 = fabs(c2) - hl;
-                e0 = e0 > 0.0 ? e0 : 0.0;
-                e1 = e1 > 0.0 ? e1 : 0.0;
-                e2 = e2 > 0.0 ? e2 : 0.0;
-                keep = wave_mask(!(fma(e0, e0, fma(e1, e1, e2 * e2)) > A.rc2));
-            }
-            const double L2 = scale_level(scale_level(A.L2r, lev), lev);
-            uint64_t open;
-            if (OPEN == TPM_OPEN_BH)
-                open = wave_mask(L2 > A.theta2 * dd);
-            else
-                open = wave_mask((A.G * r.mass) * L2 > alpha_an * (dd * dd));
-            const double lim = scale_level(A.limr, lev);
-            open |= wave_mask(fabs(c0) < lim) & wave_mask(fabs(c1) < lim) &
-                    wave_mask(fabs(c2) < lim);
-            // larger softening inside the node, target within it of the
-            // centre of mass: open (Sec. 3.2)
-            if (MIXED)
-                open |= wave_mask(hi < he) & wave_mask(dd < he * he);
-            open &= keep;
-            inter = mine & keep & ~open;
-            desc = mine & open;
-            next = lane_in(mine & ~open) ? r.skip : next;
-        }
+        uint64_t inter = m & wave_mask(e != self);
+        if (TPM)
+            inter &= wave_mask(dd < A.rc2);
         if (inter)
             interact64_wave<TPM, POT, MIXED>(A, inter, r.mass, d0, d1, d2, dd, hp, a0, a1, a2,
                                              pot, nint);
-        c = desc ? cu + 1u : r.skip;
+    };
+
+    uint32_t c = 0;
+    while (c < A.E) {
+        const uint32_t cu = __builtin_amdgcn_readfirstlane(c);
+        const Rec64 r = R[cu];
+        const uint64_t mine = wave_mask(next <= cu);
+        if (r.meta & kParticleFlag) {
+            particle(r, cu, mine);
+            c = cu + 1u;
+            continue;
+        }
+        const double he = MIXED ? ((const double *)A.eh)[cu] : 0.0;
+        const double hp = hi > he ? hi : he;  // the larger support
+        const uint32_t lev = r.meta & 0xffu;
+        const double c0 = wrap64<PER>(r.cen[0] - x0, A.box, A.half);
+        const double c1 = wrap64<PER>(r.cen[1] - x1, A.box, A.half);
+        const double c2 = wrap64<PER>(r.cen[2] - x2, A.box, A.half);
+        uint64_t keep = ~0ull;
+        if (TPM) {
+            const double hl = scale_level(A.hlr, lev);
+            double e0 = fabs(c0) - hl, e1 = fabs(c1) - hl, e2 = fabs(c2) - hl;
+            e0 = e0 > 0.0 ? e0 : 0.0;
+            e1 = e1 > 0.0 ? e1 : 0.0;
+            e2 = e2 > 0.0 ? e2 : 0.0;
+            keep = wave_mask(!(fma(e0, e0, fma(e1, e1, e2 * e2)) > A.rc2));
+            if (!(mine & keep)) {  // every lane here discards the cube
+                next = lane_in(mine) ? r.skip : next;
+                c = r.skip;
+                continue;
+            }
+        }
+        const double d0 = wrap64<PER>(r.com[0] - x0, A.box, A.half);
+        const double d1 = wrap64<PER>(r.com[1] - x1, A.box, A.half);
+        const double d2 = wrap64<PER>(r.com[2] - x2, A.box, A.half);
+        const double dd = fma(d0, d0, fma(d1, d1, d2 * d2));
+        const double L2 = scale_level(scale_level(A.L2r, lev), lev);
+        uint64_t open;
+        if (OPEN == TPM_OPEN_BH)
+            open = wave_mask(L2 > A.theta2 * dd);
+        else
+            open = wave_mask((A.G * r.mass) * L2 > alpha_an * (dd * dd));
+        const double lim = scale_level(A.limr, lev);
+        open |= wave_mask(fabs(c0) < lim) & wave_mask(fabs(c1) < lim) &
+                wave_mask(fabs(c2) < lim);
+        // larger softening inside the node, target within it of the
+        // centre of mass: open (Sec. 3.2)
+        if (MIXED)
+            open |= wave_mask(hi < he) & wave_mask(dd < he * he);
+        open &= keep;
+        const uint64_t inter = mine & keep & ~open;
+        const uint64_t desc = mine & open;
+        next = lane_in(mine & ~open) ? r.skip : next;
+        if (inter)
+            interact64_wave<TPM, POT, MIXED>(A, inter, r.mass, d0, d1, d2, dd, hp, a0, a1, a2,
+                                             pot, nint);
+        if (TPM && desc && (r.meta & kLeafParentFlag) && prefilter) {
+            const uint32_t end = r.skip;
+            for (uint32_t base = cu + 1u; base < end; base += 64u) {
+                const uint32_t k = min(64u, end - base);
+                bool near = false;
+                if ((uint32_t)lane < k) {
+                    const double *t = R[base + lane].com;
+                    const double p0 = wrap64<PER>(t[0] - xr0, A.box, A.half);
+                    const double p1 = wrap64<PER>(t[1] - xr1, A.box, A.half);
+                    const double p2 = wrap64<PER>(t[2] - xr2, A.box, A.half);
+                    const double g0 = fmax(fmax(lo0 - p0, p0 - hi0), 0.0);
+                    const double g1 = fmax(fmax(lo1 - p1, p1 - hi1), 0.0);
+                    const double g2 = fmax(fmax(lo2 - p2, p2 - hi2), 0.0);
+                    near = fma(g0, g0, fma(g1, g1, g2 * g2)) < A.pf2;
+                }
+                for (uint64_t m = wave_mask(near); m; m &= m - 1) {
+                    const uint32_t e = base + (uint32_t)__builtin_ctzll(m);
+                    particle(R[e], e, desc);
+                }
+            }
+            c = end;
+        } else {
+            c = desc ? cu + 1u : r.skip;
+        }
     }
     if (valid) {
         double *res = (double *)A.res;
@@ -558,8 +631,6 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
         const float c0 = fmaf((float)((cm & -(1 << SH)) - G0), A.fu, -xr0);
         const float c1 = fmaf((float)(r.cy - G1), A.fu, -xr1);
         const float c2 = fmaf((float)(r.cz - G2), A.fu, -xr2);
-        const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
-        const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
         const uint32_t lev = (uint32_t)cm & kRecLevel;
         uint64_t keep = ~0ull;
         if (TPM) {
@@ -568,7 +639,14 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
             const float e1 = fmaxf(fabsf(c1) - hl, 0.0f);
             const float e2 = fmaxf(fabsf(c2) - hl, 0.0f);
             keep = wave_mask(!(fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) > A.frc2));
+            if (!(mine & keep)) {  // every lane here discards the cube
+                next = lane_in(mine) ? r.skip : next;
+                c = r.skip;
+                continue;
+            }
         }
+        const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
+        const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
         const float L2 = scale_level32(scale_level32(A.fL2r, lev), lev);
         uint64_t open;
         if (OPEN == TPM_OPEN_BH)
@@ -1044,11 +1122,12 @@ int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
 // apart (sparse active sets: a shared cursor would visit the union of their
 // walks) or when the interaction is expensive (FP64 with the erfc factor);
 // the shared cursor otherwise.  Both give identical results.
+// Independent lanes for sparse active sets, whose groups are too spread out
+// for a shared cursor; the shared cursor otherwise.
 static bool use_lanes(const tpm_ctx *c, int64_t n_act) {
     if (c->walk_mode != 0)
         return c->walk_mode == 2;
-    const bool fp64_tpm = c->P.precision == TPM_FP64 && c->P.pm_grid > 0;
-    return fp64_tpm || 4 * n_act < c->n;
+    return 4 * n_act < c->n;
 }
 
 static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
@@ -1101,6 +1180,9 @@ static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
         const double tol = ldexp(A.L, -16);
         A.fpf2 = (float)((rcut + tol) * (rcut + tol));
         A.fpf_ext = P.periodic ? (float)(0.5 * P.box_size - rcut - 2.0 * tol) : 3.0e38f;
+        const double tol64 = ldexp(A.L, -40);
+        A.pf2 = (rcut + tol64) * (rcut + tol64);
+        A.pf_ext = P.periodic ? 0.5 * P.box_size - rcut - 2.0 * tol64 : 1.0e300;
     }
     A.finv2rs = (float)A.inv2rs;
     A.res = c->res.p;
