@@ -231,7 +231,7 @@ int64_t tpm_bytes_needed(const tpm_params *p, int64_t n) {
         return -1;
     // per particle: sort buffers, ranks, sorted SoA, build scratch, active set,
     // results; per entry (estimated at 2.5 n): records, first/count, level list
-    const int64_t per_part = 16 + 8 + 4 + 4 + 24 + 8 + 8 + 1 + 4 + 4 + 4 + 12 + 24 + 8 + 4;
+    const int64_t per_part = 16 + 8 + 4 + 4 + 24 + 8 + 8 + 1 + 4 + 4 + 4 + 12 + 24 + 8 + 4 + 4;
     const int64_t per_entry = 64 + (p->precision == TPM_FP32 ? 32 : 0) + 12;
     int64_t b = n * per_part + (n * 5 / 2 + 64) * per_entry + (1 << 20);
     if (p->pm_grid > 0) {

@@ -106,80 +106,210 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t *out, int64_t 
 }
 
 // Radix sort ---------------------------------------------------------------
+//
+// Stable LSD sort, eight 8-bit digits, one kernel per digit (a single sweep
+// in the manner of Merrill & Garland's decoupled look-back scan).  The eight
+// digit histograms of all keys are counted once up front.  A pass's blocks
+// take tiles of 4096 keys in the order they start (an atomic tile counter),
+// rank their tile stably in LDS, publish the tile's digit counts, and find
+// the counts of all earlier tiles by looking back through the published
+// words; a tile then writes each digit's keys as one contiguous run.
 constexpr int kSortBlock = 256;
 constexpr int kSortRounds = 16;
 constexpr int kSortTile = kSortBlock * kSortRounds;  // 4096 keys per block
 constexpr int kRadix = 256;
+constexpr int kPasses = 8;
+// Look-back word of (tile, digit): flag in bits 32-33, count in bits 0-31.
+constexpr uint64_t kAggregate = 1ull << 32;  // this tile's own count
+constexpr uint64_t kInclusive = 2ull << 32;  // count of this and all earlier tiles
 
-__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint64_t *__restrict__ keys,
-                                                           int64_t n, int shift,
-                                                           uint32_t *__restrict__ hist,
-                                                           int nb) {
-    __shared__ uint32_t h[kRadix];
-    h[threadIdx.x] = 0;
+// The eight digit histograms of all keys (one read of the keys).
+__global__ __launch_bounds__(kSortBlock) void k_radix_count(const uint64_t *__restrict__ keys,
+                                                            int64_t n,
+                                                            unsigned long long *__restrict__ hist) {
+    __shared__ uint32_t h[kPasses][kRadix];
+    for (int k = threadIdx.x; k < kPasses * kRadix; k += kSortBlock)
+        (&h[0][0])[k] = 0u;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    // a wavefront takes chunks of 1024 keys, lane l the keys 16 l .. 16 l + 15
+    // of a chunk: keys of neighbouring lanes lie 16 apart in the input, whose
+    // order is often spatial, which keeps one instruction's atomics apart
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (kSortBlock / 64);
+    for (int64_t ch = (int64_t)blockIdx.x * (kSortBlock / 64) + (threadIdx.x >> 6);
+         ch * 1024 < n; ch += nw) {
 #pragma unroll 4
-    for (int r = 0; r < kSortRounds; r++) {
-        int64_t i = base + (int64_t)r * kSortBlock + threadIdx.x;
-        if (i < n)
-            atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+        for (int j = 0; j < 16; j++) {
+            const int64_t i = ch * 1024 + lane * 16 + j;
+            if (i < n) {
+                const uint64_t k = keys[i];
+#pragma unroll
+                for (int p = 0; p < kPasses; p++)
+                    atomicAdd(&h[p][(uint32_t)(k >> (8 * p)) & 255u], 1u);
+            }
+        }
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    for (int k = threadIdx.x; k < kPasses * kRadix; k += kSortBlock) {
+        const uint32_t v = (&h[0][0])[k];
+        if (v)
+            atomicAdd(&hist[k], (unsigned long long)v);
+    }
 }
 
-// Stable scatter: each round ranks 256 consecutive keys (4 wavefronts in
-// order); within a wavefront equal digits are matched with 8 ballots.
-__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
+__device__ __forceinline__ uint64_t load_word(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_word(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One digit pass.  ctr: this pass's tile counter; hist: its digit histogram;
+// look: its nb x 256 look-back words (all zero on entry).
+__global__ __launch_bounds__(kSortBlock) void k_radix_pass(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
-    const uint32_t *__restrict__ offs, int nb) {
-    __shared__ uint32_t s_run[kRadix];
-    __shared__ uint32_t s_w[kSortBlock / 64][kRadix];
+    unsigned long long *ctr, const unsigned long long *__restrict__ hist, uint64_t *look) {
+    __shared__ uint64_t s_k[kSortTile];
+    __shared__ uint32_t s_v[kSortTile];
+    __shared__ uint32_t s_wc[kSortBlock / 64][kRadix];  // per-wavefront digit counts
+    __shared__ uint32_t s_loc[kRadix];          // start of each digit's run in the tile
+    __shared__ uint32_t s_out[kRadix];          // output position of a run's first key
+    __shared__ uint32_t s_sc[kSortBlock / 64];
+    __shared__ uint32_t s_tile;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    s_run[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    if (tid == 0)
+        s_tile = (uint32_t)atomicAdd(ctr, 1ull);
+#pragma unroll
+    for (int q = 0; q < kSortBlock / 64; q++)
+        s_wc[q][tid] = 0u;
+    __syncthreads();
+    const uint32_t t = s_tile;
+    const int64_t base = (int64_t)t * kSortTile;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+
+    // 1. stable rank of every key among the keys with its digit in its
+    // wavefront's quarter of the tile (contiguous keys, no block barrier):
+    // a ballot match finds the lanes with the same digit, the wavefront's
+    // own counter in LDS gives the keys of that digit in earlier rounds
+    uint64_t k[kSortRounds];
+    uint32_t v[kSortRounds], pos[kSortRounds];
+    const int64_t wbase = base + (int64_t)w * (kSortTile / 4);
+#pragma unroll
     for (int r = 0; r < kSortRounds; r++) {
-        const int64_t i = base + (int64_t)r * kSortBlock + tid;
+        const int64_t i = wbase + (int64_t)r * 64 + lane;
         const bool valid = i < n;
-        uint64_t k = valid ? kin[i] : 0ull;
-        uint32_t v = valid ? vin[i] : 0u;
-        uint32_t d = (uint32_t)(k >> shift) & 255u;
+        k[r] = valid ? kin[i] : 0ull;
+        v[r] = valid ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
-            bool bit = (d >> b) & 1u;
-            uint64_t m = __ballot(bit);
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        const uint32_t cnt = (uint32_t)__popcll(peers);
+        const uint32_t prev = s_wc[w][d];
+        pos[r] = prev + rank;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0)
+            s_wc[w][d] = prev + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    uint32_t cnt = 0u;  // thread tid owns digit tid: wavefront counts -> bases
+#pragma unroll
+    for (int q = 0; q < kSortBlock / 64; q++) {
+        const uint32_t cq = s_wc[q][tid];
+        s_wc[q][tid] = cnt;
+        cnt += cq;
+    }
+
+    // 2. publish this tile's count of digit tid, then add up the earlier tiles
+    uint64_t *mine = look + (size_t)t * kRadix + tid;
+    uint32_t before = 0u;
+    if (t == 0) {
+        store_word(mine, kInclusive | cnt);
+    } else {
+        store_word(mine, kAggregate | cnt);
+        // every earlier tile has started (tile numbers follow start order)
+        // and publishes its own count before it looks back itself, so each
+        // wait below ends
+        // (eight earlier tiles' words per step, loaded together; tile 0 is
+        // inclusive, so the walk never reads before it)
+        for (int64_t j = (int64_t)t - 1;;) {
+            uint64_t wd[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++)
+                wd[q] = j - q >= 0 ? load_word(look + (size_t)(j - q) * kRadix + tid) : 0ull;
+            bool done = false;
+            int used = 0;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                if (done || used < q || !(wd[q] & (kAggregate | kInclusive)))
+                    continue;
+                before += (uint32_t)wd[q];
+                used = q + 1;
+                done = (wd[q] & kInclusive) != 0;
+            }
+            if (done)
+                break;
+            j -= used;
+            if (used < 8)
+                __builtin_amdgcn_s_sleep(1);  // tile j not published yet
+        }
+        store_word(mine, kInclusive | (before + cnt));
+    }
+
+    // 3. runs of the tile in digit order; global start of each run
+    uint32_t loc;
+    {
+        const uint32_t inc = wave_incl_scan(cnt, lane);
+        if (lane == 63)
+            s_sc[w] = inc;
+        uint32_t gh = 0u;
+        const uint32_t hd = (uint32_t)hist[tid];
+        const uint32_t ginc = wave_incl_scan(hd, lane);
+        __syncthreads();
+        uint32_t wb = 0u;
 #pragma unroll
         for (int q = 0; q < kSortBlock / 64; q++)
-            s_w[q][tid] = 0;
+            wb += q < w ? s_sc[q] : 0u;
+        loc = wb + inc - cnt;
         __syncthreads();
-        if (valid && rank == 0)
-            s_w[w][d] = cnt;
+        if (lane == 63)
+            s_sc[w] = ginc;
         __syncthreads();
-        {   // thread tid owns digit tid: turn wave counts into wave bases
-            uint32_t t = s_run[tid];
+        uint32_t gb = 0u;
 #pragma unroll
-            for (int q = 0; q < kSortBlock / 64; q++) {
-                uint32_t c = s_w[q][tid];
-                s_w[q][tid] = t;
-                t += c;
-            }
-            s_run[tid] = t;
+        for (int q = 0; q < kSortBlock / 64; q++)
+            gb += q < w ? s_sc[q] : 0u;
+        gh = gb + ginc - hd;  // keys with a smaller digit, over all tiles
+        s_loc[tid] = loc;
+        s_out[tid] = gh + before;
+    }
+    __syncthreads();
+
+    // 4. place the keys in tile order by digit, then write the runs out
+#pragma unroll
+    for (int r = 0; r < kSortRounds; r++) {
+        const int64_t i = wbase + (int64_t)r * 64 + lane;
+        if (i < n) {
+            const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+            const uint32_t slot = s_loc[d] + s_wc[w][d] + pos[r];
+            s_k[slot] = k[r];
+            s_v[slot] = v[r];
         }
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = s_w[w][d] + rank;
-            kout[pos] = k;
-            vout[pos] = v;
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+    const int64_t m = n - base < kSortTile ? n - base : kSortTile;
+    for (int j = tid; j < m; j += kSortBlock) {
+        const uint64_t kk = s_k[j];
+        const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+        const uint32_t g = s_out[d] + ((uint32_t)j - s_loc[d]);
+        kout[g] = kk;
+        vout[g] = s_v[j];
     }
 }
 
@@ -218,22 +348,26 @@ int scan_u32(tpm_ctx *c, const uint32_t *in, uint32_t *out, int64_t n, uint32_t 
 }
 
 int radix_sort_pairs(tpm_ctx *c, int64_t n) {
-    const int nb = (int)((n + kSortTile - 1) / kSortTile);
-    TPM_TRY(ensure(c, c->hist, (size_t)2 * kRadix * nb * sizeof(uint32_t)));
-    uint32_t *hist = (uint32_t *)c->hist.p;
-    uint32_t *offs = hist + (size_t)kRadix * nb;
-    int cur = 0;
+    const int64_t nb = (n + kSortTile - 1) / kSortTile;
+    // tile counters, digit histograms, look-back words of every pass
+    const int64_t words = kPasses + kPasses * kRadix + kPasses * nb * kRadix;
+    TPM_TRY(ensure(c, c->hist, (size_t)words * sizeof(uint64_t)));
+    unsigned long long *ctr = (unsigned long long *)c->hist.p;
+    unsigned long long *hist = ctr + kPasses;
+    uint64_t *look = (uint64_t *)(hist + kPasses * kRadix);
     TPM_TRY(timer_begin(c, TPM_TIMER_SORT));
-    for (int shift = 0; shift < 64; shift += 8) {
-        const uint64_t *kin = (const uint64_t *)c->key[cur].p;
-        const uint32_t *vin = (const uint32_t *)c->idx[cur].p;
-        k_radix_hist<<<nb, kSortBlock, 0, c->stream>>>(kin, n, shift, hist, nb);
-        TPM_LAUNCHED(c, "k_radix_hist");
-        TPM_TRY(scan_u32(c, hist, offs, (int64_t)kRadix * nb, nullptr));
-        k_radix_scatter<<<nb, kSortBlock, 0, c->stream>>>(
-            kin, vin, (uint64_t *)c->key[cur ^ 1].p, (uint32_t *)c->idx[cur ^ 1].p, n, shift,
-            offs, nb);
-        TPM_LAUNCHED(c, "k_radix_scatter");
+    TPM_TRY(fill_u64(c, (uint64_t *)ctr, 0ull, words));
+    const int64_t cb = nb < 1024 ? nb : 1024;
+    k_radix_count<<<(unsigned)cb, kSortBlock, 0, c->stream>>>(
+        (const uint64_t *)c->key[0].p, n, hist);
+    TPM_LAUNCHED(c, "k_radix_count");
+    int cur = 0;
+    for (int p = 0; p < kPasses; p++) {
+        k_radix_pass<<<(unsigned)nb, kSortBlock, 0, c->stream>>>(
+            (const uint64_t *)c->key[cur].p, (const uint32_t *)c->idx[cur].p,
+            (uint64_t *)c->key[cur ^ 1].p, (uint32_t *)c->idx[cur ^ 1].p, n, 8 * p, ctr + p,
+            hist + (size_t)p * kRadix, look + (size_t)p * nb * kRadix);
+        TPM_LAUNCHED(c, "k_radix_pass");
         cur ^= 1;
     }
     return timer_end(c, TPM_TIMER_SORT);  // eight passes: the result is back in buffer 0

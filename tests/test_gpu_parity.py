@@ -118,6 +118,27 @@ def test_tree_bit_exact(case):
     _tree_equal(g, T)
 
 
+def test_sort_many_tiles_bit_exact():
+    """Keys and stable sort order at 2^21 + 12345 particles (516 tiles of the
+    radix sort), with 6000 copies of one position spread over the whole index
+    range so that equal keys cross many tiles: identical to the oracle."""
+    n = (1 << 21) + 12345
+    rng = np.random.default_rng(21)
+    x, y, z = rng.uniform(-50.0, 50.0, (3, n))
+    dup = rng.choice(n, 6000, replace=False)
+    x[dup], y[dup], z[dup] = 1.25, -3.5, 7.0
+    p = W.Particles(x, y, z)
+    ctx = _ctx(eps=0.01)
+    _build(ctx, p)
+    g = ctx.export_tree()
+    fr = O.frame(x, y, z)
+    assert np.array_equal(g["frame"], fr)
+    _, _, key = O.positions(x, y, z, False, fr)
+    perm = O.sort(key)
+    assert np.array_equal(g["perm"], perm)
+    assert np.array_equal(g["key"], key[perm])
+
+
 def _oracle_params(ctx_kw, opening, eps, theta=0.5, alpha=0.0025, pot=False, frame=None):
     periodic = ctx_kw.get("periodic", False)
     box = ctx_kw.get("box_size", 0.0)
