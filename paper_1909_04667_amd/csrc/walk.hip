@@ -606,9 +606,10 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
         uint64_t inter = m & wave_mask(e != self);
         if (TPM)
             inter &= wave_mask(dd < A.frc2);
-        if (inter)
-            interact32_wave<TPM, POT, MIXED>(A, inter, r.gm, d0, d1, d2, dd, hp, a0, a1, a2, pot,
-                                             nint);
+        // unconditional: nearly every visited particle interacts with some
+        // lane, and a branch here costs more than the rare empty evaluation
+        interact32_wave<TPM, POT, MIXED>(A, inter, r.gm, d0, d1, d2, dd, hp, a0, a1, a2, pot,
+                                         nint);
     };
 
     // level sizes follow from the root's by exponent arithmetic (exact; on
