@@ -1124,11 +1124,16 @@ int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
 // walks) or when the interaction is expensive (FP64 with the erfc factor);
 // the shared cursor otherwise.  Both give identical results.
 // Independent lanes for sparse active sets, whose groups are too spread out
-// for a shared cursor; the shared cursor otherwise.
+// for a shared cursor, and for FP64 TreePM of isolated systems (their
+// outer groups span many cutoff radii, and the FP64 interaction is costly);
+// the shared cursor otherwise (measured on the 128^3 box and the Hernquist
+// sphere).
 static bool use_lanes(const tpm_ctx *c, int64_t n_act) {
     if (c->walk_mode != 0)
         return c->walk_mode == 2;
-    return 4 * n_act < c->n;
+    const bool fp64_iso_tpm =
+        c->P.precision == TPM_FP64 && c->P.pm_grid > 0 && !c->P.periodic;
+    return fp64_iso_tpm || 4 * n_act < c->n;
 }
 
 static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
