@@ -122,6 +122,7 @@ static void free_all(tpm_ctx *c) {
         b->cap = 0;
     }
     c->green_tab_ng = 0;
+    c->axis_tables_M = 0;
     if (c->hpin)
         (void)hipHostFree(c->hpin);
     c->hpin = nullptr;

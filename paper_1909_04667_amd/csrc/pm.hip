@@ -239,8 +239,8 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__rest
                                                 const unsigned long long *__restrict__ mq,
                                                 T *__restrict__ phi, const Cx<T> *__restrict__ tw,
                                                 const double *__restrict__ gk2,
-                                                const double *__restrict__ gdc, double gconst,
-                                                double rs, const double *__restrict__ gtab,
+                                                const double *__restrict__ gq, double gconst,
+                                                const double *__restrict__ gtab,
                                                 const Rec64 *__restrict__ rec, double vinv,
                                                 double norm) {
     constexpr int NG = R1 * R2, C = R1 / R2, PAD = R2 + 1;
@@ -321,9 +321,9 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__rest
                     g = gconst * gtab[((size_t)ii * GH + jj) * GH + kk];
                 } else {
                     const double k2s = (gk2[i] + gk2[jline]) + gk2[kline];
-                    const double dc = (gdc[i] * gdc[jline]) * gdc[kline];
+                    const double q = (gq[i] * gq[jline]) * gq[kline];
                     if (k2s != 0.0)
-                        g = gconst * exp(-k2s * rs * rs) / (k2s * dc);
+                        g = gconst * q / k2s;
                 }
                 const Cx<T> v = line[i];
                 a[n1] = Cx<T>{(T)(v.re * g), (T)(v.im * g)};
@@ -449,8 +449,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_out(
 }
 
 struct FftArgs {
-    const double *gk2 = nullptr, *gdc = nullptr, *gtab = nullptr;
-    double gconst = 0.0, rs = 0.0, vinv = 1.0, norm = 1.0;
+    const double *gk2 = nullptr, *gq = nullptr, *gtab = nullptr;
+    double gconst = 0.0, vinv = 1.0, norm = 1.0;
     const Rec64 *rec = nullptr;
 };
 
@@ -468,8 +468,8 @@ int launch_fft(tpm_ctx *c, const FftPass &fp, Cx<T> *mc, const unsigned long lon
     const size_t lds = (size_t)B * R1 * (R2 + 1) * sizeof(Cx<T>);
     const unsigned blocks = (unsigned)((size_t)NG * NG / B);
     k_fft<T, R1, R2><<<blocks, kBlock, lds, c->stream>>>(fp, B, mc, mq, phi, tw, fa.gk2,
-                                                         fa.gdc, fa.gconst, fa.rs, fa.gtab,
-                                                         fa.rec, fa.vinv, fa.norm);
+                                                         fa.gq, fa.gconst, fa.gtab, fa.rec,
+                                                         fa.vinv, fa.norm);
     TPM_LAUNCHED(c, "k_fft");
     return TPM_OK;
 }
@@ -624,19 +624,24 @@ int solve_t(tpm_ctx *c) {
     TPM_TRY(ensure(c, c->mesh_phi, n3 * sizeof(T)));
     TPM_TRY(ensure(c, c->twiddle, (size_t)M * sizeof(Cx<T>) + 64));
     TPM_TRY(ensure(c, c->green_axis, (size_t)2 * M * sizeof(double)));
-    // tables, computed in double on the host
-    {
+    // tables, computed in double on the host once per context (they depend
+    // on the mesh size and the fixed parameters only).  Periodic Green's
+    // function per axis: k_a^2 and exp(-k_a^2 r_s^2) / sinc^4(k_a h / 2);
+    // the filter and the deconvolution are products over the axes, so a
+    // mesh point needs three multiplications and one division.
+    if (c->axis_tables_M != M) {
         const std::vector<Cx<T>> tw = twiddles<T>(M);
         std::vector<double> g(2 * M, 0.0);
         if (!iso) {
             const double box = P.box_size, h = mg.h;
+            const double rs = P.asmth * P.box_size / P.pm_grid;
             for (int i = 0; i < M; i++) {
                 const int nn = i < M / 2 ? i : i - M;
                 const double kv = 2.0 * M_PI * nn / box;
                 const double s = 0.5 * kv * h;
                 const double sc = nn == 0 ? 1.0 : std::sin(s) / s;
                 g[i] = kv * kv;
-                g[M + i] = sc * sc * sc * sc;
+                g[M + i] = std::exp(-(kv * kv) * (rs * rs)) / (sc * sc * sc * sc);
             }
         }
         TPM_HIP(c, hipMemcpyAsync(c->twiddle.p, tw.data(), tw.size() * sizeof(Cx<T>),
@@ -645,6 +650,7 @@ int solve_t(tpm_ctx *c) {
                                   hipMemcpyHostToDevice, st));
         // host vectors die at scope end: wait for the copies
         TPM_HIP(c, hipStreamSynchronize(st));
+        c->axis_tables_M = M;
     }
     unsigned long long *mq = (unsigned long long *)c->mesh_q.p;
     TPM_TRY(fill_u64(c, (uint64_t *)mq, 0ull, (int64_t)n3));
@@ -662,9 +668,8 @@ int solve_t(tpm_ctx *c) {
         fa.vinv = 1.0;
     } else {
         fa.gk2 = (const double *)c->green_axis.p;
-        fa.gdc = fa.gk2 + M;
+        fa.gq = fa.gk2 + M;
         fa.gconst = -4.0 * M_PI * P.G;
-        fa.rs = P.asmth * P.box_size / P.pm_grid;
         fa.vinv = 1.0 / (mg.h * mg.h * mg.h);
     }
     Cx<T> *mc = (Cx<T> *)c->mesh_c.p;

@@ -108,9 +108,10 @@ struct tpm_ctx {
     tpm::DBuf mesh_c;           // complex work mesh
     tpm::DBuf mesh_phi;         // real potential
     tpm::DBuf twiddle;          // FFT twiddles
-    tpm::DBuf green_axis;       // per-axis k^2 and deconvolution tables
+    tpm::DBuf green_axis;       // per-axis k^2 and filter / deconvolution tables
     tpm::DBuf green_tab;        // isolated mesh: transformed kernel, one octant
     int green_tab_ng = 0;       // pm_grid the table was built for (0: none)
+    int axis_tables_M = 0;      // mesh size the twiddle and axis tables hold (0: none)
     // measurement: event pairs per timer class, and a pool of spare events
     int timing = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[8];
