@@ -67,12 +67,54 @@ __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_in
 
 // ---- FP64 arithmetic (fixed operation order, explicit fma) -------------------
 
+// 1/d from the hardware reciprocal and two Newton steps (within an ulp, not
+// correctly rounded: used only inside erfc, d >= 4).
+__device__ __forceinline__ double rcp_refined64(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
+// e^y for y <= 0 (the argument is -x^2): Cody & Waite's reduction y = k ln2 +
+// r, |r| <= ln2 / 2, with ln2 split into a double and its remainder, then the
+// Taylor series of e^r to degree 13 (remainder below 6e-18 relative) scaled
+// by 2^k.  Arguments below -1000 give 0, as e^y does in double.
+__device__ __forceinline__ double exp_neg64(double y) {
+    constexpr double kLog2e = 0x1.71547652b82fep+0;
+    constexpr double kLn2Hi = 0x1.62e42fefa39efp-1, kLn2Lo = 0x1.abc9e3b39803fp-56;
+    constexpr double kInvFact[14] = {1.0,
+                                     1.0,
+                                     1.0 / 2.0,
+                                     1.0 / 6.0,
+                                     1.0 / 24.0,
+                                     1.0 / 120.0,
+                                     1.0 / 720.0,
+                                     1.0 / 5040.0,
+                                     1.0 / 40320.0,
+                                     1.0 / 362880.0,
+                                     1.0 / 3628800.0,
+                                     1.0 / 39916800.0,
+                                     1.0 / 479001600.0,
+                                     1.0 / 6227020800.0};
+    y = y > -1000.0 ? y : -1000.0;
+    const double k = rint(y * kLog2e);
+    double r = fma(-k, kLn2Hi, y);
+    r = fma(-k, kLn2Lo, r);
+    double p = kInvFact[13];
+#pragma unroll
+    for (int j = 12; j >= 0; j--)
+        p = fma(p, r, kInvFact[j]);
+    return ldexp(p, (int)k);
+}
+
 // Scaled complementary error function exp(x^2) erfc(x) = t g(t), t = 4/(4+x),
 // g a degree-20 polynomial in s = (4 - x)/(4 + x) (coefficients in
 // erfc_poly.h, relative error below 5e-15 for x >= 0): no branches, and
 // exp(-x^2) is shared with the Gaussian term of the short-range factor.
 __device__ __forceinline__ double erfc_scaled64(double x) {
-    const double rd = 1.0 / (4.0 + x);
+    const double rd = rcp_refined64(4.0 + x);
     const double sv = (4.0 - x) * rd;
     double g = kErfcPoly[kErfcDegree];
 #pragma unroll
@@ -126,7 +168,7 @@ __device__ __forceinline__ void interact64(const WalkArgs &A, double m, double d
     }
     if (TPM) {
         const double x = r * A.inv2rs;
-        const double gx = exp(-(x * x));
+        const double gx = exp_neg64(-(x * x));
         const double ec = gx * erfc_scaled64(x);
         fac = fac * (ec + (x * 1.1283791670955126) * gx);
         if (POT)
@@ -200,7 +242,7 @@ __device__ __forceinline__ void interact64_wave(const WalkArgs &A, uint64_t inte
     if (TPM) {
         // lanes that do not interact take a harmless argument
         const double x = inter ? r * A.inv2rs : 1.0;
-        const double gx = exp(-(x * x));
+        const double gx = exp_neg64(-(x * x));
         const double ec = gx * erfc_scaled64(x);
         fac = fac * (ec + (x * 1.1283791670955126) * gx);
         if (POT)
