@@ -181,13 +181,14 @@ __device__ __forceinline__ void interact64(const WalkArgs &A, double m, double d
         pot += phi;
 }
 
+// Nearest image of a difference |d| < box: d - box if d > box / 2, d + box
+// if d < -box / 2 (the same operations and results as the two-sided test,
+// without branches).
 template <bool PER>
 __device__ __forceinline__ double wrap64(double d, double box, double half) {
     if (PER) {
-        if (d > half)
-            d -= box;
-        else if (d < -half)
-            d += box;
+        const double t = d - copysign(box, d);
+        d = fabs(d) > half ? t : d;
     }
     return d;
 }
