@@ -152,6 +152,15 @@ def _oracle_params(ctx_kw, opening, eps, theta=0.5, alpha=0.0025, pot=False, fra
                          rcut=ctx_kw.get("rcut", 4.5) * rs if ng else 0.0, want_pot=pot)
 
 
+def _pile_box(seed):
+    """Zel'dovich box with 150 particles moved onto one point: a cell whose
+    150 particles are the children of one cube (more than a wavefront)."""
+    p = W.zeldovich_box(16, 100.0, seed)
+    x, y, z = p.x.copy(), p.y.copy(), p.z.copy()
+    x[:150], y[:150], z[:150] = 37.5, 12.25, 81.0
+    return W.Particles(x, y, z)
+
+
 FORCE_CASES = {
     "plummer_bh": (lambda: W.plummer(4096, 1), dict(eps=0.01, theta=0.5), "bh"),
     "plummer_rel": (lambda: W.plummer(4096, 1), dict(eps=0.01, theta=0.5), "rel"),
@@ -176,6 +185,17 @@ FORCE_CASES = {
     "mixed_box_rel": (lambda: W.lognormal_box(16, 100.0, 13),
                       dict(eps=100.0 / 800, periodic=True, box_size=100.0, pm_grid=32,
                            indiv_eps=3), "rel"),
+    # r_cut = 35 against a half box of 50: groups wider than 15 walk without
+    # the leaf-run prefilter (all of them here, some of them when clustered)
+    "box_wide_cutoff": (lambda: W.zeldovich_box(16, 100.0, 14),
+                        dict(eps=100.0 / 800, periodic=True, box_size=100.0, pm_grid=16), "bh"),
+    "box_clustered_wide_cutoff": (lambda: W.lognormal_box(16, 100.0, 15),
+                                  dict(eps=100.0 / 800, periodic=True, box_size=100.0,
+                                       pm_grid=16), "rel"),
+    "box_pile_bh": (lambda: _pile_box(16),
+                    dict(eps=100.0 / 800, periodic=True, box_size=100.0, pm_grid=32), "bh"),
+    "box_pile_rel": (lambda: _pile_box(17),
+                     dict(eps=100.0 / 800, periodic=True, box_size=100.0, pm_grid=32), "rel"),
 }
 
 
