@@ -6,10 +6,12 @@
 // Layout: mesh index (i * ng + j) * ng + k, i <-> x.  The deposit accumulates
 // 62-bit fixed-point masses with integer atomics, so the mesh is independent
 // of particle order (deterministic).  The 3-D FFT runs as five passes over
-// the complex mesh: forward z (reading the fixed-point mesh), forward y,
+// the half spectrum of the real mesh (kz = 0 .. ng/2): forward z (reading the
+// fixed-point mesh, two real lines per complex transform), forward y,
 // [forward x, Green's function, inverse x] fused in LDS, inverse y, inverse z
-// (writing the real potential).  Each pass loads a block of lines into LDS
-// (coalesced along the contiguous axis) and runs a radix-2 Stockham FFT.
+// (writing the real potential, again two lines per transform).  Each pass
+// holds a block of lines in registers and LDS (coalesced along the
+// contiguous axis).
 // The gradient is taken inside the interpolation kernel from the potential.
 #include "tpm_internal.h"
 
@@ -189,11 +191,18 @@ __device__ __forceinline__ void dft_regs(Cx<T> *v) {
 }
 
 struct FftPass {
-    int axis;        // 0: x (stride ng^2), 1: y (stride ng), 2: z (contiguous)
+    int axis;        // 0: x, 1: y, 2: z (contiguous)
     int in_fixed;    // read the fixed-point deposit (axis 2, forward only)
     int out_real;    // write the scaled real part (axis 2, inverse only)
     int inverse;
     int green;       // forward, multiply by the Green's function, inverse
+    // Half spectrum of a real mesh: the complex mesh holds kz = 0 .. ng/2
+    // only, (i * ng + j) * (ng/2 + 1) + kz.  The z passes then transform two
+    // real lines (j, j + 1) as one complex line: forward, their spectra are
+    // C[k] +- conj(C[ng - k]) halves; inverse, C = A + i B is rebuilt from the
+    // two half spectra by Hermitian symmetry and its real and imaginary parts
+    // are the two real lines.  Otherwise the mesh is fully complex.
+    int half;
 };
 
 // One line transform: on entry thread n2 holds a[n1] = x[R2 n1 + n2]; on exit
@@ -243,10 +252,9 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__rest
                                                 const double *__restrict__ gtab,
                                                 const Rec64 *__restrict__ rec, double vinv,
                                                 double norm) {
-    constexpr int NG = R1 * R2, C = R1 / R2, PAD = R2 + 1;
+    constexpr int NG = R1 * R2, C = R1 / R2, PAD = R2 + 1, H = NG / 2 + 1;
     extern __shared__ unsigned char lds_raw[];
     Cx<T> *lds = (Cx<T> *)lds_raw;  // B rows of R1 x (R2 + 1)
-    const size_t ng2 = (size_t)NG * NG;
     const int tid = threadIdx.x;
     int b, n2;
     if (ps.axis == 2) {  // contiguous lines: a line's threads adjacent
@@ -256,22 +264,29 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__rest
         n2 = tid / B;
         b = tid % B;
     }
-    const bool active = b < B && n2 < R2 && tid < B * R2;
+    bool active = b < B && n2 < R2 && tid < B * R2;
     size_t base, stride;
+    size_t hb = 0;             // half spectrum of the first line of a z pair
     int jline = 0, kline = 0;  // (y, z) of an x line, for the Green's function
     if (ps.axis == 2) {
-        base = ((size_t)blockIdx.x * B + b) * NG;
+        if (ps.half) {  // line pair (j, j + 1): real lines base, base + NG
+            const size_t pr = (size_t)blockIdx.x * B + b;
+            const size_t i = pr / (NG / 2), j = 2 * (pr % (NG / 2));
+            base = (i * NG + j) * NG;
+            hb = (i * NG + j) * H;
+        } else {
+            base = ((size_t)blockIdx.x * B + b) * NG;
+        }
         stride = 1;
     } else {
-        const int per = NG / B;
-        const size_t outer = blockIdx.x / per, kb = blockIdx.x % per;
-        if (ps.axis == 1)
-            base = outer * ng2 + kb * B + b;
-        else
-            base = outer * NG + kb * B + b;
-        stride = ps.axis == 1 ? (size_t)NG : ng2;
+        const int W = ps.half ? H : NG;  // lines per value of the outer index
+        const int per = (W + B - 1) / B;
+        const size_t outer = blockIdx.x / per, kz = (size_t)(blockIdx.x % per) * B + b;
+        active = active && kz < (size_t)W;
+        base = ps.axis == 1 ? outer * NG * W + kz : outer * W + kz;
+        stride = ps.axis == 1 ? (size_t)W : (size_t)NG * W;
         jline = (int)outer;
-        kline = (int)(kb * B + b);
+        kline = (int)kz;
     }
     Cx<T> *row = lds + (size_t)(active ? b : 0) * R1 * PAD;
     double qscale = 0.0;
@@ -284,11 +299,20 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__rest
     if (active) {
 #pragma unroll
         for (int n1 = 0; n1 < R1; n1++) {
-            const size_t g = base + (size_t)(R2 * n1 + n2) * stride;
-            if (ps.in_fixed)
-                a[n1] = Cx<T>{(T)((double)mq[g] * qscale), (T)0};
-            else
-                a[n1] = mesh[g];
+            const int pos = R2 * n1 + n2;
+            if (ps.in_fixed) {
+                const size_t g = base + (size_t)pos;
+                a[n1] = Cx<T>{(T)((double)mq[g] * qscale),
+                              ps.half ? (T)((double)mq[g + NG] * qscale) : (T)0};
+            } else if (ps.half && ps.axis == 2) {
+                // C[k] = A_k + i B_k; above ng/2 from A_(ng-k) = conj(A_k)
+                const int kk = pos <= NG / 2 ? pos : NG - pos;
+                const Cx<T> A = mesh[hb + kk], Bv = mesh[hb + H + kk];
+                a[n1] = pos <= NG / 2 ? Cx<T>{A.re - Bv.im, A.im + Bv.re}
+                                      : Cx<T>{A.re + Bv.im, Bv.re - A.im};
+            } else {
+                a[n1] = mesh[base + (size_t)pos * stride];
+            }
         }
     }
     if (ps.inverse && !ps.green)
@@ -332,17 +356,41 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__rest
         __syncthreads();
         line_fft<T, true, R1, R2>(a, o, row, n2, tw, active);
     }
+    if (ps.half && ps.in_fixed) {
+        // two real lines from one transform: A_k = (C_k + conj C_-k) / 2,
+        // B_k = (C_k - conj C_-k) / 2i, k = 0 .. ng/2
+        Cx<T> *line = row;
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < C; c++)
+#pragma unroll
+                for (int k2 = 0; k2 < R2; k2++)
+                    line[(n2 + c * R2) + R1 * k2] = o[c * R2 + k2];
+        }
+        __syncthreads();
+        if (active) {
+            for (int k = n2; k <= NG / 2; k += R2) {
+                const Cx<T> ck = line[k], cm = line[(NG - k) & (NG - 1)];
+                mesh[hb + k] = Cx<T>{(T)0.5 * (ck.re + cm.re), (T)0.5 * (ck.im - cm.im)};
+                mesh[hb + H + k] = Cx<T>{(T)0.5 * (ck.im + cm.im), (T)0.5 * (cm.re - ck.re)};
+            }
+        }
+        return;
+    }
     if (active) {
 #pragma unroll
         for (int c = 0; c < C; c++)
 #pragma unroll
             for (int k2 = 0; k2 < R2; k2++) {
-                const size_t g = base + (size_t)((n2 + c * R2) + R1 * k2) * stride;
+                const size_t pos = (size_t)((n2 + c * R2) + R1 * k2);
                 const Cx<T> v = o[c * R2 + k2];
-                if (ps.out_real)
-                    phi[g] = (T)(v.re * norm);
-                else
-                    mesh[g] = v;
+                if (ps.out_real) {
+                    phi[base + pos] = (T)(v.re * norm);
+                    if (ps.half)
+                        phi[base + NG + pos] = (T)(v.im * norm);
+                } else {
+                    mesh[base + pos * stride] = v;
+                }
             }
     }
 }
@@ -466,7 +514,11 @@ int launch_fft(tpm_ctx *c, const FftPass &fp, Cx<T> *mc, const unsigned long lon
     if (B > NG)
         B = NG;
     const size_t lds = (size_t)B * R1 * (R2 + 1) * sizeof(Cx<T>);
-    const unsigned blocks = (unsigned)((size_t)NG * NG / B);
+    size_t lines = (size_t)NG * NG;
+    if (fp.half)  // z: line pairs; x, y: ng/2 + 1 lines per outer index
+        lines = fp.axis == 2 ? (size_t)NG * (NG / 2)
+                             : (size_t)NG * (((NG / 2 + 1) + B - 1) / B) * B;
+    const unsigned blocks = (unsigned)(lines / B);
     k_fft<T, R1, R2><<<blocks, kBlock, lds, c->stream>>>(fp, B, mc, mq, phi, tw, fa.gk2,
                                                          fa.gq, fa.gconst, fa.gtab, fa.rec,
                                                          fa.vinv, fa.norm);
@@ -620,7 +672,8 @@ int solve_t(tpm_ctx *c) {
     if (iso)
         TPM_TRY(build_green_isolated(c));
     TPM_TRY(ensure(c, c->mesh_q, n3 * 8));
-    TPM_TRY(ensure(c, c->mesh_c, n3 * sizeof(Cx<T>)));
+    // half spectrum of the real mesh: kz = 0 .. M/2
+    TPM_TRY(ensure(c, c->mesh_c, (size_t)M * M * (M / 2 + 1) * sizeof(Cx<T>)));
     TPM_TRY(ensure(c, c->mesh_phi, n3 * sizeof(T)));
     TPM_TRY(ensure(c, c->twiddle, (size_t)M * sizeof(Cx<T>) + 64));
     TPM_TRY(ensure(c, c->green_axis, (size_t)2 * M * sizeof(double)));
@@ -675,8 +728,8 @@ int solve_t(tpm_ctx *c) {
     Cx<T> *mc = (Cx<T> *)c->mesh_c.p;
     T *phi = (T *)c->mesh_phi.p;
     const Cx<T> *tw = (const Cx<T> *)c->twiddle.p;
-    const FftPass passes[5] = {
-        {2, 1, 0, 0, 0}, {1, 0, 0, 0, 0}, {0, 0, 0, 0, 1}, {1, 0, 0, 1, 0}, {2, 0, 1, 1, 0}};
+    const FftPass passes[5] = {{2, 1, 0, 0, 0, 1}, {1, 0, 0, 0, 0, 1}, {0, 0, 0, 0, 1, 1},
+                               {1, 0, 0, 1, 0, 1}, {2, 0, 1, 1, 0, 1}};
     for (const FftPass &fp : passes)
         TPM_TRY(fft_pass<T>(c, M, fp, mc, mq, phi, tw, fa));
     return TPM_OK;
