@@ -383,8 +383,8 @@ def cpu_baseline(p, kw, sample, cfg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; the multi-GPU design is "
-                          "described in DESIGN.md and not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "only one GPU is measured: the library runs the whole path "
+                          "on a single device and has no multi-GPU code", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     c, p, kw = workload(args.config)

@@ -20,7 +20,7 @@
  *     finite differences, interpolation                     (Sec. 3.3, 3.4)
  *   - the same for isolated systems: zero-padded mesh and the
  *     real-space long-range Green's function                (Sec. 3.3)
- * plus the exact references the method is judged against: direct O(N^2)
+ * plus the exact references the method is checked against: direct O(N^2)
  * summation and an Ewald sum for periodic boxes (Sec. 3.1, Ewald paragraph).
  *
  * Readings of points the paper leaves open:
