@@ -1162,15 +1162,12 @@ int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
     return TPM_OK;
 }
 
-// Walk variant: independent lanes when the 64 targets of a group are far
-// apart (sparse active sets: a shared cursor would visit the union of their
-// walks) or when the interaction is expensive (FP64 with the erfc factor);
-// the shared cursor otherwise.  Both give identical results.
-// Independent lanes for sparse active sets, whose groups are too spread out
-// for a shared cursor, and for FP64 TreePM of isolated systems (their
-// outer groups span many cutoff radii, and the FP64 interaction is costly);
-// the shared cursor otherwise (measured on the 128^3 box and the Hernquist
-// sphere).
+// Walk variant (both give identical results): independent lanes for sparse
+// active sets, whose groups are too spread out for a shared cursor (it would
+// visit the union of their walks), and for FP64 TreePM of isolated systems
+// (their outer groups span many cutoff radii, and the FP64 interaction is
+// costly); the shared cursor otherwise (measured on the 128^3 box and the
+// Hernquist sphere).
 static bool use_lanes(const tpm_ctx *c, int64_t n_act) {
     if (c->walk_mode != 0)
         return c->walk_mode == 2;
