@@ -3,15 +3,18 @@
 //
 // One wavefront walks the depth-first entry list for 64 active particles that
 // are adjacent on the Peano-Hilbert curve.  The wave keeps ONE cursor: every
-// lane owns a "next" index (the entry its own depth-first walk needs next);
-// lanes whose next equals the cursor evaluate the entry, lanes that accepted
-// or discarded an ancestor sit out until the cursor reaches their next.  The
+// lane owns a "next" index (the entry its own depth-first walk needs next,
+// or an earlier one while it is inside a cube it opened); lanes whose next
+// is at or before the cursor evaluate the entry, lanes that accepted or
+// discarded an ancestor sit out until the cursor reaches their next.  The
 // cursor descends (c + 1) when any lane opens the entry and otherwise jumps
-// to the entry's skip pointer -- that is the minimum of all lanes' next, since
+// to the entry's skip pointer -- the next entry of some lane's walk, since
 // subtrees nest.  Entries are read with wave-uniform (scalar) loads, so each
 // lane sees exactly the entry sequence of its own recursive walk, in order:
 // the FP64 path reproduces a sequential FP64 walk bit for bit apart from the
-// last bits of erfc/exp.
+// last bits of erfc/exp.  With a cutoff, entries that can interact with no
+// lane of the wavefront are skipped (particles of opened leaf parents beyond
+// r_cut of the group's bounding box, cubes every lane discards).
 #include "tpm_internal.h"
 #include "erfc_poly.h"
 
