@@ -114,10 +114,11 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t *out, int64_t 
 // rank their tile stably in LDS, publish the tile's digit counts, and find
 // the counts of all earlier tiles by looking back through the published
 // words; a tile then writes each digit's keys as one contiguous run.
-constexpr int kSortBlock = 256;
-constexpr int kSortRounds = 16;
+constexpr int kSortBlock = 512;
+constexpr int kSortRounds = 8;
 constexpr int kSortTile = kSortBlock * kSortRounds;  // 4096 keys per block
-constexpr int kRadix = 256;
+constexpr int kSortWaves = kSortBlock / 64;
+constexpr int kRadix = 256;  // digit values; threads 0 .. 255 own one each
 constexpr int kPasses = 8;
 // Look-back word of (tile, digit): flag in bits 32-33, count in bits 0-31.
 constexpr uint64_t kAggregate = 1ull << 32;  // this tile's own count
@@ -172,29 +173,29 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_pass(
     unsigned long long *ctr, const unsigned long long *__restrict__ hist, uint64_t *look) {
     __shared__ uint64_t s_k[kSortTile];
     __shared__ uint32_t s_v[kSortTile];
-    __shared__ uint32_t s_wc[kSortBlock / 64][kRadix];  // per-wavefront digit counts
+    __shared__ uint32_t s_wc[kSortWaves][kRadix];  // per-wavefront digit counts
     __shared__ uint32_t s_loc[kRadix];          // start of each digit's run in the tile
     __shared__ uint32_t s_out[kRadix];          // output position of a run's first key
-    __shared__ uint32_t s_sc[kSortBlock / 64];
+    __shared__ uint32_t s_sc[kRadix / 64];
     __shared__ uint32_t s_tile;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const bool owner = tid < kRadix;  // thread tid owns digit tid
     if (tid == 0)
         s_tile = (uint32_t)atomicAdd(ctr, 1ull);
-#pragma unroll
-    for (int q = 0; q < kSortBlock / 64; q++)
-        s_wc[q][tid] = 0u;
+    for (int q = tid; q < kSortWaves * kRadix; q += kSortBlock)
+        (&s_wc[0][0])[q] = 0u;
     __syncthreads();
     const uint32_t t = s_tile;
     const int64_t base = (int64_t)t * kSortTile;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     // 1. stable rank of every key among the keys with its digit in its
-    // wavefront's quarter of the tile (contiguous keys, no block barrier):
+    // wavefront's share of the tile (contiguous keys, no block barrier):
     // a ballot match finds the lanes with the same digit, the wavefront's
     // own counter in LDS gives the keys of that digit in earlier rounds
     uint64_t k[kSortRounds];
     uint32_t v[kSortRounds], pos[kSortRounds];
-    const int64_t wbase = base + (int64_t)w * (kSortTile / 4);
+    const int64_t wbase = base + (int64_t)w * (kSortTile / kSortWaves);
 #pragma unroll
     for (int r = 0; r < kSortRounds; r++) {
         const int64_t i = wbase + (int64_t)r * 64 + lane;
@@ -218,76 +219,80 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_pass(
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    uint32_t cnt = 0u;  // thread tid owns digit tid: wavefront counts -> bases
+    uint32_t cnt = 0u;  // wavefront counts of digit tid -> wavefront bases
+    if (owner) {
 #pragma unroll
-    for (int q = 0; q < kSortBlock / 64; q++) {
-        const uint32_t cq = s_wc[q][tid];
-        s_wc[q][tid] = cnt;
-        cnt += cq;
+        for (int q = 0; q < kSortWaves; q++) {
+            const uint32_t cq = s_wc[q][tid];
+            s_wc[q][tid] = cnt;
+            cnt += cq;
+        }
     }
 
     // 2. publish this tile's count of digit tid, then add up the earlier tiles
-    uint64_t *mine = look + (size_t)t * kRadix + tid;
     uint32_t before = 0u;
-    if (t == 0) {
-        store_word(mine, kInclusive | cnt);
-    } else {
-        store_word(mine, kAggregate | cnt);
-        // every earlier tile has started (tile numbers follow start order)
-        // and publishes its own count before it looks back itself, so each
-        // wait below ends
-        // (eight earlier tiles' words per step, loaded together; tile 0 is
-        // inclusive, so the walk never reads before it)
-        for (int64_t j = (int64_t)t - 1;;) {
-            uint64_t wd[8];
+    if (owner) {
+        uint64_t *mine = look + (size_t)t * kRadix + tid;
+        if (t == 0) {
+            store_word(mine, kInclusive | cnt);
+        } else {
+            store_word(mine, kAggregate | cnt);
+            // every earlier tile has started (tile numbers follow start order)
+            // and publishes its own count before it looks back itself, so each
+            // wait below ends
+            // (eight earlier tiles' words per step, loaded together; tile 0 is
+            // inclusive, so the walk never reads before it)
+            for (int64_t j = (int64_t)t - 1;;) {
+                uint64_t wd[8];
 #pragma unroll
-            for (int q = 0; q < 8; q++)
-                wd[q] = j - q >= 0 ? load_word(look + (size_t)(j - q) * kRadix + tid) : 0ull;
-            bool done = false;
-            int used = 0;
+                for (int q = 0; q < 8; q++)
+                    wd[q] = j - q >= 0 ? load_word(look + (size_t)(j - q) * kRadix + tid) : 0ull;
+                bool done = false;
+                int used = 0;
 #pragma unroll
-            for (int q = 0; q < 8; q++) {
-                if (done || used < q || !(wd[q] & (kAggregate | kInclusive)))
-                    continue;
-                before += (uint32_t)wd[q];
-                used = q + 1;
-                done = (wd[q] & kInclusive) != 0;
+                for (int q = 0; q < 8; q++) {
+                    if (done || used < q || !(wd[q] & (kAggregate | kInclusive)))
+                        continue;
+                    before += (uint32_t)wd[q];
+                    used = q + 1;
+                    done = (wd[q] & kInclusive) != 0;
+                }
+                if (done)
+                    break;
+                j -= used;
+                if (used < 8)
+                    __builtin_amdgcn_s_sleep(1);  // tile j not published yet
             }
-            if (done)
-                break;
-            j -= used;
-            if (used < 8)
-                __builtin_amdgcn_s_sleep(1);  // tile j not published yet
+            store_word(mine, kInclusive | (before + cnt));
         }
-        store_word(mine, kInclusive | (before + cnt));
     }
 
-    // 3. runs of the tile in digit order; global start of each run
-    uint32_t loc;
+    // 3. runs of the tile in digit order; global start of each run (the
+    // digit owners are wavefronts 0 .. kRadix/64 - 1)
     {
+        const uint32_t hd = owner ? (uint32_t)hist[tid] : 0u;
         const uint32_t inc = wave_incl_scan(cnt, lane);
-        if (lane == 63)
-            s_sc[w] = inc;
-        uint32_t gh = 0u;
-        const uint32_t hd = (uint32_t)hist[tid];
         const uint32_t ginc = wave_incl_scan(hd, lane);
+        if (owner && lane == 63)
+            s_sc[w] = inc;
         __syncthreads();
         uint32_t wb = 0u;
 #pragma unroll
-        for (int q = 0; q < kSortBlock / 64; q++)
+        for (int q = 0; q < kRadix / 64; q++)
             wb += q < w ? s_sc[q] : 0u;
-        loc = wb + inc - cnt;
+        const uint32_t loc = wb + inc - cnt;
         __syncthreads();
-        if (lane == 63)
+        if (owner && lane == 63)
             s_sc[w] = ginc;
         __syncthreads();
         uint32_t gb = 0u;
 #pragma unroll
-        for (int q = 0; q < kSortBlock / 64; q++)
+        for (int q = 0; q < kRadix / 64; q++)
             gb += q < w ? s_sc[q] : 0u;
-        gh = gb + ginc - hd;  // keys with a smaller digit, over all tiles
-        s_loc[tid] = loc;
-        s_out[tid] = gh + before;
+        if (owner) {
+            s_loc[tid] = loc;
+            s_out[tid] = gb + ginc - hd + before;  // keys with a smaller digit + earlier tiles
+        }
     }
     __syncthreads();
 
