@@ -48,6 +48,7 @@ struct WalkArgs {
     double L2r, limr, hlr;
     // single-precision copies
     float fu, fL, ftheta2, falpha, fh2, fhinv, fh3inv, frc2, finv2rs;
+    float fgexp;  // -log2(e) / (2 r_s)^2: exp(-x^2) = exp2(d^2 fgexp), x = r / (2 r_s)
     float fL2r, flimr, fhlr;
     // leaf-run prefilter: (r_cut + tolerance)^2, and the largest group
     // extent from its reference cell for which the reference cell's nearest
@@ -473,19 +474,19 @@ __device__ __forceinline__ void interact32(const WalkArgs &A, float gm, float d0
             phi = (gm * hinv) * spline_phi32(u);
     }
     if (TPM) {
-        // erfc by Abramowitz & Stegun 7.1.26 (|error| < 1.5e-7), sharing
-        // exp(-x^2) with the Gaussian term of the short-range factor
+        // erfc(x) = t P(t) exp(-x^2) by Abramowitz & Stegun 7.1.26 (|error|
+        // < 1.5e-7); the force factor erfc(x) + (2/sqrt(pi)) x exp(-x^2)
+        // shares exp(-x^2), taken from d^2 directly
         const float x = r * A.finv2rs;
-        const float g = __builtin_amdgcn_exp2f(-(x * x) * 1.44269504f);
+        const float g = __builtin_amdgcn_exp2f(dd * A.fgexp);
         const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
-        const float poly =
+        const float tp =
             t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f),
                              -0.284496736f),
                      0.254829592f);
-        const float ec = poly * g;
-        fac *= fmaf(x * 1.12837917f, g, ec);
+        fac *= g * fmaf(x, 1.12837917f, tp);
         if (POT)
-            phi *= ec;
+            phi *= tp * g;
     }
     a0 = fmaf(fac, d0, a0);
     a1 = fmaf(fac, d1, a1);
@@ -541,18 +542,17 @@ __device__ __forceinline__ void interact32_wave(const WalkArgs &A, uint64_t inte
         if (TPM)
             r = soft ? rr : r;
     }
-    if (TPM) {
+    if (TPM) {  // as in interact32
         const float x = r * A.finv2rs;
-        const float g = __builtin_amdgcn_exp2f(-(x * x) * 1.44269504f);
+        const float g = __builtin_amdgcn_exp2f(dd * A.fgexp);
         const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
-        const float poly =
+        const float tp =
             t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f),
                              -0.284496736f),
                      0.254829592f);
-        const float ec = poly * g;
-        fac *= fmaf(x * 1.12837917f, g, ec);
+        fac *= g * fmaf(x, 1.12837917f, tp);
         if (POT)
-            phi *= ec;
+            phi *= tp * g;
     }
     fac = inter ? fac : 0.0f;
     a0 = fmaf(fac, d0, a0);
@@ -1234,6 +1234,7 @@ static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
         A.pf_ext = P.periodic ? 0.5 * P.box_size - rcut - 2.0 * tol64 : 1.0e300;
     }
     A.finv2rs = (float)A.inv2rs;
+    A.fgexp = (float)(-1.4426950408889634 * A.inv2rs * A.inv2rs);
     A.res = c->res.p;
     A.rpot = c->rpot.p;
     A.rnint = (uint32_t *)c->rnint.p;
