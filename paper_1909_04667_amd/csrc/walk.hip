@@ -214,26 +214,24 @@ __device__ __forceinline__ double spline_phi64_sel(double u) {
     return u < 0.5 ? inner : outer;
 }
 
-// The interaction of interact64 for the lanes with `inter` set, executed by
-// the whole wavefront (callers branch on "some lane interacts", a uniform
-// condition); per-lane choices are selects, so every interacting lane gets
-// exactly interact64's result.
+// The force and potential factors of interact64 (fac and phi, before the
+// products with the difference vector), computed by the whole wavefront for
+// one pair per lane; `used` marks the lanes whose factors are used (the
+// others may hold any pair, even a coincident one).  Per-lane choices are
+// selects, so each lane gets exactly interact64's factors for its pair.
 template <bool TPM, bool POT, bool MIXED>
-__device__ __forceinline__ void interact64_wave(const WalkArgs &A, uint64_t inter_m, double m,
-                                                double d0, double d1, double d2, double dd,
-                                                double hp, double &a0, double &a1, double &a2,
-                                                double &pot, uint32_t &nint) {
-    const bool inter = lane_in(inter_m);
+__device__ __forceinline__ void factor64(const WalkArgs &A, uint64_t used, double m, double dd,
+                                         double hp, double &fac, double &phi) {
     const double Gm = A.G * m;
     const double r = sqrt(dd);
     const double rinv = 1.0 / r;
     const double h = MIXED ? hp : A.h;
-    double fac = Gm * rinv * rinv * rinv;
-    double phi = 0.0;
+    fac = Gm * rinv * rinv * rinv;
+    phi = 0.0;
     if (POT)
         phi = -Gm * rinv;
     const bool soft = r < h;
-    if (inter_m & wave_mask(soft)) {
+    if (used & wave_mask(soft)) {
         double hinv = A.hinv, h3inv = A.h3inv;
         if (MIXED) {
             hinv = 1.0 / h;
@@ -245,21 +243,62 @@ __device__ __forceinline__ void interact64_wave(const WalkArgs &A, uint64_t inte
             phi = soft ? (Gm * hinv) * spline_phi64_sel(u) : phi;
     }
     if (TPM) {
-        // lanes that do not interact take a harmless argument
-        const double x = inter ? r * A.inv2rs : 1.0;
+        const double x = r * A.inv2rs;
         const double gx = exp_neg64(-(x * x));
         const double ec = gx * erfc_scaled64(x);
         fac = fac * (ec + (x * 1.1283791670955126) * gx);
         if (POT)
             phi = phi * ec;
     }
-    fac = inter ? fac : 0.0;
-    a0 = fma(fac, d0, a0);
-    a1 = fma(fac, d1, a1);
-    a2 = fma(fac, d2, a2);
-    if (POT)
-        pot += inter ? phi : 0.0;
-    nint += inter ? 1u : 0u;
+}
+
+// Interaction queue of one wavefront in the FP64 walk with a cutoff.  A step
+// of the walk interacts some of the 64 targets with one entry, and with the
+// cutoff most steps take only a few lanes.  So a step appends its pairs (in
+// lane order) and its lane mask instead of evaluating at once; when more
+// than 64 pairs are pending, the pairs queued before the last step are
+// evaluated one per lane, and each target then adds its own pairs in the
+// order of the steps: the same products and sums, in the same order, as an
+// immediate evaluation.  Pairs and steps sit in rings of 128, so a step is
+// stored before the evaluation that it triggers (its values need not stay in
+// registers across it).  Without a cutoff nearly every step takes most lanes
+// and the walk evaluates at once.
+constexpr uint32_t kQueue = 64;
+constexpr uint32_t kAccSteps = 2;
+constexpr uint32_t kRing = 128;
+struct IQ64 {
+    double d[3][kRing];  // difference vector, entry minus target
+    double m[kRing];     // mass; after evaluation the force factor
+    double h[kRing];     // larger softening; after evaluation the potential factor
+    uint64_t step[kRing];
+};
+
+// Orders the wavefront's LDS accesses (lanes read what other lanes wrote).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Number of lanes of m below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Record i for a wavefront-uniform i, read through the constant address
+// space (the tree does not change during a walk): scalar loads, whatever
+// fences the walk holds for its LDS queue.
+__device__ __forceinline__ Rec64 uniform_rec(const Rec64 *R, uint32_t i) {
+    typedef __attribute__((address_space(4))) const uint64_t cword;
+    const cword *w = (const cword *)(R + i);
+    uint64_t v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        v[k] = w[k];
+    Rec64 r;
+    __builtin_memcpy(&r, v, sizeof r);
+    return r;
 }
 
 // Side of a level-`lev` cube, scaled from the root side through the exponent
@@ -272,7 +311,7 @@ __device__ __forceinline__ double scale_level(double v, uint32_t lev) {
 // cursor and the entry are wavefront-uniform; each lane decides for itself
 // (as masks) and only branches on wavefront-uniform conditions are taken.
 template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
-__device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
+__device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave, IQ64 *Q) {
     const int lane = threadIdx.x & 63;
     const uint32_t nu = *A.nuniq;
     if (wave * 64u >= nu)
@@ -324,6 +363,108 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
         prefilter = ext < A.pf_ext;
     }
 
+    // queue state (wavefront-uniform): ring heads of the pending pairs and
+    // steps, and their counts
+    uint32_t qh = 0, qn = 0, sh = 0, ns = 0;
+    // evaluate the first n (<= 64) pending pairs, then add those of the
+    // first `steps` pending steps to their targets
+    auto flush = [&](uint32_t n, uint32_t steps) {
+        wave_sync();
+        const bool own = (uint32_t)lane < n;
+        const uint32_t i = (qh + (own ? (uint32_t)lane : 0u)) & (kRing - 1u);
+        {
+            const double d0 = Q->d[0][i], d1 = Q->d[1][i], d2 = Q->d[2][i];
+            double fac, phi;
+            factor64<TPM, POT, MIXED>(A, wave_mask(own), Q->m[i],
+                                      fma(d0, d0, fma(d1, d1, d2 * d2)),
+                                      MIXED ? Q->h[i] : 0.0, fac, phi);
+            wave_sync();
+            if (own) {
+                Q->m[i] = fac;
+                if (POT)
+                    Q->h[i] = phi;
+            }
+        }
+        // lane j holds the mask of step j
+        const uint64_t sv = Q->step[(sh + (uint32_t)lane) & (kRing - 1u)];
+        const uint32_t svl = (uint32_t)sv, svh = (uint32_t)(sv >> 32);
+        wave_sync();
+        // kAccSteps steps at a time: their loads are issued together, and
+        // each lane adds only the pairs of steps that it is in, in order
+        uint32_t b = qh;
+        for (uint32_t j = 0; j < steps; j += kAccSteps) {
+            bool in[kAccSteps];
+            uint32_t pp[kAccSteps];
+#pragma unroll
+            for (uint32_t u = 0; u < kAccSteps; ++u) {
+                const uint32_t jj = min(j + u, 63u);
+                const uint32_t ml = __builtin_amdgcn_readlane(svl, jj);
+                const uint32_t mh = __builtin_amdgcn_readlane(svh, jj);
+                const uint64_t m = j + u < steps ? ((uint64_t)mh << 32) | ml : 0ull;
+                in[u] = lane_in(m);
+                pp[u] = (b + lanes_below(m)) & (kRing - 1u);
+                b += (uint32_t)__builtin_popcountll(m);
+            }
+            double f[kAccSteps], x[kAccSteps], y[kAccSteps], z[kAccSteps], ph[kAccSteps];
+#pragma unroll
+            for (uint32_t u = 0; u < kAccSteps; ++u) {
+                f[u] = Q->m[pp[u]];
+                x[u] = Q->d[0][pp[u]];
+                y[u] = Q->d[1][pp[u]];
+                z[u] = Q->d[2][pp[u]];
+                ph[u] = POT ? Q->h[pp[u]] : 0.0;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kAccSteps; ++u) {
+                a0 = in[u] ? fma(f[u], x[u], a0) : a0;
+                a1 = in[u] ? fma(f[u], y[u], a1) : a1;
+                a2 = in[u] ? fma(f[u], z[u], a2) : a2;
+                if (POT)
+                    pot = in[u] ? pot + ph[u] : pot;
+            }
+        }
+        wave_sync();
+        qh = (qh + n) & (kRing - 1u);
+        sh = (sh + steps) & (kRing - 1u);
+    };
+    // the lanes in `inter` (not empty) interact with an entry of mass m
+    auto push = [&](uint64_t inter, double m, double d0, double d1, double d2, double dd,
+                    double hp) {
+        nint += lane_in(inter) ? 1u : 0u;
+        if (!TPM) {  // evaluate at once (fma(0, d, a) == a for the other lanes)
+            double fac, phi;
+            factor64<TPM, POT, MIXED>(A, inter, m, dd, hp, fac, phi);
+            const bool in = lane_in(inter);
+            fac = in ? fac : 0.0;
+            a0 = fma(fac, d0, a0);
+            a1 = fma(fac, d1, a1);
+            a2 = fma(fac, d2, a2);
+            if (POT)
+                pot += in ? phi : 0.0;
+            return;
+        }
+        const uint32_t k = (uint32_t)__builtin_popcountll(inter);
+        if (lane_in(inter)) {
+            const uint32_t p = (qh + qn + lanes_below(inter)) & (kRing - 1u);
+            Q->d[0][p] = d0;
+            Q->d[1][p] = d1;
+            Q->d[2][p] = d2;
+            Q->m[p] = m;
+            if (MIXED)
+                Q->h[p] = hp;
+        }
+        if (lane == 0)
+            Q->step[(sh + ns) & (kRing - 1u)] = inter;
+        if (qn + k > kQueue) {  // at most 64 pending before this step
+            flush(qn, ns);
+            qn = k;
+            ns = 1;
+        } else {
+            qn += k;
+            ++ns;
+        }
+    };
+
     // one particle entry e (wavefront-uniform) for the lanes in m
     auto particle = [&](const Rec64 &r, uint32_t e, uint64_t m) {
         const double he = MIXED ? ((const double *)A.eh)[e] : 0.0;
@@ -336,14 +477,13 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
         if (TPM)
             inter &= wave_mask(dd < A.rc2);
         if (inter)
-            interact64_wave<TPM, POT, MIXED>(A, inter, r.mass, d0, d1, d2, dd, hp, a0, a1, a2,
-                                             pot, nint);
+            push(inter, r.mass, d0, d1, d2, dd, hp);
     };
 
     uint32_t c = 0;
     while (c < A.E) {
         const uint32_t cu = __builtin_amdgcn_readfirstlane(c);
-        const Rec64 r = R[cu];
+        const Rec64 r = uniform_rec(R, cu);
         const uint64_t mine = wave_mask(next <= cu);
         if (r.meta & kParticleFlag) {
             particle(r, cu, mine);
@@ -392,8 +532,7 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
         const uint64_t desc = mine & open;
         next = lane_in(mine & ~open) ? r.skip : next;
         if (inter)
-            interact64_wave<TPM, POT, MIXED>(A, inter, r.mass, d0, d1, d2, dd, hp, a0, a1, a2,
-                                             pot, nint);
+            push(inter, r.mass, d0, d1, d2, dd, hp);
         if (TPM && desc && (r.meta & kLeafParentFlag) && prefilter) {
             const uint32_t end = r.skip;
             for (uint32_t base = cu + 1u; base < end; base += 64u) {
@@ -411,7 +550,7 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
                 }
                 for (uint64_t m = wave_mask(near); m; m &= m - 1) {
                     const uint32_t e = base + (uint32_t)__builtin_ctzll(m);
-                    particle(R[e], e, desc);
+                    particle(uniform_rec(R, e), e, desc);
                 }
             }
             c = end;
@@ -419,6 +558,8 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave) {
             c = desc ? cu + 1u : r.skip;
         }
     }
+    if (TPM && qn)
+        flush(qn, ns);
     if (valid) {
         double *res = (double *)A.res;
         res[slot] = a0;
@@ -513,7 +654,8 @@ __device__ __forceinline__ float spline_phi32_sel(float u) {
 }
 
 // interact32 for the lanes with `inter` set, executed by the whole wavefront
-// (see interact64_wave); identical results for those lanes.
+// (callers branch on "some lane interacts", a uniform condition); per-lane
+// choices are selects, so the interacting lanes get exactly interact32's result.
 template <bool TPM, bool POT, bool MIXED>
 __device__ __forceinline__ void interact32_wave(const WalkArgs &A, uint64_t inter_m, float gm,
                                                 float d0, float d1, float d2, float dd, float hp,
@@ -766,7 +908,12 @@ __device__ __forceinline__ uint32_t wave_id() {
 
 template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_walk64(const WalkArgs A) {
-    walk_group64<PER, TPM, OPEN, POT, MIXED>(A, wave_id());
+    IQ64 *Q = nullptr;  // the interaction queue, with a cutoff
+    if constexpr (TPM) {
+        __shared__ IQ64 q[kBlock / 64];
+        Q = &q[threadIdx.x >> 6];
+    }
+    walk_group64<PER, TPM, OPEN, POT, MIXED>(A, wave_id(), Q);
 }
 
 template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
@@ -1329,28 +1476,29 @@ struct BatchReq {
 };
 
 template <bool FP32, bool PER, bool TPM, int OPEN, bool MIXED>
-__device__ __forceinline__ void batch_group(const WalkArgs &A, uint32_t g, bool lanes) {
-    if (lanes) {
-        if (FP32)
+__device__ __forceinline__ void batch_group(const WalkArgs &A, uint32_t g, bool lanes, IQ64 *Q) {
+    if constexpr (FP32) {
+        if (lanes)
             walk_lanes32<PER, TPM, OPEN, false, MIXED>(A, g, 1u);
         else
-            walk_lanes64<PER, TPM, OPEN, false, MIXED>(A, g, 1u);
-    } else {
-        if (FP32)
             walk_group32<PER, TPM, OPEN, false, MIXED>(A, g);
+    } else {
+        if (lanes)
+            walk_lanes64<PER, TPM, OPEN, false, MIXED>(A, g, 1u);
         else
-            walk_group64<PER, TPM, OPEN, false, MIXED>(A, g);
+            walk_group64<PER, TPM, OPEN, false, MIXED>(A, g, Q);
     }
 }
 
 template <bool FP32, int OPEN, bool MIXED>
-__device__ __forceinline__ void batch_geometry(const BatchReq &R, uint32_t g, bool lanes) {
+__device__ __forceinline__ void batch_geometry(const BatchReq &R, uint32_t g, bool lanes,
+                                               IQ64 *Q) {
     if (R.variant & 8u)  // periodic box (always with the mesh)
-        batch_group<FP32, true, true, OPEN, MIXED>(R.A, g, lanes);
+        batch_group<FP32, true, true, OPEN, MIXED>(R.A, g, lanes, Q);
     else if (R.variant & 2u)  // isolated TreePM
-        batch_group<FP32, false, true, OPEN, MIXED>(R.A, g, lanes);
+        batch_group<FP32, false, true, OPEN, MIXED>(R.A, g, lanes, Q);
     else
-        batch_group<FP32, false, false, OPEN, MIXED>(R.A, g, lanes);
+        batch_group<FP32, false, false, OPEN, MIXED>(R.A, g, lanes, Q);
 }
 
 template <bool FP32>
@@ -1358,6 +1506,11 @@ __global__ __launch_bounds__(kBlock) void k_walk_batch(const BatchReq *__restric
                                                        uint32_t nreq, uint32_t nitems,
                                                        uint32_t *__restrict__ counter) {
     const int lane = threadIdx.x & 63;
+    IQ64 *Q = nullptr;  // the FP64 walk's interaction queue (used with a cutoff)
+    if constexpr (!FP32) {
+        __shared__ IQ64 q[kBlock / 64];
+        Q = &q[threadIdx.x >> 6];
+    }
     for (;;) {
         uint32_t item = 0;
         if (lane == 0)
@@ -1379,14 +1532,14 @@ __global__ __launch_bounds__(kBlock) void k_walk_batch(const BatchReq *__restric
         const bool rel = (R.variant & 1u) != 0, mixed = (R.variant & 16u) != 0;
         if (rel) {
             if (mixed)
-                batch_geometry<FP32, TPM_OPEN_REL, true>(R, g, lanes);
+                batch_geometry<FP32, TPM_OPEN_REL, true>(R, g, lanes, Q);
             else
-                batch_geometry<FP32, TPM_OPEN_REL, false>(R, g, lanes);
+                batch_geometry<FP32, TPM_OPEN_REL, false>(R, g, lanes, Q);
         } else {
             if (mixed)
-                batch_geometry<FP32, TPM_OPEN_BH, true>(R, g, lanes);
+                batch_geometry<FP32, TPM_OPEN_BH, true>(R, g, lanes, Q);
             else
-                batch_geometry<FP32, TPM_OPEN_BH, false>(R, g, lanes);
+                batch_geometry<FP32, TPM_OPEN_BH, false>(R, g, lanes, Q);
         }
     }
 }
