@@ -1501,8 +1501,11 @@ __device__ __forceinline__ void batch_geometry(const BatchReq &R, uint32_t g, bo
         batch_group<FP32, false, false, OPEN, MIXED>(R.A, g, lanes, Q);
 }
 
+// The FP64 instance inlines every walk variant and would take 143 VGPRs
+// (three wavefronts per SIMD); held to 128 (four) it spills 13 dwords and
+// serves 4-5 % more force evaluations per second.
 template <bool FP32>
-__global__ __launch_bounds__(kBlock) void k_walk_batch(const BatchReq *__restrict__ reqs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_walk_batch(const BatchReq *__restrict__ reqs,
                                                        uint32_t nreq, uint32_t nitems,
                                                        uint32_t *__restrict__ counter) {
     const int lane = threadIdx.x & 63;
