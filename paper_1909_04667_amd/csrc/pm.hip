@@ -40,69 +40,160 @@ struct MeshGeom {
     int ng;  // points per axis of the transformed mesh
 };
 
+// CIC base cell and weights of the particle at sorted slot s (Sec. 3.3):
+// mesh points at i h, weights (1 - w, w) on cells i0 and i0 + 1 per axis.
+// Any input (even outside the box or NaN) stays on the mesh.
+__device__ __forceinline__ void cic_cell(const double *__restrict__ ps, int64_t n, int64_t s,
+                                         const MeshGeom &mg, int i0[3], double w[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        double u = ps[(size_t)a * n + s] - mg.lo[a];
+        if (mg.box > 0.0) {
+            if (u < 0.0)
+                u += mg.box;
+            if (u >= mg.box)
+                u -= mg.box;
+        }
+        const double f = u / mg.h;
+        const double fl = floor(f);
+        w[a] = f - fl;
+        int i = (int)fmin(fmax(fl, -1.0e9), 1.0e9) % mg.ng;
+        if (i < 0)
+            i += mg.ng;
+        i0[a] = i;
+    }
+}
+
+// The deposit as 62-bit fixed-point integers (order-independent, hence
+// deterministic).  A workgroup takes kDepChunk consecutive particles in curve
+// order, a compact region of the mesh: their contributions are summed in an
+// LDS tile over the region's bounding box (cell offsets from the chunk's
+// first particle, nearest image), and the tile is added to the mesh row by
+// row, so the device-scope atomics of a wavefront hit consecutive cells.  A
+// chunk whose box exceeds the tile adds its contributions directly.
+constexpr int kDepPer = 1;
+constexpr int kDepChunk = kBlock * kDepPer;
+constexpr int kDepTile = 3072;  // cells (24 KB)
+
 __global__ __launch_bounds__(kBlock) void k_deposit(const double *__restrict__ ps,
                                                     const double *__restrict__ ms, int64_t n,
                                                     const Rec64 *__restrict__ rec, MeshGeom mg,
                                                     unsigned long long *__restrict__ mesh) {
-    const double box = mg.box, h = mg.h;
-    const int ng = mg.ng;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool live = s < n;
-    const int lane = threadIdx.x & 63;
-    const uint64_t le = ~0ull >> (63 - lane);  // lanes 0..lane
+    __shared__ unsigned long long tile[kDepTile];
+    __shared__ int red[6][kBlock / 64];
+    __shared__ int refc[3];
+    const int ng = mg.ng, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t s0 = (int64_t)blockIdx.x * kDepChunk;  // < n
     int ex;
     frexp(rec[0].mass, &ex);  // total mass < 2^ex
     const double scale = ldexp(1.0, 62 - ex);
-    int i0[3] = {0, 0, 0};
-    double w[3] = {0.0, 0.0, 0.0};
+    int i0[kDepPer][3], o[kDepPer][3];
+    double w[kDepPer][3], m[kDepPer];
+    bool live[kDepPer];
+#pragma unroll
+    for (int p = 0; p < kDepPer; p++) {
+        const int64_t s = s0 + p * kBlock + tid;
+        live[p] = s < n;
+        cic_cell(ps, n, live[p] ? s : s0, mg, i0[p], w[p]);
+        m[p] = live[p] ? ms[s] : 0.0;
+    }
+    if (tid == 0) {  // the chunk's first particle is thread 0's first
+        refc[0] = i0[0][0];
+        refc[1] = i0[0][1];
+        refc[2] = i0[0][2];
+    }
+    __syncthreads();
+    int lo[3], hi[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        double u = live ? ps[(size_t)a * n + s] - mg.lo[a] : 0.0;
-        if (box > 0.0) {
-            if (u < 0.0)
-                u += box;
-            if (u >= box)
-                u -= box;
+        lo[a] = ng;
+        hi[a] = -ng;
+#pragma unroll
+        for (int p = 0; p < kDepPer; p++) {
+            int d = i0[p][a] - refc[a];  // nearest image, |d| <= ng / 2
+            if (2 * d > ng)
+                d -= ng;
+            if (2 * d < -ng)
+                d += ng;
+            o[p][a] = live[p] ? d : 0;
+            lo[a] = min(lo[a], o[p][a]);
+            hi[a] = max(hi[a], o[p][a]);
         }
-        const double f = u / h;
-        const double fl = floor(f);
-        w[a] = f - fl;
-        // any input (even outside the box or NaN) stays on the mesh
-        int i = (int)fmin(fmax(fl, -1.0e9), 1.0e9) % ng;
-        if (i < 0)
-            i += ng;
-        i0[a] = i;
+        for (int k = 1; k < 64; k <<= 1) {
+            lo[a] = min(lo[a], __shfl_xor(lo[a], k));
+            hi[a] = max(hi[a], __shfl_xor(hi[a], k));
+        }
+        if (lane == 0) {
+            red[a][wv] = lo[a];
+            red[3 + a][wv] = hi[a];
+        }
     }
-    const double m = live ? ms[s] : 0.0;
-    // Particles are in curve order, so neighbouring lanes often hit the same
-    // cells: sum equal cells across the wavefront first (integers, so the
-    // result does not depend on the grouping) and issue one atomic per run.
+    __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 8; c++) {
-        double wt = 1.0;
-        int t[3];
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            const int up = (c >> (2 - a)) & 1;
-            wt *= up ? w[a] : 1.0 - w[a];
-            t[a] = up ? (i0[a] + 1 == ng ? 0 : i0[a] + 1) : i0[a];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = red[a][0];
+        hi[a] = red[3 + a][0];
+        for (int q = 1; q < kBlock / 64; q++) {
+            lo[a] = min(lo[a], red[a][q]);
+            hi[a] = max(hi[a], red[3 + a][q]);
         }
-        const uint32_t cell =
-            live ? (uint32_t)(((size_t)t[0] * ng + t[1]) * ng + t[2]) : 0xffffffffu;
-        unsigned long long q = live ? __double2ull_rn(m * wt * scale) : 0ull;
-        const uint32_t prev = __shfl_up(cell, 1, 64);
-        const bool head = lane == 0 || prev != cell;
-        const uint64_t heads = __ballot(head);
-        const uint32_t seg = (uint32_t)__popcll(heads & le);  // run id of this lane
+    }
+    // the tile spans offsets lo .. hi + 1 (the upper CIC neighbours)
+    const int D0 = hi[0] - lo[0] + 2, D1 = hi[1] - lo[1] + 2, D2 = hi[2] - lo[2] + 2;
+    const int64_t V = (int64_t)D0 * D1 * D2;
+    if (V <= kDepTile) {
+        for (int k = tid; k < (int)V; k += kBlock)
+            tile[k] = 0ull;
+        __syncthreads();
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {  // suffix sums within each run
-            const unsigned long long oq = __shfl_down(q, off, 64);
-            const uint32_t os = __shfl_down(seg, off, 64);
-            if (lane + off < 64 && os == seg)
-                q += oq;
+        for (int p = 0; p < kDepPer; p++) {
+            if (!live[p])
+                continue;
+#pragma unroll
+            for (int c = 0; c < 8; c++) {
+                double wt = 1.0;
+                int t[3];
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    const int up = (c >> (2 - a)) & 1;
+                    wt *= up ? w[p][a] : 1.0 - w[p][a];
+                    t[a] = o[p][a] - lo[a] + up;
+                }
+                atomicAdd(&tile[(t[0] * D1 + t[1]) * D2 + t[2]],
+                          __double2ull_rn(m[p] * wt * scale));
+            }
         }
-        if (live && head)
-            atomicAdd(&mesh[cell], q);
+        __syncthreads();
+        for (int k = tid; k < (int)V; k += kBlock) {
+            const unsigned long long v = tile[k];
+            if (v) {
+                const int l2 = k % D2, l1 = (k / D2) % D1, l0 = k / (D1 * D2);
+                int g[3] = {refc[0] + lo[0] + l0, refc[1] + lo[1] + l1, refc[2] + lo[2] + l2};
+#pragma unroll
+                for (int a = 0; a < 3; a++)
+                    g[a] = ((g[a] % ng) + ng) % ng;
+                atomicAdd(&mesh[((size_t)g[0] * ng + g[1]) * ng + g[2]], v);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < kDepPer; p++) {
+            if (!live[p])
+                continue;
+#pragma unroll
+            for (int c = 0; c < 8; c++) {
+                double wt = 1.0;
+                int t[3];
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    const int up = (c >> (2 - a)) & 1;
+                    wt *= up ? w[p][a] : 1.0 - w[p][a];
+                    t[a] = up ? (i0[p][a] + 1 == ng ? 0 : i0[p][a] + 1) : i0[p][a];
+                }
+                atomicAdd(&mesh[((size_t)t[0] * ng + t[1]) * ng + t[2]],
+                          __double2ull_rn(m[p] * wt * scale));
+            }
+        }
     }
 }
 
@@ -707,7 +798,7 @@ int solve_t(tpm_ctx *c) {
     }
     unsigned long long *mq = (unsigned long long *)c->mesh_q.p;
     TPM_TRY(fill_u64(c, (uint64_t *)mq, 0ull, (int64_t)n3));
-    k_deposit<<<grid_for(c->n, kBlock), kBlock, 0, st>>>(
+    k_deposit<<<grid_for(c->n, kDepChunk), kBlock, 0, st>>>(
         (const double *)c->ps.p, (const double *)c->ms.p, c->n, (const Rec64 *)c->rec64.p, mg,
         mq);
     TPM_LAUNCHED(c, "k_deposit");
