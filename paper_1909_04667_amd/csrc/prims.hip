@@ -330,7 +330,83 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
         p[i] = v;
 }
 
+// Compaction of the slots r with mark[r] == epoch, in increasing r: phase 1
+// counts them per tile of kScanTile slots.
+__global__ __launch_bounds__(kScanBlock) void k_mark_count(const uint32_t *__restrict__ mark,
+                                                           int64_t n, uint32_t epoch,
+                                                           uint32_t *__restrict__ counts) {
+    __shared__ uint32_t s_w[kScanBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t t = 0;
+    for (int k = threadIdx.x; k < kScanTile; k += kScanBlock) {
+        const int64_t r = base + k;
+        t += (r < n && mark[r] == epoch) ? 1u : 0u;
+    }
+    uint32_t excl;
+    const uint32_t tot = block_excl_scan(t, s_w, excl);
+    if (threadIdx.x == 0)
+        counts[blockIdx.x] = tot;
+}
+
+// Phase 2: a tile's offset is the sum of the earlier tiles' counts (read
+// here, a few per thread); the tile's own slots are ranked with a block scan.
+// Writes act[pos] = r and slot[r] = pos; workgroup 0 also writes the total.
+__global__ __launch_bounds__(kScanBlock) void k_mark_compact(
+    const uint32_t *__restrict__ mark, int64_t n, uint32_t epoch,
+    const uint32_t *__restrict__ counts, uint32_t *__restrict__ act,
+    uint32_t *__restrict__ slot, uint32_t *__restrict__ d_total) {
+    __shared__ uint32_t s_w[kScanBlock / 64];
+    const uint32_t b = blockIdx.x, nb = gridDim.x;
+    uint32_t before = 0, all = 0;
+    for (uint32_t q = threadIdx.x; q < nb; q += kScanBlock) {
+        const uint32_t v = counts[q];
+        before += q < b ? v : 0u;
+        all += v;
+    }
+    uint32_t excl;
+    const uint32_t off = block_excl_scan(before, s_w, excl);
+    const uint32_t total = block_excl_scan(all, s_w, excl);
+    if (b == 0 && threadIdx.x == 0)
+        *d_total = total;
+    const int64_t base = (int64_t)b * kScanTile;
+    uint32_t f[kScanItems], t = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        const int64_t r = base + threadIdx.x * kScanItems + j;
+        f[j] = (r < n && mark[r] == epoch) ? 1u : 0u;
+        t += f[j];
+    }
+    uint32_t pos;
+    block_excl_scan(t, s_w, pos);
+    pos += off;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        if (f[j]) {
+            const uint32_t r = (uint32_t)(base + threadIdx.x * kScanItems + j);
+            act[pos] = r;
+            slot[r] = pos;
+            ++pos;
+        }
+    }
+}
+
 }  // namespace
+
+int compact_marked(tpm_ctx *c, const uint32_t *mark, uint32_t epoch, int64_t n, uint32_t *act,
+                   uint32_t *slot, uint32_t *d_total) {
+    if (n <= 0)
+        return fill_u32(c, d_total, 0u, 1);
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    TPM_TRY(ensure(c, c->scan_tmp, (size_t)nb * sizeof(uint32_t)));
+    uint32_t *counts = (uint32_t *)c->scan_tmp.p;
+    k_mark_count<<<(unsigned)nb, kScanBlock, 0, c->stream>>>(mark, n, epoch, counts);
+    TPM_LAUNCHED(c, "k_mark_count");
+    k_mark_compact<<<(unsigned)nb, kScanBlock, 0, c->stream>>>(mark, n, epoch, counts, act, slot,
+                                                               d_total);
+    TPM_LAUNCHED(c, "k_mark_compact");
+    return TPM_OK;
+}
+
 
 int scan_u32(tpm_ctx *c, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *d_total) {
     if (n <= 0) {

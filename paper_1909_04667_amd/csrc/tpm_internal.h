@@ -139,6 +139,10 @@ size_t bytes_held(const tpm_ctx *c);
 // Primitives (prims.hip) ---------------------------------------------------
 // Exclusive scan of n uint32 values; total written to d_total if non-null.
 int scan_u32(tpm_ctx *c, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *d_total);
+// act[0 .. total) = the slots r < n with mark[r] == epoch, increasing;
+// slot[r] = the position of r in act; the total goes to *d_total (device).
+int compact_marked(tpm_ctx *c, const uint32_t *mark, uint32_t epoch, int64_t n, uint32_t *act,
+                   uint32_t *slot, uint32_t *d_total);
 // Stable ascending sort of (key, value) pairs; result lands in key[0]/idx[0].
 int radix_sort_pairs(tpm_ctx *c, int64_t n);
 int fill_u32(tpm_ctx *c, uint32_t *p, uint32_t v, int64_t n);

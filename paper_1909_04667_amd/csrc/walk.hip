@@ -1143,24 +1143,6 @@ __global__ __launch_bounds__(kBlock) void k_mark(const int32_t *__restrict__ idx
     mark[rank[i]] = epoch;
 }
 
-__global__ __launch_bounds__(kBlock) void k_flags(const uint32_t *__restrict__ mark, int64_t n,
-                                                  uint32_t epoch, uint32_t *__restrict__ flag) {
-    int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r < n)
-        flag[r] = mark[r] == epoch ? 1u : 0u;
-}
-
-__global__ __launch_bounds__(kBlock) void k_compact(const uint32_t *__restrict__ flag,
-                                                    const uint32_t *__restrict__ pos, int64_t n,
-                                                    uint32_t *__restrict__ act,
-                                                    uint32_t *__restrict__ slot) {
-    int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r < n && flag[r]) {
-        act[pos[r]] = (uint32_t)r;
-        slot[r] = pos[r];
-    }
-}
-
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_output(
     const int32_t *__restrict__ idx, int64_t n_act, int64_t n, const int32_t *__restrict__ rank,
@@ -1300,16 +1282,9 @@ int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
                                                            c->epoch);
         TPM_LAUNCHED(c, "k_mark");
     }
-    uint32_t *flag = (uint32_t *)c->cnt.p;  // build scratch, free after the build
-    uint32_t *pos = (uint32_t *)c->base.p;
-    k_flags<<<grid_for(n, kBlock), kBlock, 0, st>>>(mark, n, c->epoch, flag);
-    TPM_LAUNCHED(c, "k_flags");
     uint32_t *nuniq = (uint32_t *)c->counters.p + 40;
-    TPM_TRY(scan_u32(c, flag, pos, n, nuniq));
-    k_compact<<<grid_for(n, kBlock), kBlock, 0, st>>>(flag, pos, n, (uint32_t *)c->act.p,
-                                                      (uint32_t *)c->slot.p);
-    TPM_LAUNCHED(c, "k_compact");
-    return TPM_OK;
+    return compact_marked(c, mark, c->epoch, n, (uint32_t *)c->act.p, (uint32_t *)c->slot.p,
+                          nuniq);
 }
 
 // Walk variant (both give identical results): independent lanes for sparse
