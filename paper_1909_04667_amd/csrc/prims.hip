@@ -368,25 +368,21 @@ __global__ __launch_bounds__(kScanBlock) void k_mark_compact(
     const uint32_t total = block_excl_scan(all, s_w, excl);
     if (b == 0 && threadIdx.x == 0)
         *d_total = total;
+    // kScanItems rounds of kScanBlock consecutive slots: lanes take
+    // consecutive slots, so the outputs of a full set are written contiguously
     const int64_t base = (int64_t)b * kScanTile;
-    uint32_t f[kScanItems], t = 0;
+    uint32_t pos = off;
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
-        const int64_t r = base + threadIdx.x * kScanItems + j;
-        f[j] = (r < n && mark[r] == epoch) ? 1u : 0u;
-        t += f[j];
-    }
-    uint32_t pos;
-    block_excl_scan(t, s_w, pos);
-    pos += off;
-#pragma unroll
-    for (int j = 0; j < kScanItems; j++) {
-        if (f[j]) {
-            const uint32_t r = (uint32_t)(base + threadIdx.x * kScanItems + j);
-            act[pos] = r;
-            slot[r] = pos;
-            ++pos;
+        const int64_t r = base + j * kScanBlock + threadIdx.x;
+        const uint32_t f = (r < n && mark[r] == epoch) ? 1u : 0u;
+        uint32_t ex;
+        const uint32_t tot = block_excl_scan(f, s_w, ex);
+        if (f) {
+            act[pos + ex] = (uint32_t)r;
+            slot[r] = pos + ex;
         }
+        pos += tot;
     }
 }
 
