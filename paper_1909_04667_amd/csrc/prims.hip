@@ -110,13 +110,15 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t *out, int64_t 
 // Stable LSD sort, eight 8-bit digits, one kernel per digit (a single sweep
 // in the manner of Merrill & Garland's decoupled look-back scan).  The eight
 // digit histograms of all keys are counted once up front.  A pass's blocks
-// take tiles of 4096 keys in the order they start (an atomic tile counter),
+// take tiles of 8192 keys in the order they start (an atomic tile counter),
 // rank their tile stably in LDS, publish the tile's digit counts, and find
 // the counts of all earlier tiles by looking back through the published
-// words; a tile then writes each digit's keys as one contiguous run.
-constexpr int kSortBlock = 512;
+// words; a tile then writes each digit's keys as one contiguous run.  With
+// every tile resident at once, the inclusive counts advance a few tiles per
+// look-back round trip, so large tiles (fewer of them) shorten the pass.
+constexpr int kSortBlock = 1024;
 constexpr int kSortRounds = 8;
-constexpr int kSortTile = kSortBlock * kSortRounds;  // 4096 keys per block
+constexpr int kSortTile = kSortBlock * kSortRounds;  // 8192 keys per block
 constexpr int kSortWaves = kSortBlock / 64;
 constexpr int kRadix = 256;  // digit values; threads 0 .. 255 own one each
 constexpr int kPasses = 8;
