@@ -122,6 +122,7 @@ constexpr int kSortTile = kSortBlock * kSortRounds;  // 8192 keys per block
 constexpr int kSortWaves = kSortBlock / 64;
 constexpr int kRadix = 256;  // digit values; threads 0 .. 255 own one each
 constexpr int kPasses = 8;
+constexpr int kLook = 4;  // look-back words per step (8 and 16 were slower)
 // Look-back word of (tile, digit): flag in bits 32-33, count in bits 0-31.
 constexpr uint64_t kAggregate = 1ull << 32;  // this tile's own count
 constexpr uint64_t kInclusive = 2ull << 32;  // count of this and all earlier tiles
@@ -242,17 +243,17 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_pass(
             // every earlier tile has started (tile numbers follow start order)
             // and publishes its own count before it looks back itself, so each
             // wait below ends
-            // (eight earlier tiles' words per step, loaded together; tile 0 is
+            // (kLook earlier tiles' words per step, loaded together; tile 0 is
             // inclusive, so the walk never reads before it)
             for (int64_t j = (int64_t)t - 1;;) {
-                uint64_t wd[8];
+                uint64_t wd[kLook];
 #pragma unroll
-                for (int q = 0; q < 8; q++)
+                for (int q = 0; q < kLook; q++)
                     wd[q] = j - q >= 0 ? load_word(look + (size_t)(j - q) * kRadix + tid) : 0ull;
                 bool done = false;
                 int used = 0;
 #pragma unroll
-                for (int q = 0; q < 8; q++) {
+                for (int q = 0; q < kLook; q++) {
                     if (done || used < q || !(wd[q] & (kAggregate | kInclusive)))
                         continue;
                     before += (uint32_t)wd[q];
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_pass(
                 if (done)
                     break;
                 j -= used;
-                if (used < 8)
+                if (used < kLook)
                     __builtin_amdgcn_s_sleep(1);  // tile j not published yet
             }
             store_word(mine, kInclusive | (before + cnt));
