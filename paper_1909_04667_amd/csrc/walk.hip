@@ -144,6 +144,20 @@ __device__ __forceinline__ double spline_phi64(double u) {
            1.0 / (15.0 * u);
 }
 
+// r = |d| and 1 / r from d^2: the hardware reciprocal square root refined by
+// two Newton steps (relative error about one ulp, far below the FP64 path's
+// tolerance), in place of a correctly rounded square root and division.  A
+// coincident pair (d^2 = 0) gets r = 0 and a 1 / r that no result uses (it
+// takes the softened branch).
+__device__ __forceinline__ void r_rinv64(double dd, double &r, double &rinv) {
+    double y = __builtin_amdgcn_rsq(dd);
+    const double hd = 0.5 * dd;
+    y = y * fma(-hd * y, y, 1.5);
+    y = y * fma(-hd * y, y, 1.5);
+    rinv = y;
+    r = dd > 0.0 ? dd * y : 0.0;
+}
+
 // hp: the pair's spline support with individual softening (MIXED), else
 // the common one of the parameters.
 template <bool TPM, bool POT, bool MIXED>
@@ -151,11 +165,11 @@ __device__ __forceinline__ void interact64(const WalkArgs &A, double m, double d
                                            double d2, double dd, double hp, double &a0,
                                            double &a1, double &a2, double &pot) {
     const double Gm = A.G * m;
-    const double r = sqrt(dd);
+    double r, rinv;
+    r_rinv64(dd, r, rinv);
     const double h = MIXED ? hp : A.h;
     double fac, phi = 0.0;
     if (r >= h) {
-        const double rinv = 1.0 / r;
         fac = Gm * rinv * rinv * rinv;
         if (POT)
             phi = -Gm * rinv;
@@ -223,8 +237,8 @@ template <bool TPM, bool POT, bool MIXED>
 __device__ __forceinline__ void factor64(const WalkArgs &A, uint64_t used, double m, double dd,
                                          double hp, double &fac, double &phi) {
     const double Gm = A.G * m;
-    const double r = sqrt(dd);
-    const double rinv = 1.0 / r;
+    double r, rinv;
+    r_rinv64(dd, r, rinv);
     const double h = MIXED ? hp : A.h;
     fac = Gm * rinv * rinv * rinv;
     phi = 0.0;
