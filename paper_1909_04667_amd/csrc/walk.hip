@@ -147,15 +147,16 @@ __device__ __forceinline__ double spline_phi64(double u) {
 // r = |d| and 1 / r from d^2: the hardware reciprocal square root refined by
 // two Newton steps (relative error about one ulp, far below the FP64 path's
 // tolerance), in place of a correctly rounded square root and division.  A
-// coincident pair (d^2 = 0) gets r = 0 and a 1 / r that no result uses (it
-// takes the softened branch).
+// coincident pair, or one closer than 2^-500 (d^2 below the normal range,
+// where the estimate is not reliable), gets r = 0 and a 1 / r that no result
+// uses: it takes the softened branch.
 __device__ __forceinline__ void r_rinv64(double dd, double &r, double &rinv) {
     double y = __builtin_amdgcn_rsq(dd);
     const double hd = 0.5 * dd;
     y = y * fma(-hd * y, y, 1.5);
     y = y * fma(-hd * y, y, 1.5);
     rinv = y;
-    r = dd > 0.0 ? dd * y : 0.0;
+    r = dd >= 0x1p-1000 ? dd * y : 0.0;
 }
 
 // hp: the pair's spline support with individual softening (MIXED), else
