@@ -774,7 +774,17 @@ static void visit(walk_state *W, int64_t e)
         open = (L * L) > (P->theta * P->theta) * d2;
 #endif
     } else {
+#if ORC_MUTATION == 14
+        open = (L * L) > (P->alpha * W->anorm) * (d2 * d2);
+#elif ORC_MUTATION == 15
+        open = (P->G * T->emass[e]) * L > (P->alpha * W->anorm) * (d2 * d2);
+#elif ORC_MUTATION == 16
+        open = (P->G * T->emass[e]) * (L * L) > P->alpha * (d2 * d2);
+#elif ORC_MUTATION == 17
+        open = (P->G * T->emass[e]) * (L * L) > (P->alpha * W->anorm) * d2;
+#else
         open = (P->G * T->emass[e]) * (L * L) > (P->alpha * W->anorm) * (d2 * d2);
+#endif
     }
     /* 1.2 L box around the geometric centre: always open */
     double lim = 0.6 * L;

@@ -13,6 +13,7 @@ from tests import test_oracle_keys as K
 from tests import test_oracle_isolated as ISO
 from tests import test_oracle_kernels as KN
 from tests import test_oracle_pm as PM
+from tests import test_oracle_relative as REL
 from tests import test_oracle_softening_mixed as MS
 from tests import test_oracle_tree as TR
 from tests import test_oracle_walk as WK
@@ -40,6 +41,17 @@ MUTATIONS = {
          [lambda o: MS.test_open_all_equals_direct_mixed(o, False)]),
     13: ("no opening of nodes with larger softening",
          [lambda o: MS.test_softening_node_rule(o)]),
+    14: ("relative criterion without the node's G m",
+         [lambda o: REL.test_relative_threshold_exact(o),
+          lambda o: REL.test_relative_unit_scaling_invariance(o, False),
+          lambda o: REL.test_relative_unit_scaling_invariance(o, True)]),
+    15: ("relative criterion with L in place of L^2",
+         [lambda o: REL.test_relative_threshold_exact(o)]),
+    16: ("relative criterion without |a_old|",
+         [lambda o: REL.test_relative_threshold_exact(o),
+          lambda o: REL.test_relative_unit_scaling_invariance(o, False)]),
+    17: ("relative criterion with d^2 in place of d^4",
+         [lambda o: REL.test_relative_threshold_exact(o)]),
 }
 
 
