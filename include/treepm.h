@@ -170,6 +170,16 @@ int tpm_compute_forces(tpm_ctx *ctx, int32_t opening, int64_t n_act, const int32
 int tpm_pm_long_range(tpm_ctx *ctx, int64_t n_act, const int32_t *active_idx, void *acc,
                       void *pot);
 
+/* Verification export of the mesh of the last PM solve (Sec. 3.3), solving
+ * it first if no solve has run since the build.  rho: host double[M^3], the
+ * CIC-deposited mass density of all particles of the build (periodic: mass
+ * per unit volume on the pm_grid^3 mesh; isolated: mass per cell of the
+ * zero-padded (2 pm_grid)^3 mesh); phi: host double[M^3], the potential on
+ * the same mesh (converted from float in TPM_FP32).  Layout (i M + j) M + k,
+ * i along x.  Either pointer may be NULL.  TPM_EINVAL without a mesh,
+ * TPM_ESTATE before a build.  Synchronises. */
+int tpm_export_mesh(tpm_ctx *ctx, double *rho, double *phi);
+
 /* |a| per particle for the relative criterion of the next pass (Sec. 3.1:
  * |a| of the previous force computation).  For k < n_act:
  *   out[active_idx[k]] = |acc_a[:,k] + acc_b[:,k]|  (computed in double)

@@ -64,6 +64,7 @@ def lib():
         L.tpm_tree_info.argtypes = [vp, P(i64), P(i64), P(d)]
         L.tpm_export_tree.argtypes = [vp] + [vp] * 10
         L.tpm_accel_norm.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.tpm_export_mesh.argtypes = [vp, vp, vp]
         L.tpm_timing_enable.argtypes = [vp, C.c_int]
         L.tpm_timing_read.argtypes = [vp, C.c_int, P(d), P(i64)]
         L.tpm_timing_durations.argtypes = [vp, C.c_int, P(d), i64, P(i64)]
@@ -254,6 +255,17 @@ class Context:
         out["cen"] = out["cen"].reshape(3, E)
         out["frame"] = np.array(fr)
         return out
+
+    def export_mesh(self):
+        """Deposited density (mass per cell when isolated) and potential of
+        the last PM solve, as host arrays of shape (M, M, M)."""
+        import numpy as np
+        M = self.params.pm_grid * (1 if self.params.periodic else 2)
+        rho = np.empty(M ** 3)
+        phi = np.empty(M ** 3)
+        self._rc(lib().tpm_export_mesh(self.h, C.c_void_p(rho.ctypes.data),
+                                       C.c_void_p(phi.ctypes.data)))
+        return rho.reshape(M, M, M), phi.reshape(M, M, M)
 
 
 class Batch:

@@ -318,6 +318,21 @@ int tpm_pm_long_range(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, 
     return timer_end(c, TPM_TIMER_PM_INTERP);
 }
 
+int tpm_export_mesh(tpm_ctx *c, double *rho, double *phi) {
+    if (!c)
+        return TPM_EINVAL;
+    if (c->P.pm_grid <= 0)
+        return fail(c, TPM_EINVAL, "no PM mesh configured");
+    if (!c->built)
+        return fail(c, TPM_ESTATE, "export_mesh before build_tree");
+    TPM_HIP(c, hipSetDevice(c->device));
+    if (!c->pm_ready) {
+        TPM_TRY(pm_solve(c));
+        c->pm_ready = 1;
+    }
+    return pm_export(c, rho, phi);
+}
+
 int tpm_accel_norm(tpm_ctx *c, int64_t n_act, const int32_t *idx, const void *a, const void *b,
                    double *out) {
     if (!c)

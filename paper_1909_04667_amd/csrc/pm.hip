@@ -4,8 +4,16 @@
 // interpolation.  Mean density removed (k = 0 set to zero, Sec. 2.2).
 //
 // Layout: mesh index (i * ng + j) * ng + k, i <-> x.  The deposit accumulates
-// 62-bit fixed-point masses with integer atomics, so the mesh is independent
-// of particle order (deterministic).  The 3-D FFT runs as five passes over
+// fixed-point masses with integer atomics, so the mesh is independent of
+// particle order (deterministic).  One 64-bit word per cell holds the mass at
+// 2^-62 of the total: a mean cell of a 256^3 mesh then keeps only about 38
+// bits, which for FP64 left errors of ~1e-11 of the mean density and up to
+// ~5e-10 in the forces of weakly accelerated particles.  The FP64 solve
+// therefore adds a second plane: each contribution's rounding residual,
+// in [-1/2, 1/2] units of the first word, rounded at 2^-20 of that unit (so
+// the residual sums of any cell stay below 2^52 in magnitude); the two
+// integer sums are exact and order-independent, and the cell's mass is
+// (hi + lo 2^-20) units, rounded once.  The 3-D FFT runs as five passes over
 // the half spectrum of the real mesh (kz = 0 .. ng/2): forward z (reading the
 // fixed-point mesh, two real lines per complex transform), forward y,
 // [forward x, Green's function, inverse x] fused in LDS, inverse y, inverse z
@@ -64,22 +72,36 @@ __device__ __forceinline__ void cic_cell(const double *__restrict__ ps, int64_t 
     }
 }
 
-// The deposit as 62-bit fixed-point integers (order-independent, hence
+// The deposit as fixed-point integers (order-independent, hence
 // deterministic).  A workgroup takes kDepChunk consecutive particles in curve
 // order, a compact region of the mesh: their contributions are summed in an
 // LDS tile over the region's bounding box (cell offsets from the chunk's
 // first particle, nearest image), and the tile is added to the mesh row by
 // row, so the device-scope atomics of a wavefront hit consecutive cells.  A
 // chunk whose box exceeds the tile adds its contributions directly.
+// TWO: the second plane of residuals (mesh + plane) described above.
 constexpr int kDepPer = 1;
 constexpr int kDepChunk = kBlock * kDepPer;
-constexpr int kDepTile = 3072;  // cells (24 KB)
+constexpr int kDepTile = 3072;  // cells (24 KB per plane)
 
+// Fixed-point parts of one contribution v (in units of the first word):
+// hi = v rounded to an integer; lo = (v - hi) 2^20 rounded, two's complement.
+// v - hi is exact (Sterbenz), as is its scaling by 2^20.
+template <bool TWO>
+__device__ __forceinline__ void fixed_parts(double v, unsigned long long &hi,
+                                            unsigned long long &lo) {
+    const double vr = rint(v);
+    hi = (unsigned long long)vr;
+    lo = TWO ? (unsigned long long)(long long)rint((v - vr) * 0x1p20) : 0ull;
+}
+
+template <bool TWO>
 __global__ __launch_bounds__(kBlock) void k_deposit(const double *__restrict__ ps,
                                                     const double *__restrict__ ms, int64_t n,
                                                     const Rec64 *__restrict__ rec, MeshGeom mg,
-                                                    unsigned long long *__restrict__ mesh) {
-    __shared__ unsigned long long tile[kDepTile];
+                                                    unsigned long long *__restrict__ mesh,
+                                                    size_t plane) {
+    __shared__ unsigned long long tile[TWO ? 2 * kDepTile : kDepTile];
     __shared__ int red[6][kBlock / 64];
     __shared__ int refc[3];
     const int ng = mg.ng, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -142,8 +164,11 @@ __global__ __launch_bounds__(kBlock) void k_deposit(const double *__restrict__ p
     const int D0 = hi[0] - lo[0] + 2, D1 = hi[1] - lo[1] + 2, D2 = hi[2] - lo[2] + 2;
     const int64_t V = (int64_t)D0 * D1 * D2;
     if (V <= kDepTile) {
-        for (int k = tid; k < (int)V; k += kBlock)
+        for (int k = tid; k < (int)V; k += kBlock) {
             tile[k] = 0ull;
+            if (TWO)
+                tile[kDepTile + k] = 0ull;
+        }
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < kDepPer; p++) {
@@ -159,20 +184,28 @@ __global__ __launch_bounds__(kBlock) void k_deposit(const double *__restrict__ p
                     wt *= up ? w[p][a] : 1.0 - w[p][a];
                     t[a] = o[p][a] - lo[a] + up;
                 }
-                atomicAdd(&tile[(t[0] * D1 + t[1]) * D2 + t[2]],
-                          __double2ull_rn(m[p] * wt * scale));
+                unsigned long long qh, ql;
+                fixed_parts<TWO>(m[p] * wt * scale, qh, ql);
+                const int cell = (t[0] * D1 + t[1]) * D2 + t[2];
+                atomicAdd(&tile[cell], qh);
+                if (TWO)
+                    atomicAdd(&tile[kDepTile + cell], ql);
             }
         }
         __syncthreads();
         for (int k = tid; k < (int)V; k += kBlock) {
             const unsigned long long v = tile[k];
-            if (v) {
+            const unsigned long long vl = TWO ? tile[kDepTile + k] : 0ull;
+            if (v || vl) {
                 const int l2 = k % D2, l1 = (k / D2) % D1, l0 = k / (D1 * D2);
                 int g[3] = {refc[0] + lo[0] + l0, refc[1] + lo[1] + l1, refc[2] + lo[2] + l2};
 #pragma unroll
                 for (int a = 0; a < 3; a++)
                     g[a] = ((g[a] % ng) + ng) % ng;
-                atomicAdd(&mesh[((size_t)g[0] * ng + g[1]) * ng + g[2]], v);
+                const size_t cell = ((size_t)g[0] * ng + g[1]) * ng + g[2];
+                atomicAdd(&mesh[cell], v);
+                if (TWO)
+                    atomicAdd(&mesh[plane + cell], vl);
             }
         }
     } else {
@@ -190,8 +223,12 @@ __global__ __launch_bounds__(kBlock) void k_deposit(const double *__restrict__ p
                     wt *= up ? w[p][a] : 1.0 - w[p][a];
                     t[a] = up ? (i0[p][a] + 1 == ng ? 0 : i0[p][a] + 1) : i0[p][a];
                 }
-                atomicAdd(&mesh[((size_t)t[0] * ng + t[1]) * ng + t[2]],
-                          __double2ull_rn(m[p] * wt * scale));
+                unsigned long long qh, ql;
+                fixed_parts<TWO>(m[p] * wt * scale, qh, ql);
+                const size_t cell = ((size_t)t[0] * ng + t[1]) * ng + t[2];
+                atomicAdd(&mesh[cell], qh);
+                if (TWO)
+                    atomicAdd(&mesh[plane + cell], ql);
             }
         }
     }
@@ -334,6 +371,14 @@ __device__ __forceinline__ void line_fft(Cx<T> *a, Cx<T> *out, Cx<T> *row, int n
     __syncthreads();
 }
 
+// Mass of cell g in units of the first word: hi, plus lo 2^-20 when the
+// residual plane exists (plane > 0); one rounding.
+__device__ __forceinline__ double fixed_value(const unsigned long long *__restrict__ mq,
+                                              size_t plane, size_t g) {
+    const double hi = (double)mq[g];
+    return plane ? fma((double)(long long)mq[plane + g], 0x1p-20, hi) : hi;
+}
+
 template <typename T, int R1, int R2>
 __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__restrict__ mesh,
                                                 const unsigned long long *__restrict__ mq,
@@ -342,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__rest
                                                 const double *__restrict__ gq, double gconst,
                                                 const double *__restrict__ gtab,
                                                 const Rec64 *__restrict__ rec, double vinv,
-                                                double norm) {
+                                                double norm, size_t plane) {
     constexpr int NG = R1 * R2, C = R1 / R2, PAD = R2 + 1, H = NG / 2 + 1;
     extern __shared__ unsigned char lds_raw[];
     Cx<T> *lds = (Cx<T> *)lds_raw;  // B rows of R1 x (R2 + 1)
@@ -393,8 +438,8 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass ps, int B, Cx<T> *__rest
             const int pos = R2 * n1 + n2;
             if (ps.in_fixed) {
                 const size_t g = base + (size_t)pos;
-                a[n1] = Cx<T>{(T)((double)mq[g] * qscale),
-                              ps.half ? (T)((double)mq[g + NG] * qscale) : (T)0};
+                a[n1] = Cx<T>{(T)(fixed_value(mq, plane, g) * qscale),
+                              ps.half ? (T)(fixed_value(mq, plane, g + NG) * qscale) : (T)0};
             } else if (ps.half && ps.axis == 2) {
                 // C[k] = A_k + i B_k; above ng/2 from A_(ng-k) = conj(A_k)
                 const int kk = pos <= NG / 2 ? pos : NG - pos;
@@ -591,6 +636,7 @@ struct FftArgs {
     const double *gk2 = nullptr, *gq = nullptr, *gtab = nullptr;
     double gconst = 0.0, vinv = 1.0, norm = 1.0;
     const Rec64 *rec = nullptr;
+    size_t plane = 0;  // offset of the residual plane of the deposit (0: none)
 };
 
 template <typename T, int R1, int R2>
@@ -612,7 +658,7 @@ int launch_fft(tpm_ctx *c, const FftPass &fp, Cx<T> *mc, const unsigned long lon
     const unsigned blocks = (unsigned)(lines / B);
     k_fft<T, R1, R2><<<blocks, kBlock, lds, c->stream>>>(fp, B, mc, mq, phi, tw, fa.gk2,
                                                          fa.gq, fa.gconst, fa.gtab, fa.rec,
-                                                         fa.vinv, fa.norm);
+                                                         fa.vinv, fa.norm, fa.plane);
     TPM_LAUNCHED(c, "k_fft");
     return TPM_OK;
 }
@@ -762,7 +808,10 @@ int solve_t(tpm_ctx *c) {
     hipStream_t st = c->stream;
     if (iso)
         TPM_TRY(build_green_isolated(c));
-    TPM_TRY(ensure(c, c->mesh_q, n3 * 8));
+    // FP64: a second plane of deposit residuals
+    constexpr bool kTwo = sizeof(T) == sizeof(double);
+    const size_t planes = kTwo ? 2 : 1;
+    TPM_TRY(ensure(c, c->mesh_q, planes * n3 * 8));
     // half spectrum of the real mesh: kz = 0 .. M/2
     TPM_TRY(ensure(c, c->mesh_c, (size_t)M * M * (M / 2 + 1) * sizeof(Cx<T>)));
     TPM_TRY(ensure(c, c->mesh_phi, n3 * sizeof(T)));
@@ -797,13 +846,14 @@ int solve_t(tpm_ctx *c) {
         c->axis_tables_M = M;
     }
     unsigned long long *mq = (unsigned long long *)c->mesh_q.p;
-    TPM_TRY(fill_u64(c, (uint64_t *)mq, 0ull, (int64_t)n3));
-    k_deposit<<<grid_for(c->n, kDepChunk), kBlock, 0, st>>>(
+    TPM_TRY(fill_u64(c, (uint64_t *)mq, 0ull, (int64_t)(planes * n3)));
+    k_deposit<kTwo><<<grid_for(c->n, kDepChunk), kBlock, 0, st>>>(
         (const double *)c->ps.p, (const double *)c->ms.p, c->n, (const Rec64 *)c->rec64.p, mg,
-        mq);
+        mq, kTwo ? n3 : 0);
     TPM_LAUNCHED(c, "k_deposit");
     FftArgs fa;
     fa.rec = (const Rec64 *)c->rec64.p;
+    fa.plane = kTwo ? n3 : 0;
     fa.norm = 1.0 / (double)n3;
     if (iso) {
         // masses on the mesh, Phi = IFFT(FFT(M) T) (G / h) / M^3
@@ -846,7 +896,43 @@ int interp_t(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, void *pot
     return TPM_OK;
 }
 
+template <typename T>
+int export_t(tpm_ctx *c, double *rho, double *phi) {
+    const MeshGeom mg = mesh_geom(c);
+    const size_t M = (size_t)mg.ng, n3 = M * M * M;
+    constexpr bool kTwo = sizeof(T) == sizeof(double);
+    TPM_HIP(c, hipStreamSynchronize(c->stream));
+    if (rho) {
+        Rec64 root;
+        TPM_HIP(c, hipMemcpy(&root, c->rec64.p, sizeof(Rec64), hipMemcpyDeviceToHost));
+        int ex;
+        std::frexp(root.mass, &ex);
+        const double vinv = c->P.periodic ? 1.0 / (mg.h * mg.h * mg.h) : 1.0;
+        const double qscale = std::ldexp(1.0, ex - 62) * vinv;
+        std::vector<unsigned long long> q((kTwo ? 2 : 1) * n3);
+        TPM_HIP(c, hipMemcpy(q.data(), c->mesh_q.p, q.size() * 8, hipMemcpyDeviceToHost));
+        for (size_t g = 0; g < n3; g++) {
+            const double hi = (double)q[g];
+            const double v = kTwo ? std::fma((double)(long long)q[n3 + g], 0x1p-20, hi) : hi;
+            rho[g] = v * qscale;
+        }
+    }
+    if (phi) {
+        std::vector<T> f(n3);
+        TPM_HIP(c, hipMemcpy(f.data(), c->mesh_phi.p, n3 * sizeof(T), hipMemcpyDeviceToHost));
+        for (size_t g = 0; g < n3; g++)
+            phi[g] = (double)f[g];
+    }
+    return TPM_OK;
+}
+
 }  // namespace
+
+int pm_export(tpm_ctx *c, double *rho, double *phi) {
+    if (c->P.precision == TPM_FP32)
+        return export_t<float>(c, rho, phi);
+    return export_t<double>(c, rho, phi);
+}
 
 int pm_solve(tpm_ctx *c) {
     if (c->P.precision == TPM_FP32)

@@ -391,13 +391,13 @@ __global__ __launch_bounds__(kScanBlock) void k_mark_compact(
 
 }  // namespace
 
+int64_t compaction_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
 int compact_marked(tpm_ctx *c, const uint32_t *mark, uint32_t epoch, int64_t n, uint32_t *act,
-                   uint32_t *slot, uint32_t *d_total) {
+                   uint32_t *slot, uint32_t *d_total, uint32_t *counts) {
     if (n <= 0)
         return fill_u32(c, d_total, 0u, 1);
-    const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    TPM_TRY(ensure(c, c->scan_tmp, (size_t)nb * sizeof(uint32_t)));
-    uint32_t *counts = (uint32_t *)c->scan_tmp.p;
+    const int64_t nb = compaction_tiles(n);
     k_mark_count<<<(unsigned)nb, kScanBlock, 0, c->stream>>>(mark, n, epoch, counts);
     TPM_LAUNCHED(c, "k_mark_count");
     k_mark_compact<<<(unsigned)nb, kScanBlock, 0, c->stream>>>(mark, n, epoch, counts, act, slot,

@@ -136,13 +136,32 @@ size_t bytes_held(const tpm_ctx *c);
 #define TPM_HIP(c, expr) TPM_TRY(::tpm::hip_check((c), (expr), #expr))
 #define TPM_LAUNCHED(c, name) TPM_TRY(::tpm::hip_check((c), hipGetLastError(), name))
 
+// Working memory of one active-set call: marks and slot maps of the active
+// set, per-tile compaction counts, the count of unique actives, and the walk
+// results in slot order.  Either the context's own buffers (allocated on
+// demand) or a fixed region the caller provides.
+struct Work {
+    uint32_t *mark = nullptr;   // [n] epoch marks
+    uint32_t epoch = 0;         // the mark of this call
+    bool clear = false;         // clear the marks [0, n) before marking
+    uint32_t *act = nullptr;    // [n] active slots in curve order
+    uint32_t *slot = nullptr;   // [n] rank -> position in act
+    uint32_t *counts = nullptr; // [ceil(n / scan tile)] compaction tile counts
+    uint32_t *nuniq = nullptr;  // [1] number of unique actives
+    void *res = nullptr;        // [3][n] results in slot order (dtype of the context)
+    void *rpot = nullptr;       // [n]
+    uint32_t *rnint = nullptr;  // [n]
+};
+
 // Primitives (prims.hip) ---------------------------------------------------
 // Exclusive scan of n uint32 values; total written to d_total if non-null.
 int scan_u32(tpm_ctx *c, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *d_total);
 // act[0 .. total) = the slots r < n with mark[r] == epoch, increasing;
-// slot[r] = the position of r in act; the total goes to *d_total (device).
+// slot[r] = the position of r in act; the total goes to *d_total (device);
+// counts: compaction_tiles(n) words of scratch.
 int compact_marked(tpm_ctx *c, const uint32_t *mark, uint32_t epoch, int64_t n, uint32_t *act,
-                   uint32_t *slot, uint32_t *d_total);
+                   uint32_t *slot, uint32_t *d_total, uint32_t *counts);
+int64_t compaction_tiles(int64_t n);
 // Stable ascending sort of (key, value) pairs; result lands in key[0]/idx[0].
 int radix_sort_pairs(tpm_ctx *c, int64_t n);
 int fill_u32(tpm_ctx *c, uint32_t *p, uint32_t v, int64_t n);
@@ -155,11 +174,23 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
 // Walk (walk.hip) ----------------------------------------------------------
 int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const double *anorm,
            void *acc, void *pot, uint32_t *nint);
+// forces() with the working memory given (allocates nothing, records no
+// timers when timed = false)
+int forces_into(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx,
+                const double *anorm, void *acc, void *pot, uint32_t *nint, const Work &w,
+                bool timed);
+// the context's own working memory, allocated as needed (results: res,
+// rpot, rnint too); advances the context's mark epoch
+int work_of_ctx(tpm_ctx *c, bool results, Work &w);
 int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx);
+int select_active_into(tpm_ctx *c, int64_t n_act, const int32_t *idx, const Work &w);
 
 // Particle mesh (pm.hip) -----------------------------------------------------
 int pm_solve(tpm_ctx *c);
 int pm_interp(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, void *pot);
+// Host copies of the deposited mesh (density, or mass per cell when isolated)
+// and of the potential mesh of the last solve (synchronises).
+int pm_export(tpm_ctx *c, double *rho, double *phi);
 
 // Bracket kernels of one timer class with events (no-op unless enabled).
 int timer_begin(tpm_ctx *c, int kind);

@@ -67,6 +67,11 @@ struct WalkArgs {
 // Wavefront masks: ballot of a lane predicate, and a mask read back as the
 // predicate of each lane.
 __device__ __forceinline__ uint64_t wave_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+// a - b modulo 2^32 (the periodic wrap of the shifted integer coordinates of
+// the FP32 records), without signed overflow
+__device__ __forceinline__ int32_t wsub(int32_t a, int32_t b) {
+    return (int32_t)((uint32_t)a - (uint32_t)b);
+}
 __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
 // ---- FP64 arithmetic (fixed operation order, explicit fma) -------------------
@@ -776,9 +781,9 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
         Gr0 = __builtin_amdgcn_readfirstlane(G0);
         Gr1 = __builtin_amdgcn_readfirstlane(G1);
         Gr2 = __builtin_amdgcn_readfirstlane(G2);
-        lo0 = hi0 = fmaf((float)(G0 - Gr0), A.fu, xr0);
-        lo1 = hi1 = fmaf((float)(G1 - Gr1), A.fu, xr1);
-        lo2 = hi2 = fmaf((float)(G2 - Gr2), A.fu, xr2);
+        lo0 = hi0 = fmaf((float)wsub(G0, Gr0), A.fu, xr0);
+        lo1 = hi1 = fmaf((float)wsub(G1, Gr1), A.fu, xr1);
+        lo2 = hi2 = fmaf((float)wsub(G2, Gr2), A.fu, xr2);
         for (int o = 1; o < 64; o <<= 1) {
             lo0 = fminf(lo0, __shfl_xor(lo0, o));
             hi0 = fmaxf(hi0, __shfl_xor(hi0, o));
@@ -802,9 +807,9 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     auto particle = [&](const Rec32 &r, uint32_t e, uint64_t m) {
         const float he = MIXED ? ((const float *)A.eh)[e] : 0.0f;
         const float hp = hi > he ? hi : he;
-        const float d0 = fmaf((float)((r.cx_meta & -(1 << SH)) - G0), A.fu, -xr0) + r.dx;
-        const float d1 = fmaf((float)(r.cy - G1), A.fu, -xr1) + r.dy;
-        const float d2 = fmaf((float)(r.cz - G2), A.fu, -xr2) + r.dz;
+        const float d0 = fmaf((float)wsub(r.cx_meta & -(1 << SH), G0), A.fu, -xr0) + r.dx;
+        const float d1 = fmaf((float)wsub(r.cy, G1), A.fu, -xr1) + r.dy;
+        const float d2 = fmaf((float)wsub(r.cz, G2), A.fu, -xr2) + r.dz;
         const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
         uint64_t inter = m & wave_mask(e != self);
         if (TPM)
@@ -832,9 +837,9 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
         const float hp = hi > he ? hi : he;
         // target -> centre of the cube (32-bit differences wrap modulo the
         // periodic box), and target -> centre of mass
-        const float c0 = fmaf((float)((cm & -(1 << SH)) - G0), A.fu, -xr0);
-        const float c1 = fmaf((float)(r.cy - G1), A.fu, -xr1);
-        const float c2 = fmaf((float)(r.cz - G2), A.fu, -xr2);
+        const float c0 = fmaf((float)wsub(cm & -(1 << SH), G0), A.fu, -xr0);
+        const float c1 = fmaf((float)wsub(r.cy, G1), A.fu, -xr1);
+        const float c2 = fmaf((float)wsub(r.cz, G2), A.fu, -xr2);
         const uint32_t lev = (uint32_t)cm & kRecLevel;
         uint64_t keep = ~0ull;
         if (TPM) {
@@ -878,9 +883,9 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
                 bool near = false;
                 if ((uint32_t)lane < k) {
                     const Rec32 t = R[base + lane];
-                    const float p0 = fmaf((float)((t.cx_meta & -(1 << SH)) - Gr0), A.fu, t.dx);
-                    const float p1 = fmaf((float)(t.cy - Gr1), A.fu, t.dy);
-                    const float p2 = fmaf((float)(t.cz - Gr2), A.fu, t.dz);
+                    const float p0 = fmaf((float)wsub(t.cx_meta & -(1 << SH), Gr0), A.fu, t.dx);
+                    const float p1 = fmaf((float)wsub(t.cy, Gr1), A.fu, t.dy);
+                    const float p2 = fmaf((float)wsub(t.cz, Gr2), A.fu, t.dz);
                     const float g0 = fmaxf(fmaxf(lo0 - p0, p0 - hi0), 0.0f);
                     const float g1 = fmaxf(fmaxf(lo1 - p1, p1 - hi1), 0.0f);
                     const float g2 = fmaxf(fmaxf(lo2 - p2, p2 - hi2), 0.0f);
@@ -1085,9 +1090,9 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
             const Rec32 r = R[e];
             const float he = MIXED ? ((const float *)A.eh)[e] : 0.0f;
             const int32_t cm = r.cx_meta;
-            const float c0 = fmaf((float)((cm & -(1 << SH)) - G0), A.fu, -xr0);
-            const float c1 = fmaf((float)(r.cy - G1), A.fu, -xr1);
-            const float c2 = fmaf((float)(r.cz - G2), A.fu, -xr2);
+            const float c0 = fmaf((float)wsub(cm & -(1 << SH), G0), A.fu, -xr0);
+            const float c1 = fmaf((float)wsub(r.cy, G1), A.fu, -xr1);
+            const float c2 = fmaf((float)wsub(r.cz, G2), A.fu, -xr2);
             const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
             const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
             const bool part = (cm & kRecParticle) != 0;
@@ -1280,26 +1285,54 @@ int accel_norm(tpm_ctx *c, int64_t n_act, const int32_t *idx, const void *a, con
     return TPM_OK;
 }
 
-int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
+int work_of_ctx(tpm_ctx *c, bool results, Work &w) {
     const int64_t n = c->n;
-    hipStream_t st = c->stream;
     TPM_TRY(ensure(c, c->mark, (size_t)n * 4));
     TPM_TRY(ensure(c, c->act, (size_t)n * 4));
     TPM_TRY(ensure(c, c->slot, (size_t)n * 4));
-    uint32_t *mark = (uint32_t *)c->mark.p;
+    TPM_TRY(ensure(c, c->scan_tmp, (size_t)compaction_tiles(n) * 4));
+    if (results) {
+        const size_t esz = c->P.precision == TPM_FP32 ? 4 : 8;
+        TPM_TRY(ensure(c, c->res, (size_t)3 * n * esz));
+        TPM_TRY(ensure(c, c->rpot, (size_t)n * esz));
+        TPM_TRY(ensure(c, c->rnint, (size_t)n * 4));
+    }
+    w = Work{};
+    w.mark = (uint32_t *)c->mark.p;
+    w.clear = false;
     if (++c->epoch == 0 || c->epoch == 1) {  // fresh or wrapped: clear the marks
-        TPM_TRY(fill_u32(c, mark, 0u, n));
+        w.clear = true;
         c->epoch = 1;
     }
+    w.epoch = c->epoch;
+    w.act = (uint32_t *)c->act.p;
+    w.slot = (uint32_t *)c->slot.p;
+    w.counts = (uint32_t *)c->scan_tmp.p;
+    w.nuniq = (uint32_t *)c->counters.p + 40;
+    w.res = c->res.p;
+    w.rpot = c->rpot.p;
+    w.rnint = (uint32_t *)c->rnint.p;
+    return TPM_OK;
+}
+
+int select_active_into(tpm_ctx *c, int64_t n_act, const int32_t *idx, const Work &w) {
+    const int64_t n = c->n;
+    hipStream_t st = c->stream;
+    if (w.clear)
+        TPM_TRY(fill_u32(c, w.mark, 0u, n));
     if (n_act > 0) {
         k_mark<<<grid_for(n_act, kBlock), kBlock, 0, st>>>(idx, n_act, n,
-                                                           (const int32_t *)c->rank.p, mark,
-                                                           c->epoch);
+                                                           (const int32_t *)c->rank.p, w.mark,
+                                                           w.epoch);
         TPM_LAUNCHED(c, "k_mark");
     }
-    uint32_t *nuniq = (uint32_t *)c->counters.p + 40;
-    return compact_marked(c, mark, c->epoch, n, (uint32_t *)c->act.p, (uint32_t *)c->slot.p,
-                          nuniq);
+    return compact_marked(c, w.mark, w.epoch, n, w.act, w.slot, w.nuniq, w.counts);
+}
+
+int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
+    Work w;
+    TPM_TRY(work_of_ctx(c, false, w));
+    return select_active_into(c, n_act, idx, w);
 }
 
 // Walk variant (both give identical results): independent lanes for sparse
@@ -1316,15 +1349,15 @@ static bool use_lanes(const tpm_ctx *c, int64_t n_act) {
     return fp64_iso_tpm || 4 * n_act < c->n;
 }
 
-static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
+static void fill_args(tpm_ctx *c, const double *anorm, const Work &w, WalkArgs &A) {
     const tpm_params &P = c->P;
     const int64_t n = c->n;
     const bool fp32 = P.precision == TPM_FP32;
     A.rec = fp32 ? c->rec32.p : c->rec64.p;
     A.E = (uint32_t)c->E;
     A.n = (uint32_t)n;
-    A.act = (const uint32_t *)c->act.p;
-    A.nuniq = (const uint32_t *)c->counters.p + 40;
+    A.act = w.act;
+    A.nuniq = w.nuniq;
     A.ps = (const double *)c->ps.p;
     A.qs = (const uint64_t *)c->qs.p;
     A.pe = (const uint32_t *)c->pe.p;
@@ -1372,9 +1405,9 @@ static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
     }
     A.finv2rs = (float)A.inv2rs;
     A.fgexp = (float)(-1.4426950408889634 * A.inv2rs * A.inv2rs);
-    A.res = c->res.p;
-    A.rpot = c->rpot.p;
-    A.rnint = (uint32_t *)c->rnint.p;
+    A.res = w.res;
+    A.rpot = w.rpot;
+    A.rnint = w.rnint;
     A.L2r = A.L * A.L;
     A.limr = 0.6 * A.L;
     A.hlr = 0.5 * A.L;
@@ -1387,21 +1420,26 @@ static void fill_args(tpm_ctx *c, const double *anorm, WalkArgs &A) {
 
 int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const double *anorm,
            void *acc, void *pot, uint32_t *nint) {
+    if (n_act == 0)
+        return TPM_OK;
+    Work w;
+    TPM_TRY(work_of_ctx(c, true, w));
+    return forces_into(c, opening, n_act, idx, anorm, acc, pot, nint, w, true);
+}
+
+int forces_into(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx,
+                const double *anorm, void *acc, void *pot, uint32_t *nint, const Work &w,
+                bool timed) {
     const tpm_params &P = c->P;
     const int64_t n = c->n;
     hipStream_t st = c->stream;
     const bool fp32 = P.precision == TPM_FP32;
-    const size_t esz = fp32 ? 4 : 8;
-    TPM_TRY(ensure(c, c->res, (size_t)3 * n * esz));
-    TPM_TRY(ensure(c, c->rpot, (size_t)n * esz));
-    TPM_TRY(ensure(c, c->rnint, (size_t)n * 4));
-    TPM_TRY(ensure(c, c->err_flag, 16));
     if (n_act == 0)
         return TPM_OK;
-    TPM_TRY(select_active(c, n_act, idx));
+    TPM_TRY(select_active_into(c, n_act, idx, w));
 
     WalkArgs A{};
-    fill_args(c, anorm, A);
+    fill_args(c, anorm, w, A);
     const bool tpm_on = P.pm_grid > 0;
     const int64_t groups = (std::min<int64_t>(n_act, n) + 63) / 64;
     Launch LA;
@@ -1420,7 +1458,8 @@ int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const
     LA.blocks = (unsigned)((waves + 3) / 4);
     const bool want_pot = pot != nullptr && P.want_potential;
     const int tkind = opening == TPM_OPEN_REL ? TPM_TIMER_WALK_REL : TPM_TIMER_WALK;
-    TPM_TRY(timer_begin(c, tkind));
+    if (timed)
+        TPM_TRY(timer_begin(c, tkind));
     // periodic boxes always carry the mesh (validated at creation)
     if (P.periodic)
         dispatch_mixed<true, true>(A, LA, opening, want_pot, c->mixed, st);
@@ -1429,18 +1468,19 @@ int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const
     else
         dispatch_mixed<false, false>(A, LA, opening, want_pot, c->mixed, st);
     TPM_LAUNCHED(c, "k_walk");
-    TPM_TRY(timer_end(c, tkind));
+    if (timed)
+        TPM_TRY(timer_end(c, tkind));
     const unsigned ob = grid_for(n_act, kBlock);
     if (fp32)
         k_output<float><<<ob, kBlock, 0, st>>>(
-            idx, n_act, n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
-            (const float *)c->res.p, (const float *)c->rpot.p, (const uint32_t *)c->rnint.p,
-            (float *)acc, want_pot ? (float *)pot : nullptr, nint, (uint32_t *)c->err_flag.p);
+            idx, n_act, n, (const int32_t *)c->rank.p, w.slot, (const float *)w.res,
+            (const float *)w.rpot, w.rnint, (float *)acc, want_pot ? (float *)pot : nullptr,
+            nint, (uint32_t *)c->err_flag.p);
     else
         k_output<double><<<ob, kBlock, 0, st>>>(
-            idx, n_act, n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
-            (const double *)c->res.p, (const double *)c->rpot.p, (const uint32_t *)c->rnint.p,
-            (double *)acc, want_pot ? (double *)pot : nullptr, nint, (uint32_t *)c->err_flag.p);
+            idx, n_act, n, (const int32_t *)c->rank.p, w.slot, (const double *)w.res,
+            (const double *)w.rpot, w.rnint, (double *)acc, want_pot ? (double *)pot : nullptr,
+            nint, (uint32_t *)c->err_flag.p);
     TPM_LAUNCHED(c, "k_output");
     return TPM_OK;
 }
@@ -1672,20 +1712,16 @@ int tpm_batch_launch(tpm_batch *b) {
         const int which = c->P.precision == TPM_FP32 ? 0 : 1;
         hipStream_t saved = c->stream;
         c->stream = b->stream;
-        const size_t esz = which == 0 ? 4 : 8;
-        int rc = ensure(c, c->res, (size_t)3 * c->n * esz);
-        if (rc == TPM_OK)
-            rc = ensure(c, c->rpot, (size_t)c->n * esz);
-        if (rc == TPM_OK)
-            rc = ensure(c, c->rnint, (size_t)c->n * 4);
+        Work w;
+        int rc = work_of_ctx(c, true, w);
         if (rc == TPM_OK && p.n_act > 0)
-            rc = select_active(c, p.n_act, p.idx);
+            rc = select_active_into(c, p.n_act, p.idx, w);
         c->stream = saved;
         if (rc != TPM_OK)
             return bfail(b, rc, c->err);
         BatchReq &R = b->host[o];
         R = BatchReq{};
-        fill_args(c, p.anorm, R.A);
+        fill_args(c, p.anorm, w, R.A);
         R.variant = (p.opening == TPM_OPEN_REL ? 1u : 0u) | (c->P.pm_grid > 0 ? 2u : 0u) |
                     (use_lanes(c, p.n_act) ? 4u : 0u) | (c->P.periodic ? 8u : 0u) |
                     (c->mixed ? 16u : 0u);
