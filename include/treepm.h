@@ -158,6 +158,25 @@ int tpm_compute_forces(tpm_ctx *ctx, int32_t opening, int64_t n_act, const int32
                        const double *a_old_norm, void *acc, void *pot,
                        uint32_t *n_interactions);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): tpm_compute_forces
+ * with the same arguments, kernels and results, whose per-call working
+ * memory (active-set marks and slot lists, compaction counts, results in
+ * curve order) lives in one fixed device array of the library instead of the
+ * context's buffers.  It calls no hipMalloc, hipFree or other allocating
+ * routine and records no timer events.  Limit: trees of at most
+ * tpm_noalloc_max_n() = 2^20 particles (TPM_EINVAL beyond, before anything
+ * is enqueued); the array takes 48 MiB on every GPU the library runs on,
+ * held until the process ends.  All calls on one GPU share that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads) race;
+ * each call clears what it needs.  The tree itself comes from
+ * tpm_build_tree, which does allocate.  TPM_EDEVICE if the array's address
+ * could not be looked up when the context was created. */
+int tpm_compute_forces_noalloc(tpm_ctx *ctx, int32_t opening, int64_t n_act,
+                               const int32_t *active_idx, const double *a_old_norm, void *acc,
+                               void *pot, uint32_t *n_interactions);
+int64_t tpm_noalloc_max_n(void);
+
 /* Long-range PM acceleration at the active particles (Sec. 3.3, 3.4).
  * Requires pm_grid > 0 (else TPM_EINVAL).  Periodic box: Green's function
  * -4 pi G exp(-k^2 r_s^2) / k^2, mean density removed.  Isolated system:

@@ -60,6 +60,8 @@ def lib():
         L.tpm_build_tree_eps.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.tpm_compute_forces.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp]
         L.tpm_pm_long_range.argtypes = [vp, i64, vp, vp, vp]
+        L.tpm_compute_forces_noalloc.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp]
+        L.tpm_noalloc_max_n.restype = i64
         L.tpm_check.argtypes = [vp]
         L.tpm_tree_info.argtypes = [vp, P(i64), P(i64), P(d)]
         L.tpm_export_tree.argtypes = [vp] + [vp] * 10
@@ -102,6 +104,10 @@ def make_params(*, periodic=False, precision="fp64", want_potential=False, pm_gr
     for a in range(3):
         p.shift[a] = float(shift[a])
     return p
+
+
+def noalloc_max_n() -> int:
+    return int(lib().tpm_noalloc_max_n())
 
 
 def bytes_needed(params: TpmParams, n: int) -> int:
@@ -185,6 +191,20 @@ class Context:
         self._rc(lib().tpm_compute_forces(self.h, OPEN[opening], na, _ptr(active_idx),
                                           _ptr(a_old_norm), _ptr(acc), _ptr(pot),
                                           _ptr(n_interactions)))
+        return acc, pot
+
+    def compute_forces_noalloc(self, active_idx, opening="bh", a_old_norm=None, acc=None,
+                               pot=None, n_interactions=None):
+        """compute_forces through the allocation-free entry point; the caller
+        passes every output (acc [3][n_act] of the context's dtype, pot and
+        n_interactions optional)."""
+        if active_idx.dtype != torch.int32:
+            raise ValueError("active_idx must be int32")
+        if a_old_norm is not None and a_old_norm.dtype != torch.float64:
+            raise ValueError("a_old_norm must be float64")
+        self._rc(lib().tpm_compute_forces_noalloc(self.h, OPEN[opening], active_idx.numel(),
+                                                  _ptr(active_idx), _ptr(a_old_norm),
+                                                  _ptr(acc), _ptr(pot), _ptr(n_interactions)))
         return acc, pot
 
     def pm_long_range(self, active_idx, acc=None, pot=None, want_pot=None):

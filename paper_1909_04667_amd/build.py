@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtreepm.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["prims.hip", "build.hip", "walk.hip", "pm.hip", "api.hip", "integrate.hip"]
+SOURCES = ["prims.hip", "build.hip", "walk.hip", "pm.hip", "api.hip", "integrate.hip",
+           "noalloc.hip"]
 
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

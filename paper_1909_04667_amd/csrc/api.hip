@@ -200,6 +200,7 @@ int tpm_create(const tpm_params *p, void *hip_stream, tpm_ctx **out) {
         delete c;
         return TPM_EDEVICE;
     }
+    noalloc_attach(c->device);
     if (hipHostMalloc((void **)&c->hpin, 256 * sizeof(uint32_t), hipHostMallocDefault) !=
         hipSuccess) {
         delete c;

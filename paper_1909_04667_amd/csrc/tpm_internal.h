@@ -192,6 +192,10 @@ int pm_interp(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, void *po
 // and of the potential mesh of the last solve (synchronises).
 int pm_export(tpm_ctx *c, double *rho, double *phi);
 
+// Allocation-free forces (noalloc.hip): look up this device's scratch array
+// (once per device, the device current).
+void noalloc_attach(int device);
+
 // Bracket kernels of one timer class with events (no-op unless enabled).
 int timer_begin(tpm_ctx *c, int kind);
 int timer_end(tpm_ctx *c, int kind);
