@@ -8,14 +8,18 @@ first, then the relative criterion with |a| of that first pass):
     build_tree -> pm_long_range (deposit, FFT solve, difference, interpolate)
     -> compute_forces(BH) -> |a_tree + a_pm| -> compute_forces(relative)
 
-Default workload: periodic box L = 100 of 128^3 particles (grid plus
-Zel'dovich displacements of a Gaussian field with P(k) ~ k^-2, rms 0.1
-cell), eps = L/6400, TreePM with a 256^3 mesh, r_s = 1.25 cells, r_cut =
-4.5 r_s, theta = 0.5, alpha = 0.0025; inputs are resident in HBM.  The value
-is force evaluations per second (N per step); FP32 is the headline, the FP64
-path is measured beside it.  The walk kernel is timed by the library's own
-events around its launches; the FP64 CPU oracle is timed on a bounded sample
-of the same step on the host cores.
+Default (headline) workload: the clustered periodic box, the largest
+single-GPU configuration: L = 100, 256^3 particles drawn from a lognormal
+density field (sigma_ln = 2, Gaussian field with P(k) ~ k^-2), eps = L/12800,
+TreePM with a 256^3 mesh, r_s = 1.25 cells, r_cut = 4.5 r_s, theta = 0.5,
+alpha = 0.0025; inputs are resident in HBM.  The value is force evaluations
+per second (N per step); FP32 is the headline, the FP64 path is measured
+beside it.  The other workloads (Plummer 4096, Hernquist 2^20, the 128^3
+Zel'dovich box, active time-bin subsets, isolated TreePM, individual
+softening, time integration, serving) are reported as entries of the same
+line.  Kernel classes are timed by the library's own events around their
+launches; the roofline denominators are also measured in the same run; the
+FP64 CPU oracle is timed on a bounded sample of the headline workload.
 
 Prints ONE JSON line.
 """
@@ -51,11 +55,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=3, choices=[2, 3, 4])
+    ap.add_argument("--config", type=int, default=4, choices=[2, 3, 4])
     ap.add_argument("--precision", default="both", choices=["both", "fp32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 21,
-                    help="targets of the oracle walks (all of the default workload)")
+    ap.add_argument("--cpu-scale", type=int, default=2,
+                    help="the oracle runs the headline generator with ng / cpu-scale cells per "
+                         "side (mesh likewise): a bounded sample of the workload")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the local-timestep and serving legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -132,7 +137,7 @@ def run_gpu(p, kw, prec, steps, warmup, eps=None):
     return out
 
 
-def run_local_timestep(steps, prec="fp32"):
+def run_local_timestep(steps, prec="fp32", wl=None):
     """Clustered 256^3 box: one build (+ PM solve) reused by every active set;
     per set the PM interpolation and the relative-criterion walk with |a| of
     a full geometric pass (the previous step's accelerations)."""
@@ -140,7 +145,7 @@ def run_local_timestep(steps, prec="fp32"):
     import torch
     from paper_1909_04667_amd import binding as B
     from paper_1909_04667_amd import workloads as W
-    c, p, kw = workload(4)
+    c, p, kw = wl if wl is not None else workload(4)
     sets, bins = W.time_bin_active_sets(p.meta["rho"])
     dev = torch.device("cuda:0")
     t = lambda a, dt=torch.float64: torch.as_tensor(a, dtype=dt, device=dev).contiguous()
@@ -331,53 +336,265 @@ def pct(v, q):
     return v[k]
 
 
-def cpu_baseline(p, kw, sample, cfg):
-    """The FP64 oracle on the host: tree build and PM solve of the whole
-    system, both walks on up to ``sample`` targets (scaled to N if fewer)."""
+def pass_bytes(n, E, ng, prec, periodic, masses=False):
+    """Algorithmic HBM bytes of one build and one mesh solve, per pass: what
+    each pass must read and write at least once (caches absorb the rest).
+    n particles, E depth-first entries (E - n nodes), ng mesh cells per side
+    (0: none), prec "fp32"/"fp64"."""
+    nodes = E - n
+    t = 4 if prec == "fp32" else 8
+    b = {}
+    # root cube (isolated: one read of the positions) and keys: positions in,
+    # key and index out
+    b["keys"] = (0 if periodic else 24 * n) + 24 * n + 12 * n
+    # digit histograms (one read of the keys) + 8 passes of (key, index) in and out
+    b["sort"] = 8 * n + 8 * 24 * n
+    # index in, positions (and masses) gathered, permutation, rank, curve-order
+    # positions, masses and packed integer coordinates out
+    b["gather"] = 4 * n + (32 if masses else 24) * n + 4 * n + 4 * n + 24 * n + 8 * n + 8 * n
+    # counts (keys in, depth and count out), scan of the counts (two reads, two
+    # writes), emission (keys, depths, bases, positions, masses, integer
+    # coordinates in; 64-byte records, first/count words, particle entries and
+    # level lists out)
+    b["topology"] = (13 * n + 16 * n + (8 + 1 + 4 + 24 + 8 + 8) * n + 72 * E + 4 * n
+                     + 4 * nodes)
+    # moments: every entry read once as a child, every node written with its
+    # count; FP32 records: every record, first word and coordinate read, 32 B out
+    b["moments"] = 64 * E + 4 * E + 68 * nodes
+    if prec == "fp32":
+        b["moments"] += (64 + 4 + 8 + 32) * E
+    if ng:
+        M = ng if periodic else 2 * ng
+        m3 = M ** 3
+        planes = 1 if prec == "fp32" else 2
+        half = M * M * (M // 2 + 1) * 2 * t
+        # clear and one write of every fixed-point cell, positions and masses in
+        b["deposit"] = 2 * planes * 8 * m3 + 32 * n
+        # five passes over the half spectrum; the first reads the fixed-point
+        # mesh, the last writes the real potential
+        b["fft"] = planes * 8 * m3 + half + 3 * 2 * half + half + m3 * t
+    return b
+
+
+def interp_bytes(n_act, ng, prec, periodic):
+    """Mesh interpolation of n_act targets: slot and position in, the
+    potential mesh once, results out and scattered to caller order."""
+    t = 4 if prec == "fp32" else 8
+    M = ng if periodic else 2 * ng
+    return n_act * (4 + 24 + 4 * t) + M ** 3 * t + n_act * (12 + 4 * t + 4 * t)
+
+
+def run_config1(steps, warmup):
+    """Plummer sphere, N = 4096, eps = 0.01, geometric criterion theta = 0.5,
+    all particles, one evaluation (build + walk) in FP64 and FP32; the tree's
+    error against the direct sum (and after a relative pass, the paper's
+    second force computation) from the GPU's FP64 forces."""
+    import numpy as np
+    import torch
+    import oracle as O
+    from paper_1909_04667_amd import binding as B
+    from paper_1909_04667_amd import workloads as W
+    p = W.plummer(4096, 1)
+    dev = torch.device("cuda:0")
+    t = lambda a, dt=torch.float64: torch.as_tensor(a, dtype=dt, device=dev).contiguous()
+    x, y, z = t(p.x), t(p.y), t(p.z)
+    idx = torch.arange(p.n, dtype=torch.int32, device=dev)
+    out = {"workload": "plummer_4096", "n_particles": p.n, "eps": 0.01, "theta": 0.5,
+           "step": "build + BH walk, all particles"}
+    accs = {}
+    for prec in ("fp64", "fp32"):
+        ctx = B.Context(precision=prec, eps=0.01, theta=0.5)
+        acc = torch.empty((3, p.n), dtype=ctx.dtype, device=dev)
+
+        def step():
+            ctx.build_tree(x, y, z)
+            ctx.compute_forces(idx, "bh", acc=acc)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record()
+        for s_ in range(steps):
+            step()
+            ev[s_ + 1].record()
+        torch.cuda.synchronize()
+        ctx.check()
+        per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+        ms = sum(per) / steps
+        out[prec] = {"ms_per_step": ms, "force_evals_per_s": p.n / (ms * 1e-3),
+                     "latency_ms": {"p50": pct(per, 50), "p99": pct(per, 99)}}
+        accs[prec] = acc.double().cpu().numpy()
+        if prec == "fp64":
+            an = ctx.accel_norm(idx, acc)
+            ar, _ = ctx.compute_forces(idx, "rel", a_old_norm=an)
+            accs["rel"] = ar.cpu().numpy()
+        ctx.close()
+    ad, _ = O.direct(p.x, p.y, p.z, None, O.make_params(eps=0.01))
+
+    def err(a, ref):
+        na = np.linalg.norm(ref, axis=0)
+        return np.linalg.norm(a - ref, axis=0) / np.maximum(na, 1e-3 * np.sqrt(np.mean(na ** 2)))
+    e64, erel, e32 = err(accs["fp64"], ad), err(accs["rel"], ad), err(accs["fp32"], accs["fp64"])
+    out["error_vs_direct"] = {
+        "bh_theta0.5_fp64": {"p50": float(np.percentile(e64, 50)),
+                             "p99": float(np.percentile(e64, 99))},
+        "after_relative_alpha0.0025_fp64": {"p50": float(np.percentile(erel, 50)),
+                                            "p99": float(np.percentile(erel, 99))}}
+    out["fp32_vs_fp64_err"] = {"p99": float(np.percentile(e32, 99)), "max": float(e32.max())}
+    return out
+
+
+def run_config2(steps, warmup, sample=1024):
+    """Hernquist sphere, N = 2^20: the step (build, BH, |a|, relative) in FP64
+    and FP32; FP32 against FP64 over all targets; the relative pass against
+    the direct sum on sampled targets."""
     import numpy as np
     import oracle as O
-    periodic = bool(kw.get("periodic"))
-    rng = np.random.default_rng(0)
-    samp = np.sort(rng.choice(p.n, min(sample, p.n), replace=False))
+    c, p, kw = workload(2)
+    out = {"workload": c["name"], "n_particles": p.n, "eps": kw["eps"], "theta": kw["theta"],
+           "alpha": kw["alpha"], "step": "build + BH walk + |a| + relative walk, all particles"}
+    res = {}
+    for prec in ("fp32", "fp64"):
+        r = run_gpu(p, kw, prec, steps, warmup)
+        res[prec] = r
+        out[prec] = {"ms_per_step": r["ms_per_step"],
+                     "force_evals_per_s": r["n"] / (r["ms_per_step"] * 1e-3),
+                     "latency_ms": {"p50": pct(r["per_step"], 50),
+                                    "p99": pct(r["per_step"], 99)},
+                     "kernel_ms": kernel_ms(r),
+                     "interactions_per_particle_rel": r["inter_rel"] / r["n"],
+                     "interactions_per_s_rel":
+                         r["inter_rel"] / (r["timers"]["walk_rel"][0] / r["timers"]["walk_rel"][1]
+                                           * 1e-3)}
+    a32, a64 = res["fp32"]["acc"].numpy(), res["fp64"]["acc"].numpy()
+    na = np.linalg.norm(a64, axis=0)
+    e = np.linalg.norm(a32 - a64, axis=0) / np.maximum(na, 1e-3 * np.sqrt(np.mean(na ** 2)))
+    out["fp32_vs_fp64_err"] = {"p50": float(np.percentile(e, 50)),
+                               "p99": float(np.percentile(e, 99)), "max": float(e.max())}
+    out["fp32_speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["fp32"]["ms_per_step"]
+    samp = np.sort(np.random.default_rng(0).choice(p.n, sample, replace=False))
+    ad, _ = O.direct(p.x, p.y, p.z, None, O.make_params(eps=kw["eps"]), targets=samp)
+    nd = np.linalg.norm(ad, axis=0)
+    er = np.linalg.norm(a64[:, samp] - ad, axis=0) / np.maximum(
+        nd, 1e-3 * np.sqrt(np.mean(nd ** 2)))
+    out["error_vs_direct_fp64"] = {"targets": int(sample), "p50": float(np.percentile(er, 50)),
+                                   "p99": float(np.percentile(er, 99))}
+    return out
+
+
+def kernel_ms(r):
+    """Mean milliseconds per step of every timed kernel class."""
+    steps = len(r["per_step"])
+    return {k: v[0] / steps for k, v in r["timers"].items() if v[1]}
+
+
+def cpu_baseline(c, kw, scale):
+    """The FP64 oracle on the host, on a bounded sample of the headline
+    workload: the same generator and settings with ng / scale particles per
+    side and a mesh of pm_grid / scale cells (r_s and r_cut in mesh cells
+    unchanged), the whole step on every particle: single-threaded tree build
+    and mesh solve, both walks on all threads.  The GPU's FP64 step on the
+    same sample is compared with the oracle's (each side's relative pass uses
+    its own |a| from its own first pass)."""
+    import numpy as np
+    import oracle as O
+    from paper_1909_04667_amd import workloads as W
+    ngp = c["ng"] // scale
+    ngm = kw["pm_grid"] // scale
+    p = (W.lognormal_box if c["kind"] == "lognormal" else W.zeldovich_box)(ngp, c["box"],
+                                                                           c["seed"])
+    box = kw["box_size"]
+    eps = box / (50 * ngp)
+    rs = kw["asmth"] * box / ngm
     t0 = time.perf_counter()
-    T = O.Tree(p.x, p.y, p.z, periodic=periodic, box=kw.get("box_size", 0.0))
+    T = O.Tree(p.x, p.y, p.z, periodic=True, box=box)
     t_build = time.perf_counter() - t0
-    rs = kw.get("asmth", 1.25) * kw.get("box_size", 0.0) / kw["pm_grid"] if periodic else 0.0
-    t_pm = 0.0
-    apm = 0.0
-    if periodic:
-        t0 = time.perf_counter()
-        apm, _ = O.pm(p.x, p.y, p.z, None, kw["box_size"], kw["pm_grid"], 1.0, rs,
-                      targets=samp, want_pot=False)
-        t_pm = time.perf_counter() - t0
-    Pb = O.make_params(periodic=periodic, box=kw.get("box_size", 0.0), eps=kw["eps"],
-                       theta=kw["theta"], treepm=periodic, rs=rs,
-                       rcut=kw.get("rcut", 4.5) * rs if periodic else 0.0)
     t0 = time.perf_counter()
-    a, _, _ = T.walk(Pb, targets=samp)
+    apm, _ = O.pm(p.x, p.y, p.z, None, box, ngm, 1.0, rs, want_pot=False)
+    t_pm = time.perf_counter() - t0
+    Pb = O.make_params(periodic=True, box=box, eps=eps, theta=kw["theta"], treepm=True, rs=rs,
+                       rcut=kw["rcut"] * rs)
+    t0 = time.perf_counter()
+    a, _, _ = T.walk(Pb)
     t_bh = time.perf_counter() - t0
-    an = np.zeros(p.n)
-    an[samp] = np.linalg.norm(a + apm, axis=0)
-    Pr = O.make_params(periodic=periodic, box=kw.get("box_size", 0.0), eps=kw["eps"],
-                       opening="rel", alpha=kw["alpha"], treepm=periodic, rs=rs,
-                       rcut=kw.get("rcut", 4.5) * rs if periodic else 0.0)
+    an = np.linalg.norm(a + apm, axis=0)
+    Pr = O.make_params(periodic=True, box=box, eps=eps, opening="rel", alpha=kw["alpha"],
+                       treepm=True, rs=rs, rcut=kw["rcut"] * rs)
     t0 = time.perf_counter()
-    ar, _, _ = T.walk(Pr, targets=samp, anorm=an)
+    ar, _, _ = T.walk(Pr, anorm=an)
     t_rel = time.perf_counter() - t0
-    step = t_build + t_pm + (t_bh + t_rel) * p.n / samp.size
+    step = t_build + t_pm + t_bh + t_rel
+    # the GPU's FP64 step on the same sample
+    kws = dict(kw, eps=eps, pm_grid=ngm)
+    g = run_gpu(p, kws, "fp64", 1, 1)
+    ref = ar + apm
+    nr = np.linalg.norm(ref, axis=0)
+    e = np.linalg.norm(g["acc"].numpy() - ref, axis=0) / np.maximum(
+        nr, 1e-3 * np.sqrt(np.mean(nr ** 2)))
     return {"value": p.n / step, "unit": "force evals/s", "cores": O.max_threads(),
             "kind": "oracle",
-            "sample": (f"config {cfg}: single-threaded tree build of all {p.n} particles "
-                       f"({t_build:.1f} s)"
-                       + (f", PM solve of the full {kw['pm_grid']}^3 mesh ({t_pm:.1f} s)"
-                          if periodic else "")
-                       + (f", BH + relative walks of all {p.n} targets" if samp.size == p.n
-                          else f", BH + relative walks of {samp.size} sampled targets")
-                       + f" on {O.max_threads()} threads ({t_bh + t_rel:.1f} s)"
-                       + ("" if samp.size == p.n else " scaled to N")),
-            "seconds": {"build": t_build, "pm": t_pm, "walk_bh_sample": t_bh,
-                        "walk_rel_sample": t_rel, "step_estimate": step},
-            "acc_sample": (ar + apm), "samp": samp}
+            "sample": (f"{c['name']} generator at {ngp}^3 particles with a {ngm}^3 mesh "
+                       f"(1/{scale ** 3} of the particles; eps = L/(50 x {ngp}), r_s and r_cut "
+                       f"in mesh cells as in the workload): the whole step on all {p.n} "
+                       f"particles, tree build ({t_build:.1f} s) and mesh solve ({t_pm:.1f} s) "
+                       f"single-threaded, BH + relative walks ({t_bh + t_rel:.1f} s) on "
+                       f"{O.max_threads()} threads"),
+            "seconds": {"build": t_build, "pm": t_pm, "walk_bh": t_bh, "walk_rel": t_rel,
+                        "step": step},
+            "gpu_fp64_vs_oracle_err": {"p50": float(np.percentile(e, 50)),
+                                       "p99": float(np.percentile(e, 99)),
+                                       "max": float(e.max()),
+                                       "note": "each side's relative pass uses its own |a|"}}
+
+
+def summary(r, periodic, masses=False):
+    ms_rel, k_rel = r["timers"]["walk_rel"]
+    ms_bh, k_bh = r["timers"]["walk"]
+    steps = len(r["per_step"])
+    km = kernel_ms(r)
+    # the build's time outside its kernels: the one host synchronisation that
+    # sizes the node arrays
+    inner = sum(km.get(k, 0.0) for k in ("keys", "sort", "gather", "topology", "moments"))
+    ng = r.get("pm_grid", 0)
+    pb = pass_bytes(r["n"], r["entries"], ng, r["prec"], periodic, masses)
+    if ng:
+        pb["interp"] = interp_bytes(r["n"], ng, r["prec"], periodic)
+    gbs = {}
+    for k, nbytes in pb.items():
+        tk = {"interp": "pm_interp"}.get(k, k)
+        if km.get(tk):
+            gbs[k] = {"ms": km[tk], "algorithmic_bytes": nbytes,
+                      "GB_per_s": nbytes / (km[tk] * 1e-3) / 1e9,
+                      "frac_of_8TBps": nbytes / (km[tk] * 1e-3) / 8e12}
+    return {
+        "value": r["n"] / (r["ms_per_step"] * 1e-3),
+        "ms_per_step": r["ms_per_step"],
+        "latency_ms": {"p50": pct(r["per_step"], 50), "p99": pct(r["per_step"], 99)},
+        "kernel_ms": km,
+        "build_gap_ms": km.get("build", 0.0) - inner,
+        "kernel_ms_p50_p99": {
+            name: [pct(r["durations"][k], 50), pct(r["durations"][k], 99)]
+            for name, k in (("walk_rel", "walk_rel"), ("walk_bh", "walk"),
+                            ("build", "build"), ("sort", "sort"),
+                            ("pm_solve", "pm_solve"), ("pm_interp", "pm_interp"))
+            if r["durations"][k]},
+        "pass_GB_per_s": gbs,
+        "walk_rel_ms_per_launch": ms_rel / max(k_rel, 1),
+        "walk_bh_ms_per_launch": ms_bh / max(k_bh, 1),
+        "interactions_per_step": {"bh": r["inter_bh"], "rel": r["inter_rel"]},
+        "interactions_per_particle_rel": r["inter_rel"] / r["n"],
+        "tree_entries": r["entries"],
+    }
+
+
+def measured_peaks():
+    from paper_1909_04667_amd import binding as B
+    return {"fp32_fma_unpacked_tflops": B.probe_fma("fp32"),
+            "fp64_fma_tflops": B.probe_fma("fp64"),
+            "copy_GB_per_s": B.probe_copy(1 << 30),
+            "note": "dependent vector FMAs (FMA = 2 flops; FP32 without packed instructions, "
+                    "as the library is built) and a 1 GiB streaming copy (read + write), "
+                    "best of five launches"}
 
 
 def main():
@@ -387,49 +604,26 @@ def main():
                           "on a single device and has no multi-GPU code", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
+    peaks = measured_peaks()
+    log(f"measured peaks {peaks}")
     c, p, kw = workload(args.config)
     log(f"workload {c['name']} N={p.n} ready")
     precs = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
+    periodic = bool(kw.get("periodic"))
     res = {}
     for pr in precs:
         res[pr] = run_gpu(p, kw, pr, args.steps, args.warmup)
+        res[pr]["pm_grid"] = kw.get("pm_grid", 0)
         log(f"{pr}: {res[pr]['ms_per_step']:.3f} ms/step")
-    head = res[precs[0]]
-    periodic = bool(kw.get("periodic"))
-    fl = FLOPS_TREEPM if periodic else FLOPS_NEWTON
-
-    def summary(r):
-        ms_rel, k_rel = r["timers"]["walk_rel"]
-        ms_bh, k_bh = r["timers"]["walk"]
-        walk_ms = ms_rel / max(k_rel, 1)
-        return {
-            "value": r["n"] / (r["ms_per_step"] * 1e-3),
-            "ms_per_step": r["ms_per_step"],
-            "latency_ms": {"p50": pct(r["per_step"], 50), "p99": pct(r["per_step"], 99)},
-            "kernel_ms": {
-                "walk_rel": walk_ms, "walk_bh": ms_bh / max(k_bh, 1),
-                "build": r["timers"]["build"][0] / max(r["timers"]["build"][1], 1),
-                "sort": r["timers"]["sort"][0] / max(r["timers"]["sort"][1], 1),
-                "pm_solve": r["timers"]["pm_solve"][0] / max(r["timers"]["pm_solve"][1], 1),
-                "pm_interp": r["timers"]["pm_interp"][0] / max(r["timers"]["pm_interp"][1], 1)},
-            "kernel_ms_p50_p99": {
-                name: [pct(r["durations"][k], 50), pct(r["durations"][k], 99)]
-                for name, k in (("walk_rel", "walk_rel"), ("walk_bh", "walk"),
-                                ("build", "build"), ("sort", "sort"),
-                                ("pm_solve", "pm_solve"), ("pm_interp", "pm_interp"))
-                if r["durations"][k]},
-            "interactions_per_step": {"bh": r["inter_bh"], "rel": r["inter_rel"]},
-            "interactions_per_particle_rel": r["inter_rel"] / r["n"],
-            "tree_entries": r["entries"],
-        }
-
-    out_prec = {pr: summary(r) for pr, r in res.items()}
+    fl = FLOPS_TREEPM if kw.get("pm_grid", 0) else FLOPS_NEWTON
+    out_prec = {pr: summary(r, periodic) for pr, r in res.items()}
     h = out_prec[precs[0]]
-    walk_ms = h["kernel_ms"]["walk_rel"]
+    walk_ms = h["walk_rel_ms_per_launch"]
     achieved = res[precs[0]]["inter_rel"] * fl / (walk_ms * 1e-3) / 1e12
     per, tpm = ("true", "true") if periodic else ("false", "false")
     walk_kernel = (f"k_walk32<{per}, {tpm}, 1, false, false>" if precs[0] == "fp32"
                    else f"k_walk64{'i' if periodic else ''}<{per}, {tpm}, 1, false, false>")
+    meas = peaks["fp32_fma_unpacked_tflops" if precs[0] == "fp32" else "fp64_fma_tflops"]
     line = {
         "metric": METRIC,
         "value": h["value"],
@@ -455,7 +649,9 @@ def main():
                      "traffic": counted_traffic(c["name"], walk_kernel),
                      "kernel": walk_kernel, "flops_per_interaction": fl,
                      "interactions_per_launch": res[precs[0]]["inter_rel"],
-                     "launch_ms": walk_ms},
+                     "launch_ms": walk_ms,
+                     "measured_peak": meas, "frac_of_measured_peak": achieved / meas},
+        "measured_peaks": peaks,
     }
     if len(precs) == 2:
         a32, a64 = res["fp32"]["acc"].numpy(), res["fp64"]["acc"].numpy()
@@ -465,9 +661,35 @@ def main():
                                     "p99": float(np.percentile(e, 99)),
                                     "max": float(e.max())}
         line["fp32_speedup_vs_fp64"] = out_prec["fp64"]["ms_per_step"] / h["ms_per_step"]
+    del res
     if not args.no_extra:
+        line["configs"] = {}
+        log("config 1: Plummer 4096")
+        line["configs"]["1"] = run_config1(max(10, args.steps), args.warmup)
+        log("config 2: Hernquist 2^20")
+        line["configs"]["2"] = run_config2(max(3, args.steps // 2), 2)
+        if args.config != 3:
+            log("config 3: Zel'dovich 128^3, 256^3 mesh")
+            c3, p3, kw3 = workload(3)
+            r3 = {}
+            for pr in ("fp32", "fp64"):
+                r3[pr] = run_gpu(p3, kw3, pr, max(3, args.steps // 2), 2)
+                r3[pr]["pm_grid"] = kw3["pm_grid"]
+            e3 = {pr: summary(r, True) for pr, r in r3.items()}
+            a32, a64 = r3["fp32"]["acc"].numpy(), r3["fp64"]["acc"].numpy()
+            na = np.linalg.norm(a64, axis=0)
+            e = np.linalg.norm(a32 - a64, axis=0) / np.maximum(na, 1e-3 * np.sqrt(np.mean(na ** 2)))
+            line["configs"]["3"] = {
+                "workload": c3["name"], "n_particles": p3.n,
+                "step": "build + PM + BH walk + |a| + relative walk, all particles",
+                "fp32": e3["fp32"], "fp64": e3["fp64"],
+                "fp32_vs_fp64_err": {"p50": float(np.percentile(e, 50)),
+                                     "p99": float(np.percentile(e, 99)), "max": float(e.max())},
+                "fp32_speedup_vs_fp64": e3["fp64"]["ms_per_step"] / e3["fp32"]["ms_per_step"]}
+            del r3, p3
         log("local time-stepping workload (256^3 clustered box)")
-        line["local_timestep"] = run_local_timestep(max(3, args.steps // 2))
+        line["local_timestep"] = run_local_timestep(
+            max(3, args.steps // 2), wl=(c, p, kw) if args.config == 4 else None)
         log("isolated TreePM (Hernquist 2^20, zero-padded mesh)")
         line["isolated_treepm"] = run_isolated(max(3, args.steps // 2), 2)
         log("individual softening (Hernquist 2^20)")
@@ -476,20 +698,9 @@ def main():
         line["integration"] = run_integrators()
         log("serving stream")
         line["serving"] = run_serving()
-    if not args.no_cpu:
-        log("timing the CPU oracle on a sample")
-        cb = cpu_baseline(p, kw, args.cpu_sample, args.config)
-        a_or = cb.pop("acc_sample")
-        samp = cb.pop("samp")
-        a64 = res["fp64"]["acc"].numpy()[:, samp] if "fp64" in res else None
-        if a64 is not None:
-            na = np.linalg.norm(a_or, axis=0)
-            e = np.linalg.norm(a64 - a_or, axis=0) / np.maximum(
-                na, 1e-3 * np.sqrt(np.mean(na ** 2)))
-            # each side's relative pass uses its own |a| from its own first pass
-            cb["gpu_fp64_vs_oracle_err"] = {"p99": float(np.percentile(e, 99)),
-                                            "max": float(e.max())}
-        line["cpu_baseline"] = cb
+    if not args.no_cpu and periodic:
+        log("timing the CPU oracle on a sample of the headline workload")
+        line["cpu_baseline"] = cpu_baseline(c, kw, args.cpu_scale)
     print(json.dumps(line))
     if args.copy_probe:
         import torch

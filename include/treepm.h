@@ -220,6 +220,14 @@ int tpm_accel_norm(tpm_ctx *ctx, int64_t n_act, const int32_t *active_idx, const
 #define TPM_TIMER_PM_INTERP 3  /* difference + interpolation kernel */
 #define TPM_TIMER_SORT 4       /* radix sort within the build */
 #define TPM_TIMER_WALK_REL 5   /* tree-walk kernel, relative criterion */
+#define TPM_TIMER_KEYS 6       /* root cube and Peano-Hilbert keys (within the build) */
+#define TPM_TIMER_GATHER 7     /* gather into curve order (within the build) */
+#define TPM_TIMER_TOPOLOGY 8   /* depth-first entries: counts and scans, then emission
+                                  (two records per build) */
+#define TPM_TIMER_MOMENTS 9    /* monopole moments and FP32 records (within the build) */
+#define TPM_TIMER_DEPOSIT 10   /* mesh clear and CIC deposit (within the solve) */
+#define TPM_TIMER_FFT 11       /* the five FFT passes with the Green's function */
+#define TPM_TIMER_KINDS 12
 int tpm_timing_enable(tpm_ctx *ctx, int on);
 int tpm_timing_read(tpm_ctx *ctx, int kind, double *ms, int64_t *launches);
 
@@ -227,6 +235,18 @@ int tpm_timing_read(tpm_ctx *ctx, int kind, double *ms, int64_t *launches);
  * order: ms receives min(cap, *launches) values (host array), *launches the
  * number of launches recorded; the records are reset either way. */
 int tpm_timing_durations(tpm_ctx *ctx, int kind, double *ms, int64_t cap, int64_t *launches);
+
+/* Measured roofline denominators (measurement only, not part of the method):
+ * tpm_probe_fma times dependent vector FMAs (eight chains per lane, sixteen
+ * wavefronts per SIMD) in TPM_FP32 (unpacked, as the library is built) or
+ * TPM_FP64 and returns the best of five launches in TFLOP/s (FMA = 2 flops);
+ * sink: device memory of at least 8 bytes (never written in practice).
+ * tpm_probe_copy copies bytes (a multiple of 16) from src to dst (device
+ * buffers) and returns read + write bytes per second of the best of five
+ * launches, in GB/s.  Both run on hip_stream on the current device and
+ * synchronise it. */
+int tpm_probe_fma(int32_t precision, void *sink, void *hip_stream, double *tflops);
+int tpm_probe_copy(const void *src, void *dst, int64_t bytes, void *hip_stream, double *gbps);
 
 /* Synchronise the stream and report sticky device-side errors
  * (TPM_EINDEX for an out-of-range active index); clears them. */

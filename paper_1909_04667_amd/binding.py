@@ -67,6 +67,8 @@ def lib():
         L.tpm_export_tree.argtypes = [vp] + [vp] * 10
         L.tpm_accel_norm.argtypes = [vp, i64, vp, vp, vp, vp]
         L.tpm_export_mesh.argtypes = [vp, vp, vp]
+        L.tpm_probe_fma.argtypes = [i32, vp, vp, P(d)]
+        L.tpm_probe_copy.argtypes = [vp, vp, i64, vp, P(d)]
         L.tpm_timing_enable.argtypes = [vp, C.c_int]
         L.tpm_timing_read.argtypes = [vp, C.c_int, P(d), P(i64)]
         L.tpm_timing_durations.argtypes = [vp, C.c_int, P(d), i64, P(i64)]
@@ -104,6 +106,30 @@ def make_params(*, periodic=False, precision="fp64", want_potential=False, pm_gr
     for a in range(3):
         p.shift[a] = float(shift[a])
     return p
+
+
+def probe_fma(precision: str, stream=None) -> float:
+    """Measured dependent-FMA rate of the device in TFLOP/s."""
+    sink = torch.zeros(2, dtype=torch.float64, device="cuda")
+    out = C.c_double()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib().tpm_probe_fma(PRECISION[precision], _ptr(sink), _stream_handle(st), C.byref(out))
+    if rc != TPM_OK:
+        raise TreePMError(rc, "tpm_probe_fma failed")
+    return float(out.value)
+
+
+def probe_copy(nbytes: int = 1 << 30, stream=None) -> float:
+    """Measured streaming-copy bandwidth (read + write) in GB/s."""
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = C.c_double()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib().tpm_probe_copy(_ptr(src), _ptr(dst), 4 * n, _stream_handle(st), C.byref(out))
+    if rc != TPM_OK:
+        raise TreePMError(rc, "tpm_probe_copy failed")
+    return float(out.value)
 
 
 def noalloc_max_n() -> int:
@@ -227,7 +253,8 @@ class Context:
         return out
 
     # -- measurement -----------------------------------------------------------
-    TIMERS = {"walk": 0, "build": 1, "pm_solve": 2, "pm_interp": 3, "sort": 4, "walk_rel": 5}
+    TIMERS = {"walk": 0, "build": 1, "pm_solve": 2, "pm_interp": 3, "sort": 4, "walk_rel": 5,
+              "keys": 6, "gather": 7, "topology": 8, "moments": 9, "deposit": 10, "fft": 11}
 
     def timing(self, on: bool = True):
         self._rc(lib().tpm_timing_enable(self.h, int(on)))

@@ -378,7 +378,7 @@ static int drain_timer(tpm_ctx *c, int kind, std::vector<float> &out) {
 }
 
 int tpm_timing_read(tpm_ctx *c, int kind, double *ms, int64_t *launches) {
-    if (!c || kind < 0 || kind >= 8)
+    if (!c || kind < 0 || kind >= TPM_TIMER_KINDS)
         return TPM_EINVAL;
     std::vector<float> d;
     TPM_TRY(drain_timer(c, kind, d));
@@ -393,7 +393,7 @@ int tpm_timing_read(tpm_ctx *c, int kind, double *ms, int64_t *launches) {
 }
 
 int tpm_timing_durations(tpm_ctx *c, int kind, double *ms, int64_t cap, int64_t *launches) {
-    if (!c || kind < 0 || kind >= 8 || cap < 0 || (cap > 0 && !ms))
+    if (!c || kind < 0 || kind >= TPM_TIMER_KINDS || cap < 0 || (cap > 0 && !ms))
         return TPM_EINVAL;
     std::vector<float> d;
     TPM_TRY(drain_timer(c, kind, d));

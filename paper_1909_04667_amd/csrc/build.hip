@@ -482,6 +482,7 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
     Frame *F = (Frame *)c->frame.p;
 
     // 1. root cube
+    TPM_TRY(timer_begin(c, TPM_TIMER_KEYS));
     if (P.periodic) {
         Frame h{};
         for (int a = 0; a < 3; a++)
@@ -505,6 +506,7 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
     k_keys<<<grid_for(n, kBlock), kBlock, 0, st>>>(x, y, z, n, F, (uint64_t *)c->key[0].p,
                                                    (uint32_t *)c->idx[0].p);
     TPM_LAUNCHED(c, "k_keys");
+    TPM_TRY(timer_end(c, TPM_TIMER_KEYS));
     TPM_TRY(radix_sort_pairs(c, n));
     // individual softening: spline supports in curve order; a bad value
     // sets the second error word, read back with the sizes below
@@ -512,11 +514,13 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
     uint32_t *bad_eps = (uint32_t *)c->err_flag.p + 1;
     if (c->mixed)
         TPM_TRY(ensure(c, c->hs, (size_t)n * 8));
+    TPM_TRY(timer_begin(c, TPM_TIMER_GATHER));
     k_gather<<<grid_for(n, kBlock), kBlock, 0, st>>>(
         x, y, z, mass, n, F, (const uint32_t *)c->idx[0].p, (int32_t *)c->perm.p,
         (int32_t *)c->rank.p, (double *)c->ps.p, (double *)c->ms.p, (uint64_t *)c->qs.p, eps,
         c->mixed ? (double *)c->hs.p : nullptr, bad_eps);
     TPM_LAUNCHED(c, "k_gather");
+    TPM_TRY(timer_end(c, TPM_TIMER_GATHER));
     // 4. topology: counts, scan, one readback of the sizes
     const uint64_t *key = (const uint64_t *)c->key[0].p;
     uint32_t *lvl_count = (uint32_t *)c->counters.p;  // [0..21] level starts, [32] E, [33] nodes
@@ -524,12 +528,14 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
     TPM_TRY(ensure(c, c->hist, (size_t)2 * kLevels * nb * sizeof(uint32_t)));
     uint32_t *lhist = (uint32_t *)c->hist.p;
     uint32_t *loff = lhist + (size_t)kLevels * nb;
+    TPM_TRY(timer_begin(c, TPM_TIMER_TOPOLOGY));
     k_count<<<nb, kBlock, 0, st>>>(key, n, (int8_t *)c->dR.p, (uint32_t *)c->cnt.p, lhist, nb);
     TPM_LAUNCHED(c, "k_count");
     TPM_TRY(scan_u32(c, (const uint32_t *)c->cnt.p, (uint32_t *)c->base.p, n, lvl_count + 32));
     TPM_TRY(scan_u32(c, lhist, loff, (int64_t)kLevels * nb, lvl_count + 33));
     k_level_starts<<<1, 64, 0, st>>>(loff, nb, lvl_count);
     TPM_LAUNCHED(c, "k_level_starts");
+    TPM_TRY(timer_end(c, TPM_TIMER_TOPOLOGY));
     TPM_HIP(c, hipMemcpyAsync(c->hpin, lvl_count, 64 * sizeof(uint32_t), hipMemcpyDeviceToHost,
                               st));
     if (!P.periodic)
@@ -566,13 +572,16 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
         TPM_TRY(ensure(c, c->eh64, (size_t)E * 8));
         eh = (double *)c->eh64.p;
     }
+    TPM_TRY(timer_begin(c, TPM_TIMER_TOPOLOGY));
     k_emit<<<grid_for(n, kBlock), kBlock, 0, st>>>(
         key, n, (const int8_t *)c->dR.p, (const uint32_t *)c->base.p, F,
         (const double *)c->ps.p, (const double *)c->ms.p, (const uint64_t *)c->qs.p, rec,
         (uint32_t *)c->efirst.p, (uint32_t *)c->ecount.p, (uint32_t *)c->pe.p, loff, nb,
         (uint32_t *)c->lvl_list.p, (const double *)c->hs.p, eh);
     TPM_LAUNCHED(c, "k_emit");
+    TPM_TRY(timer_end(c, TPM_TIMER_TOPOLOGY));
     // 5. moments, deepest level first
+    TPM_TRY(timer_begin(c, TPM_TIMER_MOMENTS));
     for (int l = kMaxLevel; l >= 0; l--) {
         const uint32_t cnt = c->level_count[l];
         if (!cnt)
@@ -591,6 +600,7 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
             (Rec32 *)c->rec32.p, eh, c->mixed ? (float *)c->eh32.p : nullptr);
         TPM_LAUNCHED(c, "k_pack32");
     }
+    TPM_TRY(timer_end(c, TPM_TIMER_MOMENTS));
     c->n = n;
     c->E = E;
     return TPM_OK;

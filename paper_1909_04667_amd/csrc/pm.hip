@@ -846,11 +846,13 @@ int solve_t(tpm_ctx *c) {
         c->axis_tables_M = M;
     }
     unsigned long long *mq = (unsigned long long *)c->mesh_q.p;
+    TPM_TRY(timer_begin(c, TPM_TIMER_DEPOSIT));
     TPM_TRY(fill_u64(c, (uint64_t *)mq, 0ull, (int64_t)(planes * n3)));
     k_deposit<kTwo><<<grid_for(c->n, kDepChunk), kBlock, 0, st>>>(
         (const double *)c->ps.p, (const double *)c->ms.p, c->n, (const Rec64 *)c->rec64.p, mg,
         mq, kTwo ? n3 : 0);
     TPM_LAUNCHED(c, "k_deposit");
+    TPM_TRY(timer_end(c, TPM_TIMER_DEPOSIT));
     FftArgs fa;
     fa.rec = (const Rec64 *)c->rec64.p;
     fa.plane = kTwo ? n3 : 0;
@@ -871,9 +873,10 @@ int solve_t(tpm_ctx *c) {
     const Cx<T> *tw = (const Cx<T> *)c->twiddle.p;
     const FftPass passes[5] = {{2, 1, 0, 0, 0, 1}, {1, 0, 0, 0, 0, 1}, {0, 0, 0, 0, 1, 1},
                                {1, 0, 0, 1, 0, 1}, {2, 0, 1, 1, 0, 1}};
+    TPM_TRY(timer_begin(c, TPM_TIMER_FFT));
     for (const FftPass &fp : passes)
         TPM_TRY(fft_pass<T>(c, M, fp, mc, mq, phi, tw, fa));
-    return TPM_OK;
+    return timer_end(c, TPM_TIMER_FFT);
 }
 
 template <typename T>

@@ -114,7 +114,7 @@ struct tpm_ctx {
     int axis_tables_M = 0;      // mesh size the twiddle and axis tables hold (0: none)
     // measurement: event pairs per timer class, and a pool of spare events
     int timing = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[8];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[TPM_TIMER_KINDS];
     std::vector<hipEvent_t> event_pool;
 };
 
