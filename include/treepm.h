@@ -299,6 +299,47 @@ int tpm_batch_add(tpm_batch *batch, tpm_ctx *ctx, int32_t opening, int64_t n_act
  * after the previous launch). */
 int tpm_batch_launch(tpm_batch *batch);
 
+/* ---- Serving: a device-resident request loop ------------------------------
+ * A server is one persistent kernel per precision that keeps running while
+ * requests arrive: tree-force requests (the same arguments as
+ * tpm_compute_forces) for resident contexts of uneven N and uneven active
+ * fractions (the time-step bins of Sec. 7.2).  Submitting writes a
+ * descriptor into a ring in pinned host memory; the running kernel picks it
+ * up, runs the request's phases (active-set marking and compaction in curve
+ * order, the per-group walks, the outputs in caller order) as work items
+ * interleaved with other requests' items, and stores the request's ticket
+ * back into pinned memory when its outputs are complete.  Every work item
+ * runs the single-system code, so results are bit-identical to
+ * tpm_compute_forces alone or in any mix.  The kernel leaves after idle_ms
+ * without work and is launched again by the next submit or poll.
+ * Requirements: the context's precision is the server's; one request per
+ * context in flight; inputs (the tree, active_idx, a_old_norm) complete
+ * before submission -- submit synchronises the context's stream -- and
+ * outputs untouched until tpm_server_poll reports the request finished.
+ * A context rebuilt while the kernel runs makes the next submit drain the
+ * kernel and launch it again.  Potentials are not produced. */
+typedef struct tpm_server tpm_server;
+
+/* precision: TPM_FP32 or TPM_FP64; idle_ms in (0, 1e4]: how long the
+ * kernel waits for work before it leaves.  Creates its own non-blocking
+ * stream on the current device. */
+int tpm_server_create(int32_t precision, double idle_ms, tpm_server **out);
+/* Stops the kernel, waits for it, frees everything. */
+int tpm_server_destroy(tpm_server *server);
+const char *tpm_server_last_error(const tpm_server *server);
+/* Submit a request (n_act >= 1); *ticket identifies it.  TPM_ESTATE if the
+ * context has a request in flight or all 256 request slots are in use. */
+int tpm_server_submit(tpm_server *server, tpm_ctx *ctx, int32_t opening, int64_t n_act,
+                      const int32_t *active_idx, const double *a_old_norm, void *acc,
+                      uint32_t *n_interactions, uint64_t *ticket);
+/* 1 once the request's outputs are complete and visible to the host and to
+ * later work on any stream, 0 while pending (never blocks). */
+int tpm_server_poll(tpm_server *server, uint64_t ticket);
+/* Blocks until tpm_server_poll would return 1. */
+int tpm_server_wait(tpm_server *server, uint64_t ticket);
+/* Kernel launches so far and requests in flight (either may be NULL). */
+int tpm_server_info(const tpm_server *server, int64_t *launches, int64_t *in_flight);
+
 /* ---- time integration (Sec. 7.1-7.3) --------------------------------------
  *
  * Kernels for a leapfrog driver with the power-of-two time-step hierarchy

@@ -72,6 +72,14 @@ def lib():
         L.tpm_timing_enable.argtypes = [vp, C.c_int]
         L.tpm_timing_read.argtypes = [vp, C.c_int, P(d), P(i64)]
         L.tpm_timing_durations.argtypes = [vp, C.c_int, P(d), i64, P(i64)]
+        L.tpm_server_create.argtypes = [i32, d, P(vp)]
+        L.tpm_server_destroy.argtypes = [vp]
+        L.tpm_server_last_error.argtypes = [vp]
+        L.tpm_server_last_error.restype = C.c_char_p
+        L.tpm_server_submit.argtypes = [vp, vp, i32, i64, vp, vp, vp, vp, P(C.c_uint64)]
+        L.tpm_server_poll.argtypes = [vp, C.c_uint64]
+        L.tpm_server_wait.argtypes = [vp, C.c_uint64]
+        L.tpm_server_info.argtypes = [vp, P(i64), P(i64)]
         L.tpm_batch_create.argtypes = [vp, P(vp)]
         L.tpm_batch_destroy.argtypes = [vp]
         L.tpm_batch_last_error.argtypes = [vp]
@@ -313,6 +321,74 @@ class Context:
         self._rc(lib().tpm_export_mesh(self.h, C.c_void_p(rho.ctypes.data),
                                        C.c_void_p(phi.ctypes.data)))
         return rho.reshape(M, M, M), phi.reshape(M, M, M)
+
+
+class ResidentServer:
+    """The device-resident request loop of one precision: a persistent kernel
+    that takes tree-force requests while it runs (tpm_server_*)."""
+
+    def __init__(self, precision="fp32", idle_ms=5.0):
+        h = C.c_void_p()
+        rc = lib().tpm_server_create(PRECISION[precision], float(idle_ms), C.byref(h))
+        if rc != TPM_OK:
+            raise TreePMError(rc, "tpm_server_create failed")
+        self.h = h
+        self.precision = precision
+        self._keep = {}
+
+    def _rc(self, rc):
+        if rc < 0:
+            raise TreePMError(rc, lib().tpm_server_last_error(self.h).decode())
+        return rc
+
+    def submit(self, ctx: Context, active_idx, opening="bh", a_old_norm=None, acc=None,
+               n_interactions=None):
+        """Returns (ticket, acc); acc is valid once poll(ticket) is true."""
+        na = active_idx.numel()
+        if acc is None:
+            acc = torch.empty((3, na), dtype=ctx.dtype, device=active_idx.device)
+        t = C.c_uint64()
+        rc = lib().tpm_server_submit(self.h, ctx.h, OPEN[opening], na, _ptr(active_idx),
+                                     _ptr(a_old_norm), _ptr(acc), _ptr(n_interactions),
+                                     C.byref(t))
+        if rc != TPM_OK:
+            msg = lib().tpm_server_last_error(self.h).decode() or lib().tpm_last_error(
+                ctx.h).decode()
+            raise TreePMError(rc, msg)
+        self._keep[t.value] = (active_idx, a_old_norm, acc, n_interactions)
+        return t.value, acc
+
+    def poll(self, ticket) -> bool:
+        done = self._rc(lib().tpm_server_poll(self.h, ticket)) == 1
+        if done:
+            self._keep.pop(ticket, None)
+        return done
+
+    def wait(self, ticket, timeout_s=120.0):
+        """Polls until the request finished; raises after timeout_s."""
+        import time
+        t_end = time.perf_counter() + timeout_s
+        while not self.poll(ticket):
+            if time.perf_counter() > t_end:
+                raise TreePMError(TPM_ESTATE, f"request {ticket} not finished in {timeout_s} s")
+            time.sleep(0)
+
+    def info(self):
+        a, b = C.c_int64(), C.c_int64()
+        self._rc(lib().tpm_server_info(self.h, C.byref(a), C.byref(b)))
+        return {"launches": int(a.value), "in_flight": int(b.value)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tpm_server_destroy(self.h)
+            self.h = None
+            self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtreepm.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["prims.hip", "build.hip", "walk.hip", "pm.hip", "api.hip", "integrate.hip",
-           "noalloc.hip", "probe.hip"]
+           "noalloc.hip", "probe.hip", "server.hip"]
 
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

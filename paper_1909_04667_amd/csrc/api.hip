@@ -1,6 +1,7 @@
 // C ABI of the gfx950 TreePM library: argument validation, buffer ownership,
 // error reporting and the verification export.  The hot path lives in
 // build.hip, walk.hip and pm.hip.
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -10,6 +11,11 @@
 #include "tpm_internal.h"
 
 namespace tpm {
+
+static std::atomic<uint64_t> g_memory_epoch{0};
+
+uint64_t memory_epoch() { return g_memory_epoch.load(std::memory_order_acquire); }
+void bump_memory_epoch() { g_memory_epoch.fetch_add(1, std::memory_order_acq_rel); }
 
 int fail(tpm_ctx *c, int code, const std::string &msg) {
     if (c)
@@ -31,6 +37,7 @@ int ensure(tpm_ctx *c, DBuf &b, size_t bytes) {
         return TPM_OK;
     if (b.p) {
         TPM_HIP(c, hipStreamSynchronize(c->stream));
+        bump_memory_epoch();
         TPM_HIP(c, hipFree(b.p));
         b.p = nullptr;
         b.cap = 0;
@@ -96,6 +103,7 @@ int timer_end(tpm_ctx *c, int kind) {
 }
 
 static void free_all(tpm_ctx *c) {
+    bump_memory_epoch();
     for (auto &v : c->timed) {
         for (auto &pr : v) {
             if (pr.first)
@@ -266,6 +274,7 @@ int tpm_build_tree_eps(tpm_ctx *c, int64_t n, const double *x, const double *y,
     TPM_HIP(c, hipSetDevice(c->device));
     c->built = 0;
     c->pm_ready = 0;
+    bump_memory_epoch();
     c->epoch = 0;  // marks must be cleared before the next active set
     if (!c->err_flag.p) {
         TPM_TRY(ensure(c, c->err_flag, 16));

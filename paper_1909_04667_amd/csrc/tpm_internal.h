@@ -125,6 +125,11 @@ int fail(tpm_ctx *c, int code, const std::string &msg);
 int hip_check(tpm_ctx *c, hipError_t e, const char *what);
 int ensure(tpm_ctx *c, DBuf &b, size_t bytes);
 size_t bytes_held(const tpm_ctx *c);
+// Count of events that rewrite tree records or free device memory (builds,
+// frees), library-wide: a kernel that outlives such an event may hold stale
+// scalar-cache lines of the affected addresses.
+uint64_t memory_epoch();
+void bump_memory_epoch();
 
 #define TPM_TRY(expr)            \
     do {                         \

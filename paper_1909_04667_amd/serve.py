@@ -3,24 +3,22 @@
 Systems (N-body particle sets of uneven size) stay resident on the GPU with
 their trees; requests name a system, an active subset (the particles whose
 time-step bins are due, Sec. 7.2 of the Arepo paper) and a precision.  The
-loop:
+walks run inside the library's device-resident request loop: one persistent
+kernel per precision (``ResidentServer``) that takes requests while it runs,
+so a request that arrives while others are on the GPU joins the running
+kernel and its work items interleave with theirs.  This module schedules:
 
 * admission -- a request's system is built when first needed if its memory
   estimate (``tpm_bytes_needed``) fits the HBM budget, evicting idle systems
-  least recently used; otherwise the request waits;
-* builds (and the PM solve of periodic systems) run on a build stream while
-  the walk stream serves the systems that are ready;
-* batching -- every iteration stages at most one request stage per system
-  and launches ONE batched persistent walk per precision for all of them
-  (``tpm_batch_launch``); requests that arrive while a launch is on the GPU
-  join the next one;
+  least recently used; otherwise the request waits; a system that can never
+  fit is rejected;
 * stages -- isolated systems with the relative criterion and periodic
   systems take two passes as in the paper's first force computation
-  (Sec. 3.1): geometric criterion (plus PM long range), then the relative
-  criterion with |a| of the first pass; Plummer systems take the geometric
-  pass only;
-* completion times come from GPU events on the walk stream, so latency =
-  GPU completion time - arrival time, both relative to the same start.
+  (Sec. 3.1): geometric criterion (plus PM long range for periodic boxes),
+  then the relative criterion with |a| of the first pass; Plummer systems
+  take the geometric pass only.  One request per system is in flight; the
+  PM interpolation and |a| run on the system's own stream;
+* latency = host time at which completion is observed - arrival time.
 
 All force arithmetic runs in the library's kernels; this module only
 schedules them.
@@ -29,7 +27,7 @@ from __future__ import annotations
 
 import math
 import time
-from collections import OrderedDict
+from collections import OrderedDict, deque
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -61,9 +59,11 @@ class Resident:
     tensors: tuple
     bytes: int
     ready: torch.cuda.Event
+    stream: torch.cuda.Stream
     periodic: bool
     stages: tuple
-    busy: int = 0          # requests admitted and not finished
+    queue: deque = field(default_factory=deque)  # admitted jobs, FIFO
+    active: "Job | None" = None                  # the job in flight
     last_used: float = 0.0
 
 
@@ -73,26 +73,31 @@ class Job:
     key: tuple
     idx: torch.Tensor
     stage: int = 0
+    state: str = "new"      # new, queued, walking, norm, done, rejected
+    ticket: int = 0
     acc: torch.Tensor | None = None
     acc_pm: torch.Tensor | None = None
     anorm: torch.Tensor | None = None
-    done_event: torch.cuda.Event | None = None
-    done_ms: float = math.nan
-    admitted: bool = False
-    rejected: bool = False
+    norm_event: torch.cuda.Event | None = None
+    done_s: float = math.nan
+    waited: bool = False
+
+    @property
+    def rejected(self):
+        return self.state == "rejected"
 
 
 @dataclass
 class Stats:
     latencies_ms: list = field(default_factory=list)
     force_evals: int = 0
-    batches: int = 0
-    items_per_batch: list = field(default_factory=list)
     builds: int = 0
     evictions: int = 0
+    waits: int = 0
+    rejected: int = 0
     wall_s: float = 0.0
     span_ms: float = 0.0
-    rejected: int = 0
+    kernel_launches: int = 0
 
     def summary(self):
         lat = sorted(self.latencies_ms)
@@ -106,24 +111,19 @@ class Stats:
                 "throughput_evals_per_s": self.force_evals / (self.span_ms * 1e-3)
                 if self.span_ms > 0 else math.nan,
                 "p50_ms": q(50), "p99_ms": q(99), "max_ms": q(100),
-                "batches": self.batches,
-                "mean_stages_per_batch": float(np.mean(self.items_per_batch))
-                if self.items_per_batch else 0.0,
-                "builds": self.builds, "evictions": self.evictions, "rejected": self.rejected,
-                "wall_s": self.wall_s}
+                "builds": self.builds, "evictions": self.evictions,
+                "waited_for_memory": self.waits, "rejected": self.rejected,
+                "server_kernel_launches": self.kernel_launches, "wall_s": self.wall_s}
 
 
 class Server:
-    def __init__(self, pool, budget_bytes: int, device="cuda:0", max_inflight: int = 2):
+    def __init__(self, pool, budget_bytes: int, device="cuda:0", idle_ms: float = 5.0):
         self.pool = pool
         self.budget = int(budget_bytes)
         self.dev = torch.device(device)
-        self.build_stream = torch.cuda.Stream(device=self.dev)
-        self.walk_stream = torch.cuda.Stream(device=self.dev)
-        self.batch = B.Batch(stream=self.walk_stream)
+        self.loops = {p: B.ResidentServer(p, idle_ms) for p in ("fp32", "fp64")}
         self.resident: "OrderedDict[tuple, Resident]" = OrderedDict()
         self.used = 0
-        self.max_inflight = max_inflight
         self.particles = {}
 
     # -- memory admission ----------------------------------------------------
@@ -137,7 +137,7 @@ class Server:
             if self.used + need <= self.budget:
                 break
             r = self.resident[key]
-            if r.busy == 0:
+            if r.active is None and not r.queue:
                 r.ctx.close()
                 self.used -= r.bytes
                 del self.resident[key]
@@ -145,41 +145,87 @@ class Server:
         return self.used + need <= self.budget
 
     def _admit(self, job: Job, stats) -> bool:
+        """Queue the job on its resident system, building the system if it is
+        not resident and memory allows; False if it has to wait."""
         if job.key in self.resident:
             r = self.resident[job.key]
-            r.busy += 1
             self.resident.move_to_end(job.key)
+            r.queue.append(job)
             return True
         spec = self.pool[job.req.sid]
         params, stages = system_params(spec, job.req.precision)
         need = B.bytes_needed(params, spec.n)
         if need > self.budget:
-            job.rejected = True  # can never fit
+            job.state = "rejected"  # can never fit
             return False
         if not self._evict_for(need, stats):
+            if not job.waited:
+                job.waited = True
+                stats.waits += 1
             return False
         p = self._particles(job.req.sid)
-        with torch.cuda.stream(self.build_stream):
-            t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(self.dev, non_blocking=False)
+        st = torch.cuda.Stream(device=self.dev)
+        with torch.cuda.stream(st):
+            t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(self.dev)
             x, y, z = t(p.x), t(p.y), t(p.z)
-            ctx = B.Context(params, stream=self.build_stream)
+            ctx = B.Context(params, stream=st)
             ctx.build_tree(x, y, z)
             if spec.kind == "periodic":  # solve the mesh once per build
                 ctx.pm_long_range(torch.zeros(0, dtype=torch.int32, device=self.dev))
             ev = torch.cuda.Event()
-            ev.record(self.build_stream)
-        ctx.set_stream(self.walk_stream)  # per-request work runs on the walk stream
-        r = Resident(job.key, ctx, (x, y, z), need, ev, spec.kind == "periodic", stages,
-                     busy=1)
+            ev.record(st)
+        r = Resident(job.key, ctx, (x, y, z), need, ev, st, spec.kind == "periodic", stages)
+        r.queue.append(job)
         self.resident[job.key] = r
         self.used += need
         stats.builds += 1
         return True
 
+    # -- request stages --------------------------------------------------------
+    def _start(self, j: Job, r: Resident):
+        """Submit the job's next walk (and the first stage's PM interpolation)."""
+        loop = self.loops[j.req.precision]
+        dt = r.ctx.dtype
+        if j.stage == 0:
+            j.ticket, j.acc = loop.submit(r.ctx, j.idx, "bh",
+                                          acc=torch.empty((3, j.idx.numel()), dtype=dt,
+                                                          device=self.dev))
+            if r.periodic:  # the mesh part, on the system's stream meanwhile
+                with torch.cuda.stream(r.stream):
+                    j.acc_pm, _ = r.ctx.pm_long_range(j.idx, want_pot=False)
+        else:
+            j.ticket, j.acc = loop.submit(r.ctx, j.idx, r.stages[j.stage], a_old_norm=j.anorm,
+                                          acc=torch.empty((3, j.idx.numel()), dtype=dt,
+                                                          device=self.dev))
+        j.state = "walking"
+
+    def _advance(self, j: Job, r: Resident, now: float) -> bool:
+        """Move a job on; True when it finished."""
+        loop = self.loops[j.req.precision]
+        if j.state == "walking":
+            if not loop.poll(j.ticket):
+                return False
+            j.stage += 1
+            if j.stage >= len(r.stages):
+                j.state = "done"
+                j.done_s = now
+                return True
+            # |a| of the first pass (tree + PM) for the relative criterion
+            with torch.cuda.stream(r.stream):
+                j.anorm = torch.zeros(r.ctx.n, dtype=torch.float64, device=self.dev)
+                r.ctx.accel_norm(j.idx, j.acc, j.acc_pm, out=j.anorm)
+                j.norm_event = torch.cuda.Event()
+                j.norm_event.record(r.stream)
+            j.state = "norm"
+            return False
+        if j.state == "norm" and j.norm_event.query():
+            self._start(j, r)
+        return False
+
     # -- the loop ---------------------------------------------------------------
-    def run(self, requests, time_scale: float = 1.0):
-        """Serve ``requests`` (arrival times in seconds, scaled by time_scale)
-        and return Stats.  Active subsets are drawn and uploaded beforehand."""
+    def run(self, requests):
+        """Serve ``requests`` (arrival times in seconds) and return (Stats,
+        jobs).  Active subsets are drawn and uploaded beforehand."""
         stats = Stats()
         jobs = []
         for sid in sorted({rq.sid for rq in requests}):
@@ -188,102 +234,63 @@ class Server:
             n = self.pool[rq.sid].n
             idx = torch.as_tensor(W.request_active(rq, n), dtype=torch.int32, device=self.dev)
             jobs.append(Job(rq, (rq.sid, rq.precision), idx))
+        launches0 = sum(lp.info()["launches"] for lp in self.loops.values())
         torch.cuda.synchronize()
-        pending = list(jobs)          # not yet arrived or not yet admitted
-        ready = []                    # admitted, waiting for a stage launch
-        inflight = []                 # (event, [jobs whose stage ends there])
-        start = torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        start.record(self.walk_stream)
+        pending = deque(sorted(jobs, key=lambda j: j.req.t_arrival))
+        waiting = []        # arrived, not admitted (memory)
         finished = 0
+        t0 = time.perf_counter()
         while finished < len(jobs):
-            now = (time.perf_counter() - t0) / time_scale
-            # arrivals and admission, in arrival order
+            now = time.perf_counter() - t0
+            # arrivals
+            while pending and pending[0].req.t_arrival <= now:
+                waiting.append(pending.popleft())
+            # admission, in arrival order
             still = []
-            for j in pending:
-                if j.req.t_arrival <= now and self._admit(j, stats):
-                    j.admitted = True
-                    ready.append(j)
+            for j in waiting:
+                if self._admit(j, stats):
+                    j.state = "queued"
                 elif j.rejected:
                     finished += 1
                 else:
                     still.append(j)
-            pending = still
-            # completed launches
-            while inflight and inflight[0][0].query():
-                ev, done_jobs = inflight.pop(0)
-                for j in done_jobs:
-                    r = self.resident[j.key]
-                    r.busy -= 1
-                    r.last_used = now
-                    finished += 1
-            # launch the next batch if the GPU queue has room
-            if len(inflight) < self.max_inflight and ready:
-                staged, rest, ends = set(), [], []
-                for j in ready:
-                    r = self.resident[j.key]
-                    if j.key in staged or not r.ready.query():
-                        rest.append(j)
-                        continue
-                    staged.add(j.key)
-                    self.walk_stream.wait_event(r.ready)
-                    self._stage(j, r)
-                    if j.stage >= len(r.stages):
-                        ends.append(j)
-                    else:
-                        rest.append(j)
-                ready = rest
-                if staged:
-                    self.batch.launch()
-                    ev = torch.cuda.Event(enable_timing=True)
-                    ev.record(self.walk_stream)
-                    for j in ends:
-                        j.done_event = ev
-                    inflight.append((ev, ends))
-                    stats.batches += 1
-                    stats.items_per_batch.append(len(staged))
-            elif not ready and not inflight:
-                time.sleep(1e-4)
+            waiting = still
+            # per resident system: advance the job in flight, start the next
+            busy = False
+            for r in list(self.resident.values()):
+                if r.active is not None:
+                    busy = True
+                    if self._advance(r.active, r, now):
+                        finished += 1
+                        r.active = None
+                        r.last_used = now
+                if r.active is None and r.queue and r.ready.query():
+                    r.active = r.queue.popleft()
+                    self._start(r.active, r)
+                    busy = True
+            if not busy and not waiting:
+                time.sleep(5e-5)
         torch.cuda.synchronize()
         stats.wall_s = time.perf_counter() - t0
-        first = min((j.req.t_arrival for j in jobs if not j.rejected), default=0.0) * 1e3 * time_scale
-        last = 0.0
         stats.rejected = sum(j.rejected for j in jobs)
-        for j in jobs:
-            if j.rejected:
-                continue
-            j.done_ms = start.elapsed_time(j.done_event)
-            stats.latencies_ms.append(j.done_ms - j.req.t_arrival * 1e3 * time_scale)
+        stats.kernel_launches = sum(lp.info()["launches"] for lp in self.loops.values()) - \
+            launches0
+        served = [j for j in jobs if not j.rejected]
+        if served:
+            first = min(j.req.t_arrival for j in served)
+            last = max(j.done_s for j in served)
+            stats.span_ms = (last - first) * 1e3
+        for j in served:
+            stats.latencies_ms.append((j.done_s - j.req.t_arrival) * 1e3)
             stats.force_evals += j.idx.numel()
-            last = max(last, j.done_ms)
-        stats.span_ms = last - first
         return stats, jobs
 
-    def _stage(self, j: Job, r: Resident):
-        """Stage the next pass of job j into the current batch."""
-        opening = r.stages[j.stage]
-        dt = r.ctx.dtype
-        if j.stage == 0:
-            if r.periodic:
-                j.acc_pm, _ = r.ctx.pm_long_range(j.idx, want_pot=False)
-            j.acc = self.batch.add(r.ctx, j.idx, "bh",
-                                   acc=torch.empty((3, j.idx.numel()), dtype=dt,
-                                                   device=self.dev))
-        else:
-            # |a| of the first pass (tree + PM) feeds the relative criterion
-            with torch.cuda.stream(self.walk_stream):
-                j.anorm = torch.zeros(r.ctx.n, dtype=torch.float64, device=self.dev)
-            r.ctx.accel_norm(j.idx, j.acc, j.acc_pm, out=j.anorm)
-            j.acc = self.batch.add(r.ctx, j.idx, opening, a_old_norm=j.anorm,
-                                   acc=torch.empty((3, j.idx.numel()), dtype=dt,
-                                                   device=self.dev))
-        j.stage += 1
-
     def close(self):
+        for lp in self.loops.values():
+            lp.close()
         for r in self.resident.values():
             r.ctx.close()
         self.resident.clear()
-        self.batch.close()
 
 
 def total_force(job: Job):

@@ -349,14 +349,18 @@ def fp32_mesh_bounds(ng3, h, a_ref, pot_ref):
     u log2(ng^3) rms(Phi); the four-point difference turns them into force
     errors of order u log2(ng^3) rms(Phi) / h, i.e. u log2(ng^3) kappa
     rms|a| with kappa = rms(Phi) / (h rms|a|) (the reference's potential and
-    force at the targets).  Bounds: force 2 u log2(ng^3) kappa rms|a|,
-    potential 8 u log2(ng^3) rms(Phi); measured up to 0.75 and 4.1 of those
-    units on near-uniform and clustered boxes with meshes of 16^3 to 256^3."""
-    ul = 2.0 ** -24 * math.log2(ng3)
+    force at the targets); the float storage of the density and potential
+    adds a term of order u kappa rms|a| that does not grow with the mesh.
+    Bounds: force u (2 log2(ng^3) + 32) kappa rms|a|, potential
+    8 u log2(ng^3) rms(Phi).  Measured: force errors up to 0.75 u log2(ng^3)
+    kappa rms|a| on near-uniform and clustered boxes with meshes of 16^3 to
+    256^3, and 34 u kappa rms|a| on the 8^3 mesh."""
+    u = 2.0 ** -24
+    lg = math.log2(ng3)
     rms_a = math.sqrt(float(np.mean(np.sum(a_ref * a_ref, axis=0))))
     rms_p = math.sqrt(float(np.mean(pot_ref * pot_ref)))
     kappa = rms_p / (h * rms_a)
-    return 2.0 * ul * kappa * rms_a, 8.0 * ul * rms_p
+    return u * (2.0 * lg + 32.0) * kappa * rms_a, 8.0 * u * lg * rms_p
 
 
 def _check_fp32_mesh(a, pot, a_ref, pot_ref, ng3, h):
