@@ -273,34 +273,69 @@ def run_integrators():
     return out
 
 
-def run_serving(n_requests=10000, n_burst=2000, n_systems=16, seed=5):
-    """Continuous batching over a pool of resident systems: capacity from a
-    burst of n_burst requests all present at t = 0, then n_requests Poisson
-    arrivals at 0.7 of that capacity; p50/p99 latency from GPU events."""
+def run_serving(n_poisson=4000, n_burst=2000, n_systems=16, seed=5):
+    """Continuous batching through the device-resident request loop over a
+    pool of resident systems: capacity from a burst of n_burst requests all
+    present at t = 0, then n_poisson Poisson arrivals at 0.5, 0.7 and 0.9 of
+    that capacity; latency = completion observed on the host - arrival.  The
+    burst's first 500 requests are also served one at a time through the
+    single-system path (tpm_compute_forces) for comparison."""
+    import torch
     from paper_1909_04667_amd import serve as S
     from paper_1909_04667_amd import workloads as W
     pool = W.system_pool(n_systems, seed=seed)
     burst = W.request_stream(n_burst, rate=0.0, n_systems=n_systems, seed=seed)
     srv = S.Server(pool, budget_bytes=64 << 30)
-    srv.run(burst[:n_systems * 2])  # warm-up: builds every resident system
-    st, _ = srv.run(burst)
+    srv.run(burst[:n_systems * 4])  # warm-up: builds every resident system
+    log("serving: systems resident")
+    prog = lambda k, n: log(f"serving: {k}/{n} finished")
+    st, _ = srv.run(burst, progress=prog)
     cap = st.summary()
+    log(f"serving: burst capacity {cap['throughput_evals_per_s']:.3e} evals/s")
     req_rate = cap["requests"] / (st.span_ms * 1e-3)
-    stream = W.request_stream(n_requests, rate=0.7 * req_rate, n_systems=n_systems,
-                              seed=seed + 100)
-    st2, _ = srv.run(stream)
+    out = {"systems": n_systems, "n_range": [min(s.n for s in pool), max(s.n for s in pool)],
+           "burst_requests": n_burst, "poisson_requests_per_load": n_poisson,
+           "precisions": "fp32+fp64 mix", "loop": "device-resident (tpm_server_*)",
+           "capacity": {"force_evals_per_s": cap["throughput_evals_per_s"],
+                        "requests_per_s": req_rate, "p50_ms": cap["p50_ms"],
+                        "p99_ms": cap["p99_ms"],
+                        "server_kernel_launches": cap["server_kernel_launches"]}}
+    for load in (0.5, 0.7, 0.9):
+        stream = W.request_stream(n_poisson, rate=load * req_rate, n_systems=n_systems,
+                                  seed=seed + 100 + int(10 * load))
+        st2, _ = srv.run(stream, progress=prog)
+        s2 = st2.summary()
+        log(f"serving: load {load} p50 {s2['p50_ms']:.2f} ms p99 {s2['p99_ms']:.2f} ms")
+        out[f"poisson_{load}"] = {"force_evals_per_s": s2["throughput_evals_per_s"],
+                                  "p50_ms": s2["p50_ms"], "p99_ms": s2["p99_ms"],
+                                  "max_ms": s2["max_ms"], "rejected": s2["rejected"],
+                                  "server_kernel_launches": s2["server_kernel_launches"]}
+    # the same mix, one request at a time through the single-system path
+    seq = burst[:500]
+    jobs = []
+    for rq in seq:
+        n = pool[rq.sid].n
+        idx = torch.as_tensor(W.request_active(rq, n), dtype=torch.int32, device="cuda:0")
+        jobs.append((rq, idx))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals = 0
+    for rq, idx in jobs:
+        r = srv.resident[(rq.sid, rq.precision)]
+        ctx = r.ctx
+        with torch.cuda.stream(r.stream):
+            a, _ = ctx.compute_forces(idx, "bh")
+            apm = ctx.pm_long_range(idx)[0] if r.periodic else None
+            if len(r.stages) > 1:
+                an = ctx.accel_norm(idx, a, apm)
+                a, _ = ctx.compute_forces(idx, "rel", a_old_norm=an)
+        r.stream.synchronize()
+        evals += idx.numel()
+    dt = time.perf_counter() - t0
+    out["same_mix_one_at_a_time"] = {"requests": len(seq), "force_evals_per_s": evals / dt}
+    out["capacity_vs_one_at_a_time"] = cap["throughput_evals_per_s"] / (evals / dt)
     srv.close()
-    s2 = st2.summary()
-    return {"systems": n_systems, "n_range": [min(s.n for s in pool), max(s.n for s in pool)],
-            "requests": n_requests, "burst_requests": n_burst, "precisions": "fp32+fp64 mix",
-            "capacity": {"force_evals_per_s": cap["throughput_evals_per_s"],
-                         "requests_per_s": req_rate, "p50_ms": cap["p50_ms"],
-                         "p99_ms": cap["p99_ms"]},
-            "poisson_0.7": {"force_evals_per_s": s2["throughput_evals_per_s"],
-                            "p50_ms": s2["p50_ms"], "p99_ms": s2["p99_ms"],
-                            "max_ms": s2["max_ms"], "batches": s2["batches"],
-                            "mean_stages_per_batch": s2["mean_stages_per_batch"],
-                            "rejected": s2["rejected"]}}
+    return out
 
 
 def counted_traffic(workload, kernel):

@@ -185,7 +185,8 @@ int64_t tpm_noalloc_max_n(void);
  * divide by the CIC deconvolution.  The mesh is solved from ALL particles
  * of the last build on first use after that build and cached; every call
  * interpolates.  acc: device [3][n_act], pot: device
- * [n_act] or NULL, dtype as in tpm_compute_forces.  Does not synchronise. */
+ * [n_act] or NULL (written whenever given, whatever want_potential says),
+ * dtype as in tpm_compute_forces.  Does not synchronise. */
 int tpm_pm_long_range(tpm_ctx *ctx, int64_t n_act, const int32_t *active_idx, void *acc,
                       void *pot);
 
@@ -316,6 +317,7 @@ int tpm_batch_launch(tpm_batch *batch);
  * context in flight; inputs (the tree, active_idx, a_old_norm) complete
  * before submission -- submit synchronises the context's stream -- and
  * outputs untouched until tpm_server_poll reports the request finished.
+ * The running kernels leave room on the chip for other kernels.
  * A context rebuilt while the kernel runs makes the next submit drain the
  * kernel and launch it again.  Potentials are not produced. */
 typedef struct tpm_server tpm_server;
@@ -332,6 +334,18 @@ const char *tpm_server_last_error(const tpm_server *server);
 int tpm_server_submit(tpm_server *server, tpm_ctx *ctx, int32_t opening, int64_t n_act,
                       const int32_t *active_idx, const double *a_old_norm, void *acc,
                       uint32_t *n_interactions, uint64_t *ticket);
+/* The paper's first force computation as one request (Sec. 3.1): the
+ * geometric pass, the mesh force when the context has a mesh (Sec. 3.3,
+ * 3.4; the mesh is solved first if needed), |a| of their sum for every
+ * active particle, and the relative pass with that |a|.  acc: the relative
+ * pass's tree force [3][n_act] in caller order; acc_pm: the mesh force
+ * [3][n_act] (required exactly when the context has a mesh, else NULL);
+ * n_interactions: the relative pass's counts or NULL.  Results equal
+ * tpm_compute_forces(BH), tpm_pm_long_range, tpm_accel_norm and
+ * tpm_compute_forces(REL) in sequence, bit for bit. */
+int tpm_server_submit_step(tpm_server *server, tpm_ctx *ctx, int64_t n_act,
+                           const int32_t *active_idx, void *acc, void *acc_pm,
+                           uint32_t *n_interactions, uint64_t *ticket);
 /* 1 once the request's outputs are complete and visible to the host and to
  * later work on any stream, 0 while pending (never blocks). */
 int tpm_server_poll(tpm_server *server, uint64_t ticket);

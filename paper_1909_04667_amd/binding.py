@@ -77,6 +77,7 @@ def lib():
         L.tpm_server_last_error.argtypes = [vp]
         L.tpm_server_last_error.restype = C.c_char_p
         L.tpm_server_submit.argtypes = [vp, vp, i32, i64, vp, vp, vp, vp, P(C.c_uint64)]
+        L.tpm_server_submit_step.argtypes = [vp, vp, i64, vp, vp, vp, vp, P(C.c_uint64)]
         L.tpm_server_poll.argtypes = [vp, C.c_uint64]
         L.tpm_server_wait.argtypes = [vp, C.c_uint64]
         L.tpm_server_info.argtypes = [vp, P(i64), P(i64)]
@@ -357,6 +358,25 @@ class ResidentServer:
             raise TreePMError(rc, msg)
         self._keep[t.value] = (active_idx, a_old_norm, acc, n_interactions)
         return t.value, acc
+
+    def submit_step(self, ctx: Context, active_idx, acc=None, acc_pm=None, n_interactions=None):
+        """The first force computation (BH, mesh, |a|, relative) as one request.
+        Returns (ticket, acc, acc_pm); acc_pm is None without a mesh."""
+        na = active_idx.numel()
+        dev = active_idx.device
+        if acc is None:
+            acc = torch.empty((3, na), dtype=ctx.dtype, device=dev)
+        if acc_pm is None and ctx.params.pm_grid > 0:
+            acc_pm = torch.empty((3, na), dtype=ctx.dtype, device=dev)
+        t = C.c_uint64()
+        rc = lib().tpm_server_submit_step(self.h, ctx.h, na, _ptr(active_idx), _ptr(acc),
+                                          _ptr(acc_pm), _ptr(n_interactions), C.byref(t))
+        if rc != TPM_OK:
+            msg = lib().tpm_server_last_error(self.h).decode() or lib().tpm_last_error(
+                ctx.h).decode()
+            raise TreePMError(rc, msg)
+        self._keep[t.value] = (active_idx, acc, acc_pm, n_interactions)
+        return t.value, acc, acc_pm
 
     def poll(self, ticket) -> bool:
         done = self._rc(lib().tpm_server_poll(self.h, ticket)) == 1

@@ -59,7 +59,7 @@ size_t bytes_held(const tpm_ctx *c) {
                          &c->hist, &c->scan_tmp, &c->perm, &c->rank, &c->ps, &c->ms, &c->qs,
                          &c->dR, &c->cnt, &c->base, &c->lvl_cursor, &c->lvl_list, &c->rec64,
                          &c->rec32, &c->efirst, &c->ecount, &c->pe, &c->mark, &c->act, &c->slot,
-                         &c->counters, &c->res, &c->rpot, &c->rnint, &c->err_flag, &c->mesh_q,
+                         &c->counters, &c->res, &c->rpot, &c->rnint, &c->srv_pm, &c->srv_an, &c->err_flag, &c->mesh_q,
                          &c->mesh_c, &c->mesh_phi, &c->twiddle, &c->green_axis, &c->green_tab,
                          &c->hs, &c->eh64, &c->eh32, &c->ig_flag, &c->ig_off};
     size_t s = 0;
@@ -120,7 +120,7 @@ static void free_all(tpm_ctx *c) {
                    &c->hist, &c->scan_tmp, &c->perm, &c->rank, &c->ps, &c->ms, &c->qs,
                    &c->dR, &c->cnt, &c->base, &c->lvl_cursor, &c->lvl_list, &c->rec64,
                    &c->rec32, &c->efirst, &c->ecount, &c->pe, &c->mark, &c->act, &c->slot,
-                   &c->counters, &c->res, &c->rpot, &c->rnint, &c->err_flag, &c->mesh_q,
+                   &c->counters, &c->res, &c->rpot, &c->rnint, &c->srv_pm, &c->srv_an, &c->err_flag, &c->mesh_q,
                    &c->mesh_c, &c->mesh_phi, &c->twiddle, &c->green_axis, &c->green_tab,
                    &c->hs, &c->eh64, &c->eh32, &c->ig_flag, &c->ig_off};
     for (DBuf *b : all) {

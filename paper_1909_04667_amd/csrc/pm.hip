@@ -21,7 +21,7 @@
 // holds a block of lines in registers and LDS (coalesced along the
 // contiguous axis).
 // The gradient is taken inside the interpolation kernel from the potential.
-#include "tpm_internal.h"
+#include "pm_device.h"
 
 #include <algorithm>
 #include <cmath>
@@ -30,22 +30,14 @@
 namespace tpm {
 namespace {
 
+using namespace pmk;
+
 constexpr int kBlock = 256;
 constexpr size_t kFftLds = 64 * 1024;  // LDS budget of one FFT block
 
 template <typename T>
 struct Cx {
     T re, im;
-};
-
-// Mesh geometry: point i of an axis sits at lo + i h; `box` > 0 wraps
-// positions periodically into [0, box) (lo = 0 then), `box` = 0 leaves them
-// (the isolated mesh, where every position lies well inside the mesh).
-struct MeshGeom {
-    double lo[3];
-    double box;
-    double h;
-    int ng;  // points per axis of the transformed mesh
 };
 
 // CIC base cell and weights of the particle at sorted slot s (Sec. 3.3):
@@ -540,68 +532,11 @@ __global__ __launch_bounds__(kBlock) void k_interp(const uint32_t *__restrict__ 
                                                    int64_t n, const double *__restrict__ ps,
                                                    const T *__restrict__ phi, MeshGeom mg,
                                                    T *__restrict__ res, T *__restrict__ rpot) {
-    const double box = mg.box, h = mg.h;
-    const int ng = mg.ng;
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= (int64_t)*nuniq)
         return;
-    const int64_t s = act[k];
-    int i0[3];
-    double w[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        double u = ps[(size_t)a * n + s] - mg.lo[a];
-        if (box > 0.0) {
-            if (u < 0.0)
-                u += box;
-            if (u >= box)
-                u -= box;
-        }
-        const double f = u / h;
-        const double fl = floor(f);
-        w[a] = f - fl;
-        // any input (even outside the box or NaN) stays on the mesh
-        int i = (int)fmin(fmax(fl, -1.0e9), 1.0e9) % ng;
-        if (i < 0)
-            i += ng;
-        i0[a] = i;
-    }
-    const int mask = ng - 1;
-    auto at = [&](int x, int y, int z) -> double {
-        return (double)phi[((size_t)(x & mask) * ng + (y & mask)) * ng + (z & mask)];
-    };
-    double F[3] = {0.0, 0.0, 0.0}, P = 0.0;
-#pragma unroll
-    for (int c = 0; c < 8; c++) {
-        double wt = 1.0;
-        int t[3];
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            const int up = (c >> (2 - a)) & 1;
-            wt *= up ? w[a] : 1.0 - w[a];
-            t[a] = i0[a] + up;
-        }
-        // -grad Phi at mesh point t
-        {
-            const double g = ((2.0 / 3.0) * (at(t[0] + 1, t[1], t[2]) - at(t[0] - 1, t[1], t[2])) -
-                              (1.0 / 12.0) * (at(t[0] + 2, t[1], t[2]) - at(t[0] - 2, t[1], t[2]))) /
-                             h;
-            F[0] += wt * -g;
-        }
-        {
-            const double g = ((2.0 / 3.0) * (at(t[0], t[1] + 1, t[2]) - at(t[0], t[1] - 1, t[2])) -
-                              (1.0 / 12.0) * (at(t[0], t[1] + 2, t[2]) - at(t[0], t[1] - 2, t[2]))) /
-                             h;
-            F[1] += wt * -g;
-        }
-        {
-            const double g = ((2.0 / 3.0) * (at(t[0], t[1], t[2] + 1) - at(t[0], t[1], t[2] - 1)) -
-                              (1.0 / 12.0) * (at(t[0], t[1], t[2] + 2) - at(t[0], t[1], t[2] - 2))) /
-                             h;
-            F[2] += wt * -g;
-        }
-        P += wt * at(t[0], t[1], t[2]);
-    }
+    double F[3], P;
+    interp_at<T>(ps, n, act[k], phi, mg, F, P);
     res[k] = (T)F[0];
     res[n + k] = (T)F[1];
     res[2 * n + k] = (T)F[2];
@@ -778,26 +713,6 @@ int build_green_isolated(tpm_ctx *c) {
     return rc;
 }
 
-// Mesh geometry of the current build: periodic box of ng cells, or the
-// isolated ng-cell mesh of spacing L_root / (ng - 4) starting two cells
-// below the root cube, zero-padded to (2 ng)^3.
-MeshGeom mesh_geom(const tpm_ctx *c) {
-    const tpm_params &P = c->P;
-    MeshGeom g{};
-    if (P.periodic) {
-        g.box = P.box_size;
-        g.h = P.box_size / P.pm_grid;
-        g.ng = P.pm_grid;
-    } else {
-        g.box = 0.0;
-        g.h = c->frame_host.L / (P.pm_grid - 4);
-        for (int a = 0; a < 3; a++)
-            g.lo[a] = c->frame_host.x0[a] - 2.0 * g.h;
-        g.ng = 2 * P.pm_grid;
-    }
-    return g;
-}
-
 template <typename T>
 int solve_t(tpm_ctx *c) {
     const tpm_params &P = c->P;
@@ -931,6 +846,26 @@ int export_t(tpm_ctx *c, double *rho, double *phi) {
 
 }  // namespace
 
+// Mesh geometry of the current build: periodic box of ng cells, or the
+// isolated ng-cell mesh of spacing L_root / (ng - 4) starting two cells
+// below the root cube, zero-padded to (2 ng)^3.
+MeshGeom pmk::mesh_geom(const tpm_ctx *c) {
+    const tpm_params &P = c->P;
+    MeshGeom g{};
+    if (P.periodic) {
+        g.box = P.box_size;
+        g.h = P.box_size / P.pm_grid;
+        g.ng = P.pm_grid;
+    } else {
+        g.box = 0.0;
+        g.h = c->frame_host.L / (P.pm_grid - 4);
+        for (int a = 0; a < 3; a++)
+            g.lo[a] = c->frame_host.x0[a] - 2.0 * g.h;
+        g.ng = 2 * P.pm_grid;
+    }
+    return g;
+}
+
 int pm_export(tpm_ctx *c, double *rho, double *phi) {
     if (c->P.precision == TPM_FP32)
         return export_t<float>(c, rho, phi);
@@ -946,10 +881,12 @@ int pm_solve(tpm_ctx *c) {
 int pm_interp(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, void *pot) {
     if (n_act == 0)
         return TPM_OK;
-    void *p = (pot && c->P.want_potential) ? pot : nullptr;
+    // the interpolation yields the potential anyway: written whenever the
+    // caller passes a buffer, whatever want_potential says (that flag prices
+    // the tree walk's potential)
     if (c->P.precision == TPM_FP32)
-        return interp_t<float>(c, n_act, idx, acc, p);
-    return interp_t<double>(c, n_act, idx, acc, p);
+        return interp_t<float>(c, n_act, idx, acc, pot);
+    return interp_t<double>(c, n_act, idx, acc, pot);
 }
 
 }  // namespace tpm

@@ -1,6 +1,9 @@
 // Device-resident serving loop: one persistent kernel per precision takes
-// tree-force requests for many resident systems (uneven N, uneven active
-// fractions -- the time-step bins of Sec. 7.2) while it runs.
+// force requests for many resident systems (uneven N, uneven active
+// fractions -- the time-step bins of Sec. 7.2) while it runs.  A request is
+// one tree pass (geometric or relative criterion), or the paper's whole
+// first force computation (Sec. 3.1): geometric pass, mesh force (Sec. 3.3,
+// when the context has a mesh), |a| of their sum, relative pass.
 //
 // Host side: a request is a descriptor (walk arguments of its context, the
 // active list, the outputs) written into a ring in coherent pinned host
@@ -10,6 +13,7 @@
 // job.  A request runs as phases, each a job of independent work items of one
 // wavefront: [clear the marks] -> mark the active list -> count marked ranks
 // per tile -> compact them into curve order -> walk groups of 64 targets ->
+// [mesh interpolation -> |a| -> walk again with the relative criterion] ->
 // write the outputs in caller order.  The wavefront that completes a phase's
 // last item publishes the next phase; the last item of the output phase
 // stores the request's ticket into pinned host memory (system scope), which
@@ -20,8 +24,15 @@
 // the same output gather), so each result is bit-identical alone and in any
 // mix.
 //
-// Coherence: the kernel outlives many requests, so nothing it reads through
-// the scalar cache may change while it runs.  Each request's descriptor goes
+// Coherence: the chip's dies each have their own L2, so data one work item
+// hands to a later one (marks, counts, active slots, results, |a|, job
+// entries) is written and read with device-scope relaxed accesses, which
+// bypass the non-coherent caches, and every counter that publishes it is
+// incremented only after the wavefront's own stores have completed.  No
+// acquire or release fence (cache invalidation or write-back) runs at all:
+// the outputs for the host are written through to memory with system-scope
+// stores before the request's ticket is stored into pinned memory.  The kernel outlives many requests, so nothing it
+// reads through the scalar cache may change while it runs.  Each request's descriptor goes
 // to its own entry of a ring of kDescRing entries (index = ticket modulo the
 // ring), and the host launches the kernel anew after kRelaunch requests, so
 // within one launch no entry is written twice: the walks read the arguments
@@ -31,17 +42,19 @@
 // also read with scalar loads, change only when a tree is rebuilt or device
 // memory is freed (and possibly reused): the library counts both, and a
 // submit after such an event drains the kernel and launches it again (a
-// launch starts with fresh caches) before the request runs.  Exit: a
-// wavefront leaves when the host asks (stop or drain) or after idle_ms
-// without work; the host relaunches the kernel whenever it finds it gone
-// with requests pending.
+// launch starts with fresh caches) before the request runs.  Exit: every
+// wavefront leaves when the host asks (stop or drain) or when the fetcher has
+// seen no live request for idle_ms; the host relaunches the kernel whenever
+// it finds it gone with requests pending.
 #include <atomic>
 #include <cstring>
+#include <type_traits>
 #include <new>
 #include <string>
 #include <thread>
 #include <vector>
 
+#include "pm_device.h"
 #include "walk_device.h"
 
 namespace tpm {
@@ -51,12 +64,17 @@ using namespace wk;
 
 constexpr uint32_t kSrvTile = 2048;   // ranks per count / compact item
 constexpr uint32_t kSrvChunk = 4096;  // list entries per clear / mark / output item
+constexpr uint32_t kSrvSlots = 1024;  // active slots per mesh / |a| item
 constexpr uint32_t kJobCap = 1u << 16;  // job ring (one live job per request)
 constexpr int kMaxSlots = 256;        // live requests per server
 constexpr uint32_t kDescRing = 1u << 16;  // device descriptors (index = ticket mod ring)
 constexpr uint64_t kRelaunch = 1u << 14;  // requests per launch, well below the ring
 
-enum : uint32_t { kPhClear = 0, kPhMark, kPhCount, kPhCompact, kPhWalk, kPhOutput, kPhases };
+enum : uint32_t {
+    kPhClear = 0, kPhMark, kPhCount, kPhCompact, kPhWalk, kPhPm, kPhNorm, kPhWalk2, kPhOutput
+};
+constexpr uint32_t kStep = 1u;   // flags: the whole first force computation
+constexpr uint32_t kMesh = 2u;   //        with the mesh part
 
 // One request, as the host prepares it.  variant: bit 0 relative criterion,
 // 1 TreePM, 2 lane-independent walk, 3 periodic, 4 individual softening.
@@ -76,6 +94,13 @@ struct alignas(64) SrvReq {
     uint32_t epoch;
     uint32_t clear;
     uint32_t variant;
+    uint32_t flags;       // kStep, kMesh
+    uint32_t pad0;
+    pmk::MeshGeom mg;     // mesh geometry (kMesh)
+    const void *phi;      // potential mesh (kMesh)
+    void *res_pm;         // [3][n] mesh force in slot order (kMesh)
+    void *acc_pm;         // [3][n_act] mesh force in caller order (kMesh)
+    double *anorm_out;    // [n] |a| in build order, read by the relative pass (kStep)
     uint64_t ticket;
     uint32_t slot_id;     // host slot: completion flag and ring entry
     uint32_t desc;        // device descriptor index
@@ -96,7 +121,9 @@ struct SrvDev {
     uint32_t job_reserve;  // next job index to publish
     uint32_t job_head;     // oldest job that may still have items
     uint32_t host_head;    // ring entries copied to the device
-    uint32_t fetch_lock;
+    uint32_t live;         // requests taken from the ring and not yet finished
+    uint32_t ctl;          // the host's control word, mirrored by the fetcher;
+                           // 3: the fetcher found the server idle
     uint32_t done[kDescRing];  // items finished in the live phase of each request
 };
 
@@ -110,8 +137,23 @@ struct SrvHost {
 };
 
 template <typename T>
-__device__ __forceinline__ T ld_acq(T *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ T ld_rlx(T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A result for the host: a system-scope store, written through to memory.
+template <typename T>
+__device__ __forceinline__ void out_st(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Waits until the wavefront's memory operations have completed (its
+// device-scope stores are then visible chip-wide), and keeps the compiler
+// from moving memory accesses across this point.
+__device__ __forceinline__ void wait_mem() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 __device__ __forceinline__ uint32_t phase_items(uint32_t n, uint32_t n_act, uint32_t ph,
@@ -122,7 +164,20 @@ __device__ __forceinline__ uint32_t phase_items(uint32_t n, uint32_t n_act, uint
     case kPhOutput: return (n_act + kSrvChunk - 1) / kSrvChunk;
     case kPhCount:
     case kPhCompact: return (n + kSrvTile - 1) / kSrvTile;
+    case kPhPm:
+    case kPhNorm: return (nuniq + kSrvSlots - 1) / kSrvSlots;
     default: return (nuniq + 63) / 64;  // walk groups (one slot per lane)
+    }
+}
+
+// The phase after ph.
+__device__ __forceinline__ uint32_t next_phase(uint32_t ph, uint32_t flags) {
+    switch (ph) {
+    case kPhWalk: return (flags & kStep) ? ((flags & kMesh) ? kPhPm : kPhNorm) : kPhOutput;
+    case kPhPm: return kPhNorm;
+    case kPhNorm: return kPhWalk2;
+    case kPhWalk2: return kPhOutput;
+    default: return ph + 1u;
     }
 }
 
@@ -131,71 +186,77 @@ __device__ void publish(SrvDev *st, Job *jobs, uint32_t slot, uint32_t phase, ui
     const uint32_t j = __hip_atomic_fetch_add(&st->job_reserve, 1u, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
     Job *J = &jobs[j % kJobCap];
-    __hip_atomic_store(&J->claim, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&st->done[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(&J->slot, slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&J->phase, phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&J->nitems, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&J->claim, (unsigned long long)(j + 1u) << 32, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    coherent_st(&J->claim, 0ull);
+    coherent_st(&st->done[slot], 0u);
+    wait_mem();
+    coherent_st(&J->slot, slot);
+    coherent_st(&J->phase, phase);
+    coherent_st(&J->nitems, n);
+    wait_mem();
+    coherent_st(&J->claim, (unsigned long long)(j + 1u) << 32);
 }
 
-// Lane 0: claims the next item of the oldest job that has one.  Returns
-// false when no published job has an item left.
+// Lane 0: claims the next item of the oldest job that has one: a load sees
+// items left, then one fetch-and-add takes an item (no compare-and-swap
+// retries when many wavefronts look at once).  The item taken is always
+// honoured: should the entry have been republished in between (it is reused
+// only after kJobCap newer jobs), it is that job's item.  Returns false when
+// no published job has an item left.
 __device__ bool claim(SrvDev *st, Job *jobs, uint32_t &slot, uint32_t &phase, uint32_t &nitems,
                       uint32_t &item) {
-    for (int guard = 0; guard < 1 << 20; guard++) {
-        const uint32_t h = ld_acq(&st->job_head);
+    for (int guard = 0; guard < 64; guard++) {
+        const uint32_t h = ld_rlx(&st->job_head);
         Job *J = &jobs[h % kJobCap];
-        const unsigned long long c1 = ld_acq(&J->claim);
+        const unsigned long long c1 = ld_rlx(&J->claim);
         if ((uint32_t)(c1 >> 32) != h + 1u)
             return false;  // not (yet) published
-        const uint32_t sl = ld_acq(&J->slot), ph = ld_acq(&J->phase), ni = ld_acq(&J->nitems);
-        unsigned long long c2 = ld_acq(&J->claim);
-        if ((uint32_t)(c2 >> 32) != h + 1u)
-            continue;  // rewritten meanwhile: read again
-        if ((uint32_t)c2 >= ni) {
+        wait_mem();
+        const uint32_t ni = ld_rlx(&J->nitems);
+        if ((uint32_t)c1 >= ni) {  // exhausted: move the head on
             uint32_t e = h;
-            __hip_atomic_compare_exchange_strong(&st->job_head, &e, h + 1u, __ATOMIC_ACQ_REL,
-                                                 __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_compare_exchange_strong(&st->job_head, &e, h + 1u, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             continue;
         }
-        if (__hip_atomic_compare_exchange_strong(&J->claim, &c2, c2 + 1ull, __ATOMIC_ACQ_REL,
-                                                 __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) {
-            slot = sl;
-            phase = ph;
-            nitems = ni;
-            item = (uint32_t)c2;
-            return true;
-        }
+        const unsigned long long c = __hip_atomic_fetch_add(&J->claim, 1ull, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+        wait_mem();
+        const uint32_t seq = (uint32_t)(c >> 32);
+        if (seq == 0)
+            continue;  // being written: the publisher's final store replaces the add
+        // the job whose item this is (normally the one at h)
+        const uint32_t jn = ld_rlx(&J->nitems);
+        if ((uint32_t)c >= jn)
+            continue;  // exhausted meanwhile
+        slot = ld_rlx(&J->slot);
+        phase = ld_rlx(&J->phase);
+        nitems = jn;
+        item = (uint32_t)c;
+        return true;
     }
     return false;
 }
 
-// Copies new host descriptors into the slot table under the fetch lock (all
-// lanes copy, lane 0 publishes each request's first job).  Returns the number
-// of descriptors taken.
+// The fetcher wavefront (the kernel's first): copies new host descriptors
+// into the slot table (all lanes copy, lane 0 publishes each request's first
+// job) and mirrors the host's control word into device memory.  It is the
+// only wavefront that reads host memory.  Returns the descriptors taken.
 __device__ uint32_t fetch(SrvDev *st, SrvHost *host, SrvReq *slots, Job *jobs) {
     const int lane = threadIdx.x & 63;
-    uint32_t got = 0;
-    if (lane == 0) {
-        uint32_t z = 0;
-        got = __hip_atomic_compare_exchange_strong(&st->fetch_lock, &z, 1u, __ATOMIC_ACQUIRE,
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                  ? 1u
-                  : 0u;
-    }
-    if (!__builtin_amdgcn_readfirstlane(got))
-        return 0;
     uint32_t head = 0, tail = 0;
     if (lane == 0) {
-        head = ld_acq(&st->host_head);
-        tail = (uint32_t)__hip_atomic_load(&host->tail, __ATOMIC_ACQUIRE,
+        head = ld_rlx(&st->host_head);
+        // relaxed: the descriptor words are read after it (wait_mem below)
+        // with system-scope loads, which do not go through the caches
+        tail = (uint32_t)__hip_atomic_load(&host->tail, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint32_t ctl = __hip_atomic_load(&host->ctl, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_SYSTEM);
+        coherent_st(&st->ctl, ctl);
     }
     head = __builtin_amdgcn_readfirstlane(head);
     tail = __builtin_amdgcn_readfirstlane(tail);
+    wait_mem();
     uint32_t n = 0;
     for (uint32_t r = head; r != tail && n < 16; r++, n++) {
         SrvReq *hr = &host->ring[r % kMaxSlots];
@@ -204,28 +265,32 @@ __device__ uint32_t fetch(SrvDev *st, SrvHost *host, SrvReq *slots, Job *jobs) {
         const unsigned long long *src = (const unsigned long long *)hr;
         unsigned long long *dst = (unsigned long long *)&slots[sid];
         for (uint32_t w = lane; w < kReqWords; w += 64)
-            __hip_atomic_store(&dst[w],
-                               __hip_atomic_load(&src[w], __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_SYSTEM),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            coherent_st(&dst[w], __hip_atomic_load(&src[w], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_SYSTEM));
+        wait_mem();
         if (lane == 0) {
-            const uint32_t n = __hip_atomic_load(&hr->A.n, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_SYSTEM);
+            const uint32_t nn = __hip_atomic_load(&hr->A.n, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_SYSTEM);
             const uint32_t na = __hip_atomic_load(&hr->n_act, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_SYSTEM);
             const uint32_t ph = __hip_atomic_load(&hr->clear, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_SYSTEM)
                                     ? kPhClear
                                     : kPhMark;
-            publish(st, jobs, sid, ph, phase_items(n, na, ph, 0));
+            __hip_atomic_fetch_add(&st->live, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            publish(st, jobs, sid, ph, phase_items(nn, na, ph, 0));
         }
     }
-    if (lane == 0) {
-        __hip_atomic_store(&st->host_head, head + n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&st->fetch_lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (lane == 0 && n)
+        coherent_st(&st->host_head, head + n);
     return n;
+}
+
+// True while a published job may still have items (the head job is
+// published): the fetcher stays while there is work.
+__device__ __forceinline__ bool jobs_pending(SrvDev *st, Job *jobs) {
+    const uint32_t h = ld_rlx(&st->job_head);
+    return (uint32_t)(ld_rlx(&jobs[h % kJobCap].claim) >> 32) == h + 1u;
 }
 
 // ---- the work items -----------------------------------------------------------
@@ -234,7 +299,7 @@ __device__ __forceinline__ void item_clear(const SrvReq &R, uint32_t it) {
     const int lane = threadIdx.x & 63;
     const uint32_t n = R.A.n;
     for (uint32_t k = it * kSrvChunk + lane; k < min(n, (it + 1) * kSrvChunk); k += 64)
-        R.mark[k] = 0u;
+        coherent_st(R.mark + k, 0u);
 }
 
 __device__ __forceinline__ void item_mark(const SrvReq &R, uint32_t it) {
@@ -243,7 +308,7 @@ __device__ __forceinline__ void item_mark(const SrvReq &R, uint32_t it) {
     for (uint32_t k = it * kSrvChunk + lane; k < min(R.n_act, (it + 1) * kSrvChunk); k += 64) {
         const int32_t i = R.idx[k];
         if (i >= 0 && (uint32_t)i < n)
-            R.mark[R.rank[i]] = R.epoch;  // out-of-range indices: the output phase
+            coherent_st(R.mark + R.rank[i], R.epoch);  // out-of-range indices: the output phase
     }
 }
 
@@ -254,10 +319,10 @@ __device__ __forceinline__ void item_count(const SrvReq &R, uint32_t it) {
     uint32_t t = 0;
     for (uint32_t j = 0; j < kSrvTile; j += 64) {
         const uint32_t r = base + j + lane;
-        t += (uint32_t)__popcll(__ballot(r < n && R.mark[r] == R.epoch));
+        t += (uint32_t)__popcll(__ballot(r < n && coherent_ld(R.mark + r) == R.epoch));
     }
     if (lane == 0)
-        R.counts[it] = t;
+        coherent_st(R.counts + it, t);
 }
 
 // The tile's marked ranks in increasing order at their positions in the
@@ -269,7 +334,7 @@ __device__ __forceinline__ void item_compact(const SrvReq &R, uint32_t it) {
     const uint32_t nt = (n + kSrvTile - 1) / kSrvTile;
     uint32_t before = 0, all = 0;
     for (uint32_t q = lane; q < nt; q += 64) {
-        const uint32_t v = R.counts[q];
+        const uint32_t v = coherent_ld(R.counts + q);
         before += q < it ? v : 0u;
         all += v;
     }
@@ -278,17 +343,17 @@ __device__ __forceinline__ void item_compact(const SrvReq &R, uint32_t it) {
         all += __shfl_xor(all, o);
     }
     if (it == 0 && lane == 0)
-        *(uint32_t *)R.A.nuniq = all;
+        coherent_st((uint32_t *)R.A.nuniq, all);
     uint32_t pos = before;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     for (uint32_t j = 0; j < kSrvTile; j += 64) {
         const uint32_t r = base + j + lane;
-        const bool f = r < n && R.mark[r] == R.epoch;
+        const bool f = r < n && coherent_ld(R.mark + r) == R.epoch;
         const uint64_t m = __ballot(f);
         if (f) {
             const uint32_t p = pos + (uint32_t)__popcll(m & below);
-            ((uint32_t *)R.A.act)[p] = r;
-            R.slot[r] = p;
+            coherent_st((uint32_t *)R.A.act + p, r);
+            coherent_st(R.slot + r, p);
         }
         pos += (uint32_t)__popcll(m);
     }
@@ -320,9 +385,9 @@ __device__ __forceinline__ void srv_geometry(const SrvReq &R, uint32_t g, bool l
 }
 
 template <bool FP32>
-__device__ __forceinline__ void item_walk(const SrvReq &R, uint32_t g, IQ64 *Q) {
+__device__ __forceinline__ void item_walk(const SrvReq &R, uint32_t g, IQ64 *Q, bool rel) {
     const bool lanes = (R.variant & 4u) != 0;
-    const bool rel = (R.variant & 1u) != 0, mixed = (R.variant & 16u) != 0;
+    const bool mixed = (R.variant & 16u) != 0;
     if (rel) {
         if (mixed)
             srv_geometry<FP32, TPM_OPEN_REL, true>(R, g, lanes, Q);
@@ -336,33 +401,81 @@ __device__ __forceinline__ void item_walk(const SrvReq &R, uint32_t g, IQ64 *Q) 
     }
 }
 
-// Results in caller order (as the single-system output kernel).
+// Mesh force at the active slots (as the single-system interpolation kernel).
+template <typename T>
+__device__ __forceinline__ void item_pm(const SrvReq &R, uint32_t it, uint32_t nu) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t n = R.A.n;
+    T *res = (T *)R.res_pm;
+    for (uint32_t k = it * kSrvSlots + lane; k < min(nu, (it + 1) * kSrvSlots); k += 64) {
+        double F[3], P;
+        pmk::interp_at<T, true>(R.A.ps, n, coherent_ld(R.A.act + k), (const T *)R.phi, R.mg, F,
+                                P);
+        coherent_st(res + k, (T)F[0]);
+        coherent_st(res + n + k, (T)F[1]);
+        coherent_st(res + 2 * (size_t)n + k, (T)F[2]);
+    }
+}
+
+// |a| of the geometric pass plus the mesh force, into build order (as the
+// single-system |a| kernel: the sum and the norm in double).
+template <typename T>
+__device__ __forceinline__ void item_norm(const SrvReq &R, uint32_t it, uint32_t nu) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t n = R.A.n;
+    const T *a = (const T *)R.A.res, *b = (const T *)R.res_pm;
+    const bool mesh = (R.flags & kMesh) != 0;
+    for (uint32_t k = it * kSrvSlots + lane; k < min(nu, (it + 1) * kSrvSlots); k += 64) {
+        double v[3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            v[d] = (double)coherent_ld(a + (size_t)d * n + k);
+            if (mesh)
+                v[d] += (double)coherent_ld(b + (size_t)d * n + k);
+        }
+        coherent_st(R.anorm_out + R.A.perm[coherent_ld(R.A.act + k)],
+                    sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+    }
+}
+
+// Results in caller order (as the single-system output kernels).
 template <typename T>
 __device__ __forceinline__ void item_output(const SrvReq &R, uint32_t it) {
     const int lane = threadIdx.x & 63;
     const uint32_t n = R.A.n, na = R.n_act;
-    const T *res = (const T *)R.A.res;
-    T *acc = (T *)R.acc;
+    const T *res = (const T *)R.A.res, *rpm = (const T *)R.res_pm;
+    T *acc = (T *)R.acc, *apm = (T *)R.acc_pm;
+    const bool mesh = (R.flags & kMesh) != 0;
     for (uint32_t k = it * kSrvChunk + lane; k < min(na, (it + 1) * kSrvChunk); k += 64) {
         const int32_t i = R.idx[k];
+        T v[6] = {(T)NAN, (T)NAN, (T)NAN, (T)NAN, (T)NAN, (T)NAN};
+        uint32_t ni = 0xffffffffu;
         if (i < 0 || (uint32_t)i >= n) {
-            acc[k] = acc[na + k] = acc[2 * (size_t)na + k] = (T)NAN;
-            if (R.nint)
-                R.nint[k] = 0xffffffffu;
             atomicOr(R.err, 1u);
-            continue;
+        } else {
+            const uint32_t sl = coherent_ld(R.slot + R.rank[i]);
+            for (int d = 0; d < 3; d++)
+                v[d] = coherent_ld(res + (size_t)d * n + sl);
+            if (mesh)
+                for (int d = 0; d < 3; d++)
+                    v[3 + d] = coherent_ld(rpm + (size_t)d * n + sl);
+            if (R.nint)
+                ni = coherent_ld(R.A.rnint + sl);
         }
-        const uint32_t sl = R.slot[R.rank[i]];
-        acc[k] = res[sl];
-        acc[na + k] = res[n + sl];
-        acc[2 * (size_t)na + k] = res[2 * (size_t)n + sl];
+        // outputs written through to memory (other dies' caches are not
+        // written back for the host)
+        for (int d = 0; d < 3; d++)
+            out_st(acc + (size_t)d * na + k, v[d]);
+        if (mesh)
+            for (int d = 0; d < 3; d++)
+                out_st(apm + (size_t)d * na + k, v[3 + d]);
         if (R.nint)
-            R.nint[k] = R.A.rnint[sl];
+            out_st(R.nint + k, ni);
     }
 }
 
-// The FP64 instance inlines every walk variant and runs two wavefronts per
-// SIMD (up to 256 VGPRs, no spills); the FP32 instance runs four.
+// Both instances inline every walk variant; the FP64 one runs one wavefront
+// per SIMD (up to 256 VGPRs, no spills), the FP32 one three.
 template <bool FP32>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FP32 ? 4 : 2))) void k_server(
     SrvDev *st, SrvHost *host, SrvReq *slots, Job *jobs, unsigned long long idle_ticks) {
@@ -372,7 +485,46 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FP32 ? 4
         __shared__ IQ64 q[kBlock / 64];
         Q = &q[threadIdx.x >> 6];
     }
-    unsigned long long last = wall_clock64();
+    // per block: bumped when one of its wavefronts sees more items left, so
+    // its sleeping siblings wake up and claim (an LDS read, no memory traffic)
+    __shared__ uint32_t s_hint;
+    if (threadIdx.x == 0)
+        s_hint = 0u;
+    __syncthreads();
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the kernel's first wavefront only fetches requests from the host; it
+    // also decides, for the whole kernel, when the server has been idle
+    // (no request live, none fetched) for idle_ticks, and then tells every
+    // wavefront to leave.  (Wavefronts deciding that each for themselves would
+    // thin the server out under sparse arrivals.)
+    if (blockIdx.x == 0 && wv == 0) {
+        unsigned long long last = wall_clock64();
+        for (;;) {
+            const uint32_t got = fetch(st, host, slots, jobs);
+            uint32_t ctl = 0, busy = 0;
+            if (lane == 0) {
+                ctl = ld_rlx(&st->ctl);
+                busy = (ld_rlx(&st->live) != 0u || jobs_pending(st, jobs)) ? 1u : 0u;
+            }
+            if (__builtin_amdgcn_readfirstlane(ctl) != 0)
+                break;
+            if (got || __builtin_amdgcn_readfirstlane(busy)) {
+                last = wall_clock64();
+            } else if (wall_clock64() - last > idle_ticks) {
+                if (lane == 0)
+                    coherent_st(&st->ctl, 3u);
+                break;
+            }
+            if (got && lane == 0)
+                __hip_atomic_fetch_add(&s_hint, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __builtin_amdgcn_s_sleep(16);
+        }
+        return;
+    }
+    // one wavefront in every 24 blocks (a few per die) polls the job queue
+    // often; the others sleep on their block's hint and look themselves
+    // every ~30 us
+    const bool hot = wv == (blockIdx.x == 0 ? 1u : 0u) && (blockIdx.x % 24u) == 0;
     for (;;) {
         uint32_t has = 0, sid = 0, ph = 0, nitems = 0, item = 0;
         if (lane == 0)
@@ -381,17 +533,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FP32 ? 4
         if (!has) {
             uint32_t ctl = 0;
             if (lane == 0)
-                ctl = __hip_atomic_load(&host->ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            ctl = __builtin_amdgcn_readfirstlane(ctl);
-            if (ctl != 0)
-                break;  // stop or drain: every wavefront reaches this
-            if (fetch(st, host, slots, jobs))
-                continue;
-            if (wall_clock64() - last > idle_ticks)
-                break;  // idle: the host relaunches when work arrives
-            __builtin_amdgcn_s_sleep(8);
+                ctl = ld_rlx(&st->ctl);
+            if (__builtin_amdgcn_readfirstlane(ctl) != 0)
+                break;  // stop, drain or idle: every wavefront reaches this
+            if (hot) {
+                __builtin_amdgcn_s_sleep(64);  // ~2 us
+            } else {
+                const uint32_t seen = __hip_atomic_load(&s_hint, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+                for (int k = 0; k < 16; k++) {
+                    __builtin_amdgcn_s_sleep(64);
+                    if (__hip_atomic_load(&s_hint, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP) != seen)
+                        break;
+                }
+            }
             continue;
         }
+        if (lane == 0 && item + 1u < nitems)  // more left: wake the block
+            __hip_atomic_fetch_add(&s_hint, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         sid = __builtin_amdgcn_readfirstlane(sid);
         ph = __builtin_amdgcn_readfirstlane(ph);
         nitems = __builtin_amdgcn_readfirstlane(nitems);
@@ -401,44 +561,46 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FP32 ? 4
         // like kernel arguments)
         typedef __attribute__((address_space(4))) const SrvReq creq;
         const SrvReq &R = *(const SrvReq *)(const creq *)&slots[sid];
+        using T = typename std::conditional<FP32, float, double>::type;
         switch (ph) {
         case kPhClear: item_clear(R, item); break;
         case kPhMark: item_mark(R, item); break;
         case kPhCount: item_count(R, item); break;
         case kPhCompact: item_compact(R, item); break;
-        case kPhWalk: item_walk<FP32>(R, item, Q); break;
-        default:
-            if (FP32)
-                item_output<float>(R, item);
-            else
-                item_output<double>(R, item);
+        case kPhWalk:
+        case kPhWalk2:  // the request's own criterion; a step: geometric, then relative
+            item_walk<FP32>(R, item, Q,
+                            ph == kPhWalk2 || (!(R.flags & kStep) && (R.variant & 1u)));
             break;
+        case kPhPm: item_pm<T>(R, item, load_count(R.A.nuniq)); break;
+        case kPhNorm: item_norm<T>(R, item, load_count(R.A.nuniq)); break;
+        default: item_output<T>(R, item); break;
         }
-        __threadfence();
+        wait_mem();  // this item's stores are visible before it counts as done
         if (lane == 0) {
-            const uint32_t d = __hip_atomic_fetch_add(&st->done[sid], 1u, __ATOMIC_ACQ_REL,
+            const uint32_t d = __hip_atomic_fetch_add(&st->done[sid], 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
+            wait_mem();
             if (d + 1u == nitems) {  // this wavefront finished the phase
                 if (ph == kPhOutput) {
-                    __threadfence_system();
-                    __hip_atomic_store(&host->done[R.slot_id], R.ticket + 1ull,
-                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                    // every output item wrote through to memory and waited
+                    // for its stores before counting itself done
+                    out_st(&host->done[R.slot_id], R.ticket + 1ull);
+                    __hip_atomic_fetch_sub(&st->live, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                 } else {
-                    uint32_t nph = ph + 1u, nu = 0;
-                    if (nph == kPhWalk)
-                        nu = __hip_atomic_load(R.A.nuniq, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                    uint32_t cnt = phase_items(R.A.n, R.n_act, nph, nu);
-                    if (nph == kPhWalk && cnt == 0) {  // nothing to walk
-                        nph = kPhOutput;
-                        cnt = phase_items(R.A.n, R.n_act, nph, 0);
-                    }
-                    publish(st, jobs, sid, nph, cnt);
+                    uint32_t nph = next_phase(ph, R.flags), nu = 0;
+                    if (nph >= kPhWalk)
+                        nu = coherent_ld(R.A.nuniq);
+                    if (nph >= kPhWalk && nph != kPhOutput && nu == 0)
+                        nph = kPhOutput;  // no valid target: only the outputs remain
+                    publish(st, jobs, sid, nph, phase_items(R.A.n, R.n_act, nph, nu));
+                    __hip_atomic_fetch_add(&s_hint, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
         }
         wave_sync();
-        last = wall_clock64();
     }
 }
 
@@ -490,6 +652,8 @@ int sfail(tpm_server *s, int code, const std::string &m) {
 int launch(tpm_server *s) {
     s->host->ctl = 0;
     std::atomic_thread_fence(std::memory_order_seq_cst);
+    // the device mirror of the control word starts at "run"
+    SHIP(s, hipMemsetAsync(&s->dev->ctl, 0, sizeof(uint32_t), s->stream));
     if (s->precision == TPM_FP32)
         k_server<true><<<s->blocks, kBlock, 0, s->stream>>>(s->dev, s->host_dev, s->slots,
                                                             s->jobs, s->idle_ticks);
@@ -551,9 +715,11 @@ int tpm_server_create(int32_t precision, double idle_ms, tpm_server **out) {
         hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, s->device) !=
             hipSuccess)
         rc = TPM_EDEVICE;
-    // FP32 (85 VGPRs): four wavefronts per SIMD; FP64 (165 VGPRs): one; the
-    // two servers then fit in a SIMD's registers beside each other
-    s->blocks = cus * (precision == TPM_FP32 ? 4 : 1);
+    // FP32 (about 110 VGPRs): three wavefronts per SIMD; FP64 (about 170):
+    // one.  The two servers then fit in a SIMD's registers beside each other;
+    // kernels of other work (builds of newly admitted systems) run when the
+    // servers drain or idle.
+    s->blocks = cus * (precision == TPM_FP32 ? 3 : 1);
     if (clock_khz <= 0)
         clock_khz = 100000;  // the usual 100 MHz constant clock
     s->idle_ticks = (unsigned long long)(idle_ms * (double)clock_khz);
@@ -613,9 +779,11 @@ int tpm_server_destroy(tpm_server *s) {
 
 const char *tpm_server_last_error(const tpm_server *s) { return s ? s->err.c_str() : "NULL server"; }
 
-int tpm_server_submit(tpm_server *s, tpm_ctx *c, int32_t opening, int64_t n_act,
-                      const int32_t *idx, const double *anorm, void *acc, uint32_t *nint,
-                      uint64_t *ticket) {
+namespace {
+
+int submit_impl(tpm_server *s, tpm_ctx *c, bool step, int32_t opening, int64_t n_act,
+                const int32_t *idx, const double *anorm, void *acc, void *acc_pm,
+                uint32_t *nint, uint64_t *ticket) {
     if (!s || !c || !ticket)
         return TPM_EINVAL;
     *ticket = 0;
@@ -623,12 +791,15 @@ int tpm_server_submit(tpm_server *s, tpm_ctx *c, int32_t opening, int64_t n_act,
         return sfail(s, TPM_ESTATE, "submit before build_tree");
     if (c->P.precision != s->precision)
         return sfail(s, TPM_EINVAL, "context precision differs from the server's");
-    if (opening != TPM_OPEN_BH && opening != TPM_OPEN_REL)
+    if (!step && opening != TPM_OPEN_BH && opening != TPM_OPEN_REL)
         return sfail(s, TPM_EINVAL, "opening must be TPM_OPEN_BH or TPM_OPEN_REL");
     if (n_act < 1 || n_act > (int64_t(1) << 31) - 1 || !idx || !acc)
         return sfail(s, TPM_EINVAL, "n_act must be >= 1 with active_idx and acc");
-    if (opening == TPM_OPEN_REL && !anorm)
+    if (!step && opening == TPM_OPEN_REL && !anorm)
         return sfail(s, TPM_EINVAL, "the relative criterion needs a_old_norm");
+    const bool mesh = step && c->P.pm_grid > 0;
+    if (mesh != (acc_pm != nullptr))
+        return sfail(s, TPM_EINVAL, "acc_pm is required exactly when the step has a mesh");
     if (c->device != s->device)
         return sfail(s, TPM_EINVAL, "context on another device");
     for (int k = 0; k < kMaxSlots; k++)
@@ -640,6 +811,17 @@ int tpm_server_submit(tpm_server *s, tpm_ctx *c, int32_t opening, int64_t n_act,
     // complete before the request is published
     Work w;
     TPM_TRY(work_of_ctx(c, true, w));
+    const size_t esz = c->P.precision == TPM_FP32 ? 4 : 8;
+    if (step) {
+        TPM_TRY(ensure(c, c->srv_an, (size_t)c->n * 8));
+        if (mesh) {
+            TPM_TRY(ensure(c, c->srv_pm, (size_t)3 * c->n * esz));
+            if (!c->pm_ready) {
+                TPM_TRY(pm_solve(c));
+                c->pm_ready = 1;
+            }
+        }
+    }
     TPM_HIP(c, hipStreamSynchronize(c->stream));
     // trees are read through the scalar cache: after any rebuild or free
     // since the running kernel started, drain it and launch it again
@@ -651,7 +833,7 @@ int tpm_server_submit(tpm_server *s, tpm_ctx *c, int32_t opening, int64_t n_act,
     const int sid = s->free_slots.back();
     s->free_slots.pop_back();
     SrvReq R{};
-    wk::fill_args(c, anorm, w, R.A);
+    wk::fill_args(c, step ? (const double *)c->srv_an.p : anorm, w, R.A);
     R.idx = idx;
     R.rank = (const int32_t *)c->rank.p;
     R.mark = w.mark;
@@ -666,6 +848,14 @@ int tpm_server_submit(tpm_server *s, tpm_ctx *c, int32_t opening, int64_t n_act,
     R.variant = (opening == TPM_OPEN_REL ? 1u : 0u) | (c->P.pm_grid > 0 ? 2u : 0u) |
                 (wk::use_lanes(c, n_act) ? 4u : 0u) | (c->P.periodic ? 8u : 0u) |
                 (c->mixed ? 16u : 0u);
+    R.flags = (step ? kStep : 0u) | (mesh ? kMesh : 0u);
+    if (mesh) {
+        R.mg = pmk::mesh_geom(c);
+        R.phi = c->mesh_phi.p;
+        R.res_pm = c->srv_pm.p;
+        R.acc_pm = acc_pm;
+    }
+    R.anorm_out = step ? (double *)c->srv_an.p : nullptr;
     R.ticket = s->next_ticket++;
     R.slot_id = (uint32_t)sid;
     R.desc = (uint32_t)(R.ticket % kDescRing);
@@ -679,6 +869,20 @@ int tpm_server_submit(tpm_server *s, tpm_ctx *c, int32_t opening, int64_t n_act,
         TPM_TRY(launch(s));
     *ticket = R.ticket;
     return TPM_OK;
+}
+
+}  // namespace
+
+int tpm_server_submit(tpm_server *s, tpm_ctx *c, int32_t opening, int64_t n_act,
+                      const int32_t *idx, const double *anorm, void *acc, uint32_t *nint,
+                      uint64_t *ticket) {
+    return submit_impl(s, c, false, opening, n_act, idx, anorm, acc, nullptr, nint, ticket);
+}
+
+int tpm_server_submit_step(tpm_server *s, tpm_ctx *c, int64_t n_act, const int32_t *idx,
+                           void *acc, void *acc_pm, uint32_t *nint, uint64_t *ticket) {
+    return submit_impl(s, c, true, TPM_OPEN_REL, n_act, idx, nullptr, acc, acc_pm, nint,
+                       ticket);
 }
 
 // 1: the request finished (outputs complete and visible); 0: pending.

@@ -96,6 +96,7 @@ struct tpm_ctx {
     tpm::DBuf pe;               // rank -> entry
     tpm::DBuf mark, act, slot, counters;
     tpm::DBuf res, rpot, rnint; // walk results in slot order
+    tpm::DBuf srv_pm, srv_an;   // resident server steps: mesh force (slot order), |a|
     tpm::DBuf err_flag;         // [0] bad active index, [1] bad softening length
     // individual softening (Sec. 3.2): spline supports per particle in curve
     // order, and per entry the largest of its particles (FP64, FP32 copy)

@@ -276,6 +276,19 @@ struct IQ64 {
     uint64_t step[kRing];
 };
 
+// Device-coherent accesses (relaxed device-scope atomics: they bypass the
+// caches that are not coherent across the chip's dies) for the data one
+// phase of the resident serving loop hands to the next: the active slots,
+// |a| and the walk results.  Single-system launches use the same code.
+template <typename T>
+__device__ __forceinline__ T coherent_ld(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void coherent_st(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The number of unique active targets, written by an earlier kernel or, in
 // the resident server, by another wavefront of the same kernel: read with a
 // coherent vector load (never through the scalar cache) and made uniform.
@@ -358,12 +371,12 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave, I
         return;  // whole wavefront
     const uint32_t slot = wave * 64u + lane;
     const bool valid = slot < nu;
-    const uint32_t s = A.act[valid ? slot : wave * 64u];
+    const uint32_t s = coherent_ld(A.act + (valid ? slot : wave * 64u));
     const double x0 = A.ps[s], x1 = A.ps[A.n + s], x2 = A.ps[2 * (size_t)A.n + s];
     const uint32_t self = A.pe[s];
     double an = 0.0;
     if (OPEN == TPM_OPEN_REL)
-        an = A.anorm[A.perm[s]];
+        an = coherent_ld(A.anorm + A.perm[s]);
     const double alpha_an = A.alpha * an;
     const double hi = MIXED ? A.hs[s] : 0.0;  // the target's own support
     // the lane's walk stands at the cursor when next <= cursor (next moves
@@ -602,12 +615,12 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave, I
         flush(qn, ns);
     if (valid) {
         double *res = (double *)A.res;
-        res[slot] = a0;
-        res[A.n + slot] = a1;
-        res[2 * (size_t)A.n + slot] = a2;
+        coherent_st(res + slot, a0);
+        coherent_st(res + A.n + slot, a1);
+        coherent_st(res + 2 * (size_t)A.n + slot, a2);
         if (POT)
-            ((double *)A.rpot)[slot] = pot;
-        A.rnint[slot] = nint;
+            coherent_st((double *)A.rpot + slot, pot);
+        coherent_st(A.rnint + slot, nint);
     }
 }
 
@@ -758,7 +771,7 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
         return;
     const uint32_t slot = wave * 64u + lane;
     const bool valid = slot < nu;
-    const uint32_t s = A.act[valid ? slot : wave * 64u];
+    const uint32_t s = coherent_ld(A.act + (valid ? slot : wave * 64u));
     // own depth-21 cell centre (integer, shifted like the records) and the
     // float offset of the particle from it
     const uint64_t qq = A.qs[s];
@@ -776,7 +789,7 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     const uint32_t self = A.pe[s];
     float an = 0.0f;
     if (OPEN == TPM_OPEN_REL)
-        an = (float)A.anorm[A.perm[s]];
+        an = (float)coherent_ld(A.anorm + A.perm[s]);
     const float alpha_an = A.falpha * an;
     const float hi = MIXED ? (float)A.hs[s] : 0.0f;
     // A lane's walk stands at the cursor when next <= cursor: next is only
@@ -923,12 +936,12 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
     }
     if (valid) {
         float *res = (float *)A.res;
-        res[slot] = a0;
-        res[A.n + slot] = a1;
-        res[2 * (size_t)A.n + slot] = a2;
+        coherent_st(res + slot, a0);
+        coherent_st(res + A.n + slot, a1);
+        coherent_st(res + 2 * (size_t)A.n + slot, a2);
         if (POT)
-            ((float *)A.rpot)[slot] = pot;
-        A.rnint[slot] = nint;
+            coherent_st((float *)A.rpot + slot, pot);
+        coherent_st(A.rnint + slot, nint);
     }
 }
 
@@ -971,13 +984,13 @@ __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, u
            hi = 0.0;
     uint32_t self = 0, nint = 0, e = 0;
     auto start = [&](uint32_t sl) {
-        const uint32_t s = A.act[sl];
+        const uint32_t s = coherent_ld(A.act + sl);
         x0 = A.ps[s];
         x1 = A.ps[A.n + s];
         x2 = A.ps[2 * (size_t)A.n + s];
         self = A.pe[s];
         if (OPEN == TPM_OPEN_REL)
-            an = A.anorm[A.perm[s]];
+            an = coherent_ld(A.anorm + A.perm[s]);
         if (MIXED)
             hi = A.hs[s];
         a0 = a1 = a2 = pot = 0.0;
@@ -1035,12 +1048,12 @@ __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, u
             e = step_in ? e + 1u : r.skip;
             if (e >= A.E) {
                 double *res = (double *)A.res;
-                res[slot] = a0;
-                res[A.n + slot] = a1;
-                res[2 * (size_t)A.n + slot] = a2;
+                coherent_st(res + slot, a0);
+                coherent_st(res + A.n + slot, a1);
+                coherent_st(res + 2 * (size_t)A.n + slot, a2);
                 if (POT)
-                    ((double *)A.rpot)[slot] = pot;
-                A.rnint[slot] = nint;
+                    coherent_st((double *)A.rpot + slot, pot);
+                coherent_st(A.rnint + slot, nint);
                 slot += 64u;
                 live = slot < chunk_end;
                 if (live)
@@ -1068,7 +1081,7 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
           pot = 0.f, hi = 0.f;
     uint32_t self = 0, nint = 0, e = 0;
     auto start = [&](uint32_t sl) {
-        const uint32_t s = A.act[sl];
+        const uint32_t s = coherent_ld(A.act + sl);
         const uint64_t qq = A.qs[s];
         const uint32_t q0 = (uint32_t)(qq >> 42) & 0x1fffffu,
                        q1 = (uint32_t)(qq >> 21) & 0x1fffffu, q2 = (uint32_t)qq & 0x1fffffu;
@@ -1081,7 +1094,7 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
         self = A.pe[s];
         alpha_an = 0.f;
         if (OPEN == TPM_OPEN_REL)
-            alpha_an = A.falpha * (float)A.anorm[A.perm[s]];
+            alpha_an = A.falpha * (float)coherent_ld(A.anorm + A.perm[s]);
         if (MIXED)
             hi = (float)A.hs[s];
         a0 = a1 = a2 = pot = 0.f;
@@ -1129,12 +1142,12 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
             e = (part || open) ? e + 1u : r.skip;
             if (e >= A.E) {
                 float *res = (float *)A.res;
-                res[slot] = a0;
-                res[A.n + slot] = a1;
-                res[2 * (size_t)A.n + slot] = a2;
+                coherent_st(res + slot, a0);
+                coherent_st(res + A.n + slot, a1);
+                coherent_st(res + 2 * (size_t)A.n + slot, a2);
                 if (POT)
-                    ((float *)A.rpot)[slot] = pot;
-                A.rnint[slot] = nint;
+                    coherent_st((float *)A.rpot + slot, pot);
+                coherent_st(A.rnint + slot, nint);
                 slot += 64u;
                 live = slot < chunk_end;
                 if (live)

@@ -12,12 +12,12 @@ kernel and its work items interleave with theirs.  This module schedules:
   estimate (``tpm_bytes_needed``) fits the HBM budget, evicting idle systems
   least recently used; otherwise the request waits; a system that can never
   fit is rejected;
-* stages -- isolated systems with the relative criterion and periodic
-  systems take two passes as in the paper's first force computation
-  (Sec. 3.1): geometric criterion (plus PM long range for periodic boxes),
-  then the relative criterion with |a| of the first pass; Plummer systems
-  take the geometric pass only.  One request per system is in flight; the
-  PM interpolation and |a| run on the system's own stream;
+* one request, one submission -- isolated systems with the relative
+  criterion and periodic systems take the paper's first force computation
+  (Sec. 3.1) as one device-side request (``submit_step``: geometric pass,
+  the mesh force for periodic boxes, |a| of their sum, relative pass);
+  Plummer systems take the geometric pass only.  One request per system is
+  in flight; others wait in the system's queue;
 * latency = host time at which completion is observed - arrival time.
 
 All force arithmetic runs in the library's kernels; this module only
@@ -72,13 +72,10 @@ class Job:
     req: W.Request
     key: tuple
     idx: torch.Tensor
-    stage: int = 0
-    state: str = "new"      # new, queued, walking, norm, done, rejected
+    state: str = "new"      # new, queued, walking, done, rejected
     ticket: int = 0
     acc: torch.Tensor | None = None
     acc_pm: torch.Tensor | None = None
-    anorm: torch.Tensor | None = None
-    norm_event: torch.cuda.Event | None = None
     done_s: float = math.nan
     waited: bool = False
 
@@ -181,51 +178,31 @@ class Server:
         stats.builds += 1
         return True
 
-    # -- request stages --------------------------------------------------------
+    # -- requests -------------------------------------------------------------
     def _start(self, j: Job, r: Resident):
-        """Submit the job's next walk (and the first stage's PM interpolation)."""
+        """Submit the job to the running kernel of its precision."""
         loop = self.loops[j.req.precision]
-        dt = r.ctx.dtype
-        if j.stage == 0:
-            j.ticket, j.acc = loop.submit(r.ctx, j.idx, "bh",
-                                          acc=torch.empty((3, j.idx.numel()), dtype=dt,
-                                                          device=self.dev))
-            if r.periodic:  # the mesh part, on the system's stream meanwhile
-                with torch.cuda.stream(r.stream):
-                    j.acc_pm, _ = r.ctx.pm_long_range(j.idx, want_pot=False)
+        if len(r.stages) > 1:
+            j.ticket, j.acc, j.acc_pm = loop.submit_step(r.ctx, j.idx)
         else:
-            j.ticket, j.acc = loop.submit(r.ctx, j.idx, r.stages[j.stage], a_old_norm=j.anorm,
-                                          acc=torch.empty((3, j.idx.numel()), dtype=dt,
-                                                          device=self.dev))
+            j.ticket, j.acc = loop.submit(r.ctx, j.idx, "bh")
         j.state = "walking"
 
     def _advance(self, j: Job, r: Resident, now: float) -> bool:
-        """Move a job on; True when it finished."""
-        loop = self.loops[j.req.precision]
-        if j.state == "walking":
-            if not loop.poll(j.ticket):
-                return False
-            j.stage += 1
-            if j.stage >= len(r.stages):
-                j.state = "done"
-                j.done_s = now
-                return True
-            # |a| of the first pass (tree + PM) for the relative criterion
-            with torch.cuda.stream(r.stream):
-                j.anorm = torch.zeros(r.ctx.n, dtype=torch.float64, device=self.dev)
-                r.ctx.accel_norm(j.idx, j.acc, j.acc_pm, out=j.anorm)
-                j.norm_event = torch.cuda.Event()
-                j.norm_event.record(r.stream)
-            j.state = "norm"
-            return False
-        if j.state == "norm" and j.norm_event.query():
-            self._start(j, r)
+        """True when the job finished."""
+        if self.loops[j.req.precision].poll(j.ticket):
+            j.state = "done"
+            j.done_s = now
+            return True
         return False
 
     # -- the loop ---------------------------------------------------------------
-    def run(self, requests):
+    def run(self, requests, progress=None, stall_s: float = 60.0):
         """Serve ``requests`` (arrival times in seconds) and return (Stats,
-        jobs).  Active subsets are drawn and uploaded beforehand."""
+        jobs).  Active subsets are drawn and uploaded beforehand.  progress, if
+        given, is called with (finished, total) about every 5 s; a run in which
+        nothing finishes for stall_s seconds while requests are in flight
+        raises RuntimeError naming them."""
         stats = Stats()
         jobs = []
         for sid in sorted({rq.sid for rq in requests}):
@@ -240,8 +217,17 @@ class Server:
         waiting = []        # arrived, not admitted (memory)
         finished = 0
         t0 = time.perf_counter()
+        last_done, last_report = 0.0, 0.0
         while finished < len(jobs):
             now = time.perf_counter() - t0
+            if progress is not None and now - last_report > 5.0:
+                progress(finished, len(jobs))
+                last_report = now
+            if now - last_done > stall_s:
+                flying = [(r.key, r.active.ticket) for r in self.resident.values()
+                          if r.active is not None]
+                raise RuntimeError(f"no request finished for {stall_s} s; in flight: {flying}")
+            before = finished
             # arrivals
             while pending and pending[0].req.t_arrival <= now:
                 waiting.append(pending.popleft())
@@ -268,6 +254,8 @@ class Server:
                     r.active = r.queue.popleft()
                     self._start(r.active, r)
                     busy = True
+            if finished != before or (not busy and not waiting):
+                last_done = now
             if not busy and not waiting:
                 time.sleep(5e-5)
         torch.cuda.synchronize()

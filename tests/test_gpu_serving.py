@@ -139,6 +139,48 @@ def test_resident_alone_equals_mix_equals_single():
         lp.close()
 
 
+def test_resident_step_equals_single_system_sequence():
+    """One step request (geometric pass, mesh force, |a|, relative pass) run
+    inside the resident kernel equals the four single-system calls in
+    sequence, bit for bit: periodic boxes and isolated systems with and
+    without a mesh, both precisions, several at once."""
+    from paper_1909_04667_amd import binding as B
+    cases = [(W.zeldovich_box(16, 100.0, 31), dict(periodic=True, box_size=100.0, pm_grid=32,
+                                                   eps=100.0 / 800), 1.0),
+             (W.lognormal_box(16, 100.0, 32), dict(periodic=True, box_size=100.0, pm_grid=64,
+                                                   eps=100.0 / 800), 0.3),
+             (W.hernquist(1 << 14, 33), dict(eps=0.005), 0.5),
+             (W.hernquist(1 << 13, 34), dict(eps=0.005, pm_grid=32), 1.0)]
+    for prec in ("fp64", "fp32"):
+        lp = B.ResidentServer(prec)
+        subs, refs = [], []
+        for p, kw, f in cases:
+            ctx = B.Context(precision=prec, **kw)
+            t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=_dev())
+            ctx.build_tree(t(p.x), t(p.y), t(p.z))
+            rng = np.random.default_rng(5)
+            ids = rng.choice(p.n, max(1, int(f * p.n)), replace=False).astype(np.int32)
+            ix = torch.as_tensor(ids, device=_dev())
+            a, _ = ctx.compute_forces(ix, "bh")
+            apm = ctx.pm_long_range(ix)[0] if kw.get("pm_grid") else None
+            an = ctx.accel_norm(ix, a, apm)
+            n_ref = torch.empty(ids.size, dtype=torch.int32, device=_dev())
+            ar, _ = ctx.compute_forces(ix, "rel", a_old_norm=an, n_interactions=n_ref)
+            refs.append((ar.cpu(), None if apm is None else apm.cpu(), n_ref.cpu()))
+            torch.cuda.synchronize()
+            n = torch.zeros(ids.size, dtype=torch.int32, device=_dev())
+            subs.append((ctx, n) + lp.submit_step(ctx, ix, n_interactions=n))
+        for (ctx, n, tk, acc, acc_pm), (ar, apm, n_ref) in zip(subs, refs):
+            lp.wait(tk)
+            ctx.check()
+            assert torch.equal(acc.cpu(), ar), prec
+            assert (apm is None) == (acc_pm is None)
+            if apm is not None:
+                assert torch.equal(acc_pm.cpu(), apm), prec
+            assert torch.equal(n.cpu(), n_ref), prec
+        lp.close()
+
+
 def test_resident_requests_join_the_running_kernel():
     """A large request keeps the kernel busy; requests submitted meanwhile
     are taken up by the same launch, and a context rebuilt meanwhile is
