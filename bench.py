@@ -241,35 +241,66 @@ def run_mixed_softening(steps, warmup):
 
 
 def run_integrators():
-    """Sec. 7.2-7.3 on a 2^18 Hernquist sphere: one longest step dt_max of the
-    block-step leapfrog and of the split-Hamiltonian integration, FP32 walks,
-    time-step parameter C = 0.025 with six bins."""
+    """Sec. 7.2-7.3, one longest step dt_max of the block-step leapfrog and of
+    the split-Hamiltonian integration, FP32 walks, six bins:
+    * a 2^18 Hernquist sphere (tree forces), C = 0.025;
+    * a clustered periodic box (64^3 particles, lognormal density, TreePM with a
+      128^3 mesh), where block steps rebuild the tree and solve the mesh at
+      every sync point while the split solves the mesh twice per longest step
+      and builds trees over the fast parts only; dt_max is set so that half
+      of the particles ask for a shorter step than dt_max (C = 0.025)."""
     import numpy as np
     import torch
+    from paper_1909_04667_amd import binding as B
     from paper_1909_04667_amd import integrate as GI
     from paper_1909_04667_amd import workloads as W
-    p = W.hernquist(1 << 18, 31)
     dev = torch.device("cuda:0")
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
-    rng = np.random.default_rng(32)
-    r = np.sqrt(p.x ** 2 + p.y ** 2 + p.z ** 2)
-    vc = np.sqrt(r) / (1.0 + r)  # circular speed of a Hernquist sphere (G = M = a = 1)
-    v = rng.normal(0.0, 1.0, (3, p.n)) * (vc / np.sqrt(3.0))
-    out = {"workload": "hernquist_2p18_kdk", "n_particles": p.n, "C": 0.025,
-           "dt_max": 0.05, "max_bin": 6}
-    for name, cls in (("block_leapfrog", GI.BlockLeapfrog), ("hierarchical", GI.Hierarchical)):
-        integ = cls((t(p.x), t(p.y), t(p.z)), (t(v[0]), t(v[1]), t(v[2])), C=0.025,
-                    dt_max=0.05, max_bin=6, precision="fp32", eps=0.005)
+
+    def one(name, cls, p, v, **kw):
+        integ = cls((t(p.x), t(p.y), t(p.z)), (t(v[0]), t(v[1]), t(v[2])), **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = integ.run(1)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        occ = np.bincount(integ.bins.cpu().numpy(), minlength=7).tolist()
-        out[name] = {"wall_ms": wall * 1e3, "force_evals": st["force_evals"],
-                     "force_evals_per_s": st["force_evals"] / wall, "final_bins": occ,
-                     **{k: v for k, v in st.items() if k != "force_evals"}}
+        occ = np.bincount(integ.bins.cpu().numpy(), minlength=kw["max_bin"] + 1).tolist()
         integ.ctx.close()
+        return {"wall_ms": wall * 1e3, "force_evals": st["force_evals"],
+                "force_evals_per_s": st["force_evals"] / wall, "final_bins": occ,
+                **{k: v for k, v in st.items() if k != "force_evals"}}
+
+    p = W.hernquist(1 << 18, 31)
+    rng = np.random.default_rng(32)
+    r = np.sqrt(p.x ** 2 + p.y ** 2 + p.z ** 2)
+    vc = np.sqrt(r) / (1.0 + r)  # circular speed of a Hernquist sphere (G = M = a = 1)
+    v = rng.normal(0.0, 1.0, (3, p.n)) * (vc / np.sqrt(3.0))
+    out = {"hernquist_2p18_kdk": {"n_particles": p.n, "C": 0.025, "dt_max": 0.05,
+                                  "max_bin": 6}}
+    for name, cls in (("block_leapfrog", GI.BlockLeapfrog), ("hierarchical", GI.Hierarchical)):
+        out["hernquist_2p18_kdk"][name] = one(name, cls, p, v, C=0.025, dt_max=0.05, max_bin=6,
+                                              precision="fp32", eps=0.005)
+    # clustered periodic box with the mesh
+    box, ng = 100.0, 128
+    p = W.lognormal_box(64, box, 33)
+    eps = box / (50 * 64)
+    kw = dict(precision="fp32", eps=eps, periodic=True, box_size=box, pm_grid=ng)
+    ctx = B.Context(**kw)
+    ctx.build_tree(t(p.x), t(p.y), t(p.z))
+    idx = torch.arange(p.n, dtype=torch.int32, device=dev)
+    a, _ = ctx.compute_forces(idx, "bh")
+    apm, _ = ctx.pm_long_range(idx)
+    an = (a.double() + apm.double()).norm(dim=0).cpu().numpy()
+    ctx.close()
+    C = 0.025
+    dt_max = float(np.median(np.sqrt(2.0 * C * eps / an)))
+    v = np.random.default_rng(34).normal(0.0, 1.0, (3, p.n)) * (0.02 * box / dt_max)
+    wl = {"n_particles": p.n, "pm_grid": ng, "C": C, "dt_max": dt_max, "max_bin": 6}
+    for name, cls in (("block_leapfrog", GI.BlockLeapfrog), ("hierarchical", GI.Hierarchical)):
+        wl[name] = one(name, cls, p, v, C=C, dt_max=dt_max, max_bin=6, **kw)
+    wl["hierarchical_wall_vs_block"] = wl["hierarchical"]["wall_ms"] / \
+        wl["block_leapfrog"]["wall_ms"]
+    out["lognormal_64c_pm128_kdk"] = wl
     return out
 
 

@@ -140,6 +140,17 @@ int tpm_build_tree(tpm_ctx *ctx, int64_t n, const double *x, const double *y,
 int tpm_build_tree_eps(tpm_ctx *ctx, int64_t n, const double *x, const double *y,
                        const double *z, const double *mass, const double *eps);
 
+/* Random placement of the tree domain (Sec. 3.1: each tree construction
+ * places the root anew so that force errors decorrelate in time; a periodic
+ * box is shifted as a whole by a new random vector).  shift: host double[3],
+ * each in [0, 1): non-periodic, the fraction of the root cube's slack below
+ * the particles' minimum along each axis; periodic, the shift of the box
+ * origin as a fraction of box_size.  The caller draws the numbers; they apply
+ * to every build that follows (the initial value is params.shift) and leave
+ * the current tree and a cached mesh unchanged.  TPM_EINVAL for a value
+ * outside [0, 1) or NaN (the setting is then unchanged). */
+int tpm_set_shift(tpm_ctx *ctx, const double *shift);
+
 /* Tree force on the active particles (Sec. 3.1, 3.2, 3.4).
  * opening:     TPM_OPEN_BH or TPM_OPEN_REL.
  * n_act:       number of active particles (>= 0).

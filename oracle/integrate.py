@@ -19,6 +19,11 @@ the oracle's force routines, shares nothing with the HIP path).
   Bins are assigned at the start of every dt_max step from the full force and
   kept over that step.  The mutual forces are the difference of the forces of
   P and of the part itself, so every level needs forces among P, S and F only.
+  With a mesh (TreePM, Sec. 3.3) the split applies to the short-range
+  Hamiltonian: each dt_max step is K_long(dt/2) [the split integration of
+  T + V_short] K_long(dt/2), the long-range kicks taking the mesh force of
+  all particles from all of them at the step's start and end (the mesh part
+  moves on the longest step), and the bins come from |a_short + a_long|.
 
 Arithmetic: a kick is v + a * dt per component with dt = 0.5 * dt_max *
 2^-b, a drift is x + v * dt with dt = ticks * dt_max / 2^max_bin (products
@@ -128,10 +133,13 @@ def leapfrog_bins(x, v, force, *, eps, C, dt_max, max_bin, n_max_steps, box=0.0,
     return x, v, {"force_evals": nforce, "final_bins": bins}
 
 
-def hierarchical(x, v, force_sub, *, eps, C, dt_max, max_bin, n_max_steps, box=0.0):
+def hierarchical(x, v, force_sub, *, eps, C, dt_max, max_bin, n_max_steps, box=0.0,
+                 force_long=None):
     """The split-Hamiltonian integration (Sec. 7.3).  force_sub(x, members)
     -> acc [3, len(members)] of the members from the members only (a tree or
-    sum over that subset).  Returns x, v and statistics."""
+    sum over that subset; the short-range force when there is a mesh).
+    force_long(x) -> acc [3, n], the mesh force of all particles, or None.
+    Returns x, v and statistics."""
     x = np.array(x, np.float64)
     v = np.array(v, np.float64)
     n = x.shape[1]
@@ -181,6 +189,14 @@ def hierarchical(x, v, force_sub, *, eps, C, dt_max, max_bin, n_max_steps, box=0
     everyone = np.arange(n)
     for _ in range(n_max_steps):
         a = forces(everyone)
-        bins = bin_of(norm3(a), eps, C, dt_max, max_bin)
+        if force_long is None:
+            bins = bin_of(norm3(a), eps, C, dt_max, max_bin)
+        else:
+            a_long = force_long(x)
+            bins = bin_of(norm3(a + a_long), eps, C, dt_max, max_bin)
+            if MUTATION != 3:  # mutation 3: the opening long-range kick is lost
+                kick(v, everyone, a_long, 0.5 * dt_max)
         level(everyone, 0, bins, dt_max)
+        if force_long is not None:
+            kick(v, everyone, force_long(x), 0.5 * dt_max)
     return x, v, stats

@@ -60,6 +60,7 @@ def lib():
         L.tpm_build_tree_eps.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         L.tpm_compute_forces.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp]
         L.tpm_pm_long_range.argtypes = [vp, i64, vp, vp, vp]
+        L.tpm_set_shift.argtypes = [vp, P(d)]
         L.tpm_compute_forces_noalloc.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp]
         L.tpm_noalloc_max_n.restype = i64
         L.tpm_check.argtypes = [vp]
@@ -199,6 +200,12 @@ class Context:
         self._rc(lib().tpm_set_stream(self.h, _stream_handle(stream)))
 
     # -- the three operations of the hot path ---------------------------------
+    def set_shift(self, shift):
+        """Root placement for the builds that follow (three numbers in [0, 1),
+        drawn by the caller)."""
+        arr = (C.c_double * 3)(*[float(v) for v in shift])
+        self._rc(lib().tpm_set_shift(self.h, arr))
+
     def build_tree(self, x, y, z, mass=None, eps=None):
         """eps: optional individual softening lengths (float64, build order)."""
         extra = tuple(t for t in (mass, eps) if t is not None)

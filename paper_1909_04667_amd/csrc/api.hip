@@ -357,6 +357,19 @@ int tpm_accel_norm(tpm_ctx *c, int64_t n_act, const int32_t *idx, const void *a,
     return accel_norm(c, n_act, idx, a, b, out);
 }
 
+int tpm_set_shift(tpm_ctx *c, const double *shift) {
+    if (!c)
+        return TPM_EINVAL;
+    if (!shift)
+        return fail(c, TPM_EINVAL, "shift must not be NULL");
+    for (int a = 0; a < 3; a++)
+        if (!(shift[a] >= 0.0 && shift[a] < 1.0))
+            return fail(c, TPM_EINVAL, "shift must lie in [0, 1)");
+    for (int a = 0; a < 3; a++)
+        c->P.shift[a] = shift[a];
+    return TPM_OK;
+}
+
 int tpm_timing_enable(tpm_ctx *c, int on) {
     if (!c)
         return TPM_EINVAL;

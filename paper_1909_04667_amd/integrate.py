@@ -6,7 +6,14 @@ distribution (the tree is rebuilt from all particles at every sync point).
 ``Hierarchical`` is the split-Hamiltonian variant of Sec. 7.3: over a step of
 level b the particles of bins >= b split into slow (bin b) and fast (bins >
 b) parts; mutual kicks, the slow part's own leapfrog and two fast steps of
-level b + 1, with trees built over the parts only.
+level b + 1, with trees built over the parts only.  With a mesh the split
+applies to the short-range tree force and the mesh force kicks everyone on
+the longest step (solved from all particles at its start and end).
+
+Random placement (Sec. 3.1): with ``shift_seed`` every tree construction
+takes a new root placement (non-periodic) or box shift (periodic), drawn
+from a seeded generator here and passed to the library, so that tree force
+errors decorrelate from step to step.
 
 Every kick, drift, time-bin assignment, selection and gather runs in the
 library's kernels (``tpm_kick``, ``tpm_drift``, ``tpm_time_bins``,
@@ -29,11 +36,14 @@ def _i32(n, dev):
 
 class _Base:
     def __init__(self, pos, vel, mass=None, softening=None, *, C, dt_max, max_bin,
-                 params=None, **ctx_kw):
+                 params=None, shift_seed=None, **ctx_kw):
         """pos, vel: (x, y, z) device FP64 tensors; mass: FP64 or None (1/n);
         softening: individual softening lengths or None (the context's eps);
         C, dt_max, max_bin: time-step parameter, longest step, deepest bin;
-        the context is made from ``params`` or the remaining keywords."""
+        shift_seed: None (the context's fixed placement) or the seed of the
+        placements drawn before every build (three uniform numbers in [0, 1)
+        per build, numpy's default generator); the context is made from
+        ``params`` or the remaining keywords."""
         x, y, z = pos
         self.dev = x.device
         self.n = x.numel()
@@ -53,6 +63,21 @@ class _Base:
         self.bins = torch.zeros(self.n, dtype=torch.int32, device=self.dev)
         self.hist = torch.zeros(self.max_bin + 1, dtype=torch.int32, device=self.dev)
         self.force_evals = 0
+        self.builds = 0
+        self._shifts = None if shift_seed is None else np.random.default_rng(shift_seed)
+
+    def _build(self, x, y, z, mass=None, eps=None):
+        """One tree construction, with a new placement when shifts are on."""
+        if self._shifts is not None:
+            self.ctx.set_shift(self._shifts.random(3))
+        self.ctx.build_tree(x, y, z, mass, eps=eps)
+        self.builds += 1
+
+    def momentum(self):
+        """Total momentum sum m v (FP64, on the host)."""
+        m = self.mass if self.mass is not None else \
+            torch.full((self.n,), 1.0 / self.n, dtype=torch.float64, device=self.dev)
+        return np.array([float((m * t).sum()) for t in (self.vx, self.vy, self.vz)])
 
     # -- kernel calls through the C ABI -------------------------------------------
     def _kick(self, idx, acc, acc_b=None, b_sign=1, dt=0.0, by_bins=False):
@@ -94,7 +119,7 @@ class BlockLeapfrog(_Base):
     opening half kick)."""
 
     def _force(self, idx):
-        self.ctx.build_tree(self.x, self.y, self.z, self.mass, eps=self.eps)
+        self._build(self.x, self.y, self.z, self.mass, eps=self.eps)
         a, _ = self.ctx.compute_forces(idx, "bh", want_pot=False)
         apm = self.ctx.pm_long_range(idx, want_pot=False)[0] if self.has_pm else None
         self.force_evals += idx.numel()
@@ -129,16 +154,15 @@ class BlockLeapfrog(_Base):
             occ += self._time_bins(act, a, apm, t)
             self._kick(act, a, apm, 1, by_bins=True)  # open the new step
         self.ctx.check()
-        return {"sync_points": steps, "force_evals": self.force_evals}
+        return {"sync_points": steps, "force_evals": self.force_evals, "builds": self.builds}
 
 
 class Hierarchical(_Base):
-    """Split-Hamiltonian integration (Sec. 7.3; Pelupessy et al. 2012)."""
+    """Split-Hamiltonian integration (Sec. 7.3; Pelupessy et al. 2012), with
+    the mesh force (if the context has a mesh) on the longest step."""
 
     def __init__(self, *a, **kw):
         super().__init__(*a, **kw)
-        if self.has_pm:
-            raise ValueError("the hierarchical split is built for tree forces without a mesh")
         if self.mass is None:  # a tree over a part must keep the system's masses
             self.mass = torch.full((self.n,), 1.0 / self.n, dtype=torch.float64,
                                    device=self.dev)
@@ -161,7 +185,7 @@ class Hierarchical(_Base):
         if self.se is not None:
             self._gather(members, self.eps, self.se)
         sl = lambda t: None if t is None else t[:m]
-        self.ctx.build_tree(self.sx[:m], self.sy[:m], self.sz[:m], sl(self.sm), eps=sl(self.se))
+        self._build(self.sx[:m], self.sy[:m], self.sz[:m], sl(self.sm), eps=sl(self.se))
 
     def _forces(self, members, targets_local=None):
         """Forces among ``members`` at the members listed (by position) in
@@ -208,11 +232,27 @@ class Hierarchical(_Base):
         self._level(F, b + 1, 0.5 * dt)
         self._cross(P, S_loc, S, F_loc, F, 0.5 * dt)
 
+    def _long(self, everyone):
+        """Mesh force of all particles from all of them (the last build must
+        be over everyone: the mesh is solved from the particles of the last
+        build)."""
+        a, _ = self.ctx.pm_long_range(everyone, want_pot=False)
+        self.force_evals += self.n
+        return a
+
     def run(self, n_max_steps):
         everyone = _i32(self.n, self.dev)
         for _ in range(int(n_max_steps)):
             a = self._forces(everyone)
-            self._time_bins(everyone, a, None, 0)
+            if not self.has_pm:
+                self._time_bins(everyone, a, None, 0)
+                self._level(everyone, 0, self.dt_max)
+                continue
+            a_long = self._long(everyone)
+            self._time_bins(everyone, a, a_long, 0)
+            self._kick(everyone, a_long, dt=0.5 * self.dt_max)
             self._level(everyone, 0, self.dt_max)
+            self._build_sub(everyone)
+            self._kick(everyone, self._long(everyone), dt=0.5 * self.dt_max)
         self.ctx.check()
-        return {"levels": self.levels, "force_evals": self.force_evals}
+        return {"levels": self.levels, "force_evals": self.force_evals, "builds": self.builds}

@@ -7,7 +7,10 @@
   lengthens its step only at a synchronised time, several bins are used.
 * Hierarchical split (Sec. 7.3): with pairwise forces it conserves momentum
   to round-off even with local steps, which the block-step scheme does not;
-  with a single bin it is the plain leapfrog, bit for bit.
+  with a single bin it is the plain leapfrog, bit for bit.  With a
+  long-range part (kicked on the longest step) it still conserves momentum
+  when both parts are pairwise, and with a single bin it equals the leapfrog
+  on the summed force up to rounding (the kicks commute).
 """
 import math
 
@@ -129,8 +132,49 @@ def test_hierarchical_single_bin_is_leapfrog(orc):
     assert np.array_equal(xh, xb) and np.array_equal(vh, vb)
 
 
+def _long_force(orc, mass):
+    """A smooth pairwise stand-in for the mesh force: the direct sum with a
+    wide softening (pairwise, so it conserves momentum)."""
+    P = orc.make_params(eps=0.5)
+
+    def force_long(x):
+        a, _ = orc.direct(x[0], x[1], x[2], mass, P)
+        return a
+    return force_long
+
+
+def test_hierarchical_long_range_conserves_momentum(orc):
+    p = W.plummer(160, 12)
+    x0 = np.stack([p.x, p.y, p.z])
+    v0 = 0.4 * np.random.default_rng(13).normal(size=x0.shape)
+    m = np.random.default_rng(14).uniform(0.5, 1.5, p.n) / p.n
+    mom = lambda v: (v * m).sum(axis=1)
+    scale = float(np.sum(m * np.linalg.norm(v0, axis=0)))
+    kw = dict(eps=0.02, C=0.02, dt_max=0.04, max_bin=3, n_max_steps=2)
+    _, vh, st = I.hierarchical(x0, v0, _direct_force_sub(orc, m, 0.02),
+                               force_long=_long_force(orc, m), **kw)
+    assert st["levels"] >= 3
+    assert np.abs(mom(vh) - mom(v0)).max() / scale <= 1e-14
+
+
+def test_hierarchical_long_range_single_bin_is_leapfrog(orc):
+    p = W.plummer(120, 15)
+    x0 = np.stack([p.x, p.y, p.z])
+    v0 = 0.3 * np.random.default_rng(16).normal(size=x0.shape)
+    m = np.full(p.n, 1.0 / p.n)
+    kw = dict(eps=0.03, C=1e9, dt_max=0.02, max_bin=3, n_max_steps=3)
+    short, long_ = _direct_force_sub(orc, m, 0.03), _long_force(orc, m)
+    xh, vh, _ = I.hierarchical(x0, v0, short, force_long=long_, **kw)
+    full = lambda x, t: short(x, np.arange(p.n))[:, t] + long_(x)[:, t]
+    xb, vb, _ = I.leapfrog_bins(x0, v0, full, **kw)
+    dv = np.abs(v0 - vb).max()  # the velocity change the forces made
+    assert np.abs(xh - xb).max() <= 1e-13 * np.abs(x0).max()
+    assert np.abs(vh - vb).max() <= 1e-11 * dv, (np.abs(vh - vb).max(), dv)
+
+
 @pytest.mark.parametrize("mut,pin", [(1, "test_time_bins_follow_the_hierarchy"),
-                                     (2, "test_hierarchical_conserves_momentum")])
+                                     (2, "test_hierarchical_conserves_momentum"),
+                                     (3, "test_hierarchical_long_range_single_bin_is_leapfrog")])
 def test_integrator_mutation_is_caught(orc, mut, pin):
     saved = I.MUTATION
     I.MUTATION = mut
