@@ -93,8 +93,26 @@ typedef struct tpm_ctx tpm_ctx;
 
 /* Create a context bound to a HIP stream (NULL: the null stream) on the
  * current device.  Validates *p (TPM_EINVAL).  No device memory is allocated
- * until the first build.  *out receives the context, NULL on error. */
+ * until the first build; each buffer is then allocated when first needed and
+ * reallocated when a larger build needs more.  *out receives the context,
+ * NULL on error. */
 int tpm_create(const tpm_params *p, void *hip_stream, tpm_ctx **out);
+
+/* Create a context whose device memory is one arena of arena_bytes, allocated
+ * here (the memory manager of Sec. 9.4: one allocation, carved by the
+ * library); arena_bytes 0 is tpm_create.  No later call allocates or frees
+ * device memory.  A build releases the previous build's buffers and carves
+ * every per-particle buffer at once; buffers kept across builds (mesh,
+ * tables, flags) sit at the arena's end.  A call that would need more than
+ * the arena holds returns TPM_ENOMEM before it writes any output (a build
+ * then leaves the context without a tree).  tpm_bytes_needed(p, n) bytes
+ * hold every call on trees of at most n particles and 2.5 n + 64 entries
+ * (any input without many near-coincident particles).  Rebuilding must not
+ * overlap work still reading the context on another stream (the resident
+ * server).  TPM_EINVAL for invalid parameters or arena_bytes < 0,
+ * TPM_ENOMEM when the arena cannot be allocated. */
+int tpm_create_arena(const tpm_params *p, void *hip_stream, int64_t arena_bytes,
+                     tpm_ctx **out);
 
 /* Free every device and host buffer of the context (synchronises its stream). */
 int tpm_destroy(tpm_ctx *ctx);
@@ -105,11 +123,15 @@ const char *tpm_last_error(const tpm_ctx *ctx);
 /* Rebind the context to another stream. */
 int tpm_set_stream(tpm_ctx *ctx, void *hip_stream);
 
-/* Upper bound of the device bytes a build of n particles allocates, for
- * admission by memory budget.  Returns -1 on invalid parameters. */
+/* Upper bound of the device bytes a context holds for builds of at most n
+ * particles (trees of at most 2.5 n + 64 entries) and every call on them
+ * (forces, mesh, resident-server steps, time-bin selections), with or
+ * without individual softening, in either allocation mode: the admission
+ * estimate for a memory budget and a sufficient arena size.  Returns -1 on
+ * invalid parameters. */
 int64_t tpm_bytes_needed(const tpm_params *p, int64_t n);
 
-/* Device bytes the context holds now. */
+/* Device bytes the context holds now (an arena context: the arena size). */
 int64_t tpm_bytes_held(const tpm_ctx *ctx);
 
 /* Build the tree (Sec. 3.1) of n >= 1 particles.

@@ -48,6 +48,7 @@ def lib():
         vp, i64, i32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_double
         P = C.POINTER
         L.tpm_create.argtypes = [P(TpmParams), vp, P(vp)]
+        L.tpm_create_arena.argtypes = [P(TpmParams), vp, i64, P(vp)]
         L.tpm_destroy.argtypes = [vp]
         L.tpm_last_error.argtypes = [vp]
         L.tpm_last_error.restype = C.c_char_p
@@ -168,14 +169,21 @@ def _stream_handle(stream):
 class Context:
     """One tree (and PM mesh) on one device, bound to a stream."""
 
-    def __init__(self, params: TpmParams | None = None, stream=None, **kw):
+    def __init__(self, params: TpmParams | None = None, stream=None, arena_bytes=None, **kw):
+        """arena_bytes: None (buffers allocated as needed) or the size of the
+        one device arena the context works in (tpm_create_arena)."""
         self.params = params if params is not None else make_params(**kw)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.dtype = torch.float32 if self.params.precision == 1 else torch.float64
         h = C.c_void_p()
-        rc = lib().tpm_create(C.byref(self.params), _stream_handle(self.stream), C.byref(h))
+        if arena_bytes is None:
+            rc = lib().tpm_create(C.byref(self.params), _stream_handle(self.stream),
+                                  C.byref(h))
+        else:
+            rc = lib().tpm_create_arena(C.byref(self.params), _stream_handle(self.stream),
+                                        int(arena_bytes), C.byref(h))
         if rc != TPM_OK:
-            raise TreePMError(rc, "tpm_create rejected the parameters")
+            raise TreePMError(rc, "tpm_create rejected the parameters or the arena")
         self.h = h
         self.n = 0
         self._keep = ()

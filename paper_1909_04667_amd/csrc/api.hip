@@ -35,6 +35,23 @@ int ensure(tpm_ctx *c, DBuf &b, size_t bytes) {
         bytes = 16;
     if (b.cap >= bytes)
         return TPM_OK;
+    if (c->arena) {  // carve from the arena: nothing is freed or allocated
+        const size_t sz = (bytes + 255) & ~size_t(255);
+        if (c->arena_hi - c->arena_lo < sz)
+            return fail(c, TPM_ENOMEM,
+                        "arena of " + std::to_string(c->arena_size) + " bytes exhausted (" +
+                            std::to_string(c->arena_hi - c->arena_lo) + " free, " +
+                            std::to_string(sz) + " needed)");
+        if (b.persistent) {
+            c->arena_hi -= sz;
+            b.p = c->arena + c->arena_hi;
+        } else {
+            b.p = c->arena + c->arena_lo;
+            c->arena_lo += sz;
+        }
+        b.cap = sz;
+        return TPM_OK;
+    }
     if (b.p) {
         TPM_HIP(c, hipStreamSynchronize(c->stream));
         bump_memory_epoch();
@@ -54,18 +71,95 @@ int ensure(tpm_ctx *c, DBuf &b, size_t bytes) {
     return TPM_OK;
 }
 
+std::vector<DBuf *> all_bufs(tpm_ctx *c) {
+    return {&c->frame, &c->bbox, &c->key[0], &c->key[1], &c->idx[0], &c->idx[1],
+            &c->hist, &c->scan_tmp, &c->perm, &c->rank, &c->ps, &c->ms, &c->qs,
+            &c->dR, &c->cnt, &c->base, &c->lvl_cursor, &c->lvl_list, &c->rec64,
+            &c->rec32, &c->efirst, &c->ecount, &c->pe, &c->mark, &c->act, &c->slot,
+            &c->counters, &c->res, &c->rpot, &c->rnint, &c->srv_pm, &c->srv_an,
+            &c->err_flag, &c->mesh_q, &c->mesh_c, &c->mesh_phi, &c->twiddle,
+            &c->green_axis, &c->green_tab, &c->hs, &c->eh64, &c->eh32, &c->ig_flag,
+            &c->ig_off};
+}
+
 size_t bytes_held(const tpm_ctx *c) {
-    const DBuf *all[] = {&c->frame, &c->bbox, &c->key[0], &c->key[1], &c->idx[0], &c->idx[1],
-                         &c->hist, &c->scan_tmp, &c->perm, &c->rank, &c->ps, &c->ms, &c->qs,
-                         &c->dR, &c->cnt, &c->base, &c->lvl_cursor, &c->lvl_list, &c->rec64,
-                         &c->rec32, &c->efirst, &c->ecount, &c->pe, &c->mark, &c->act, &c->slot,
-                         &c->counters, &c->res, &c->rpot, &c->rnint, &c->srv_pm, &c->srv_an, &c->err_flag, &c->mesh_q,
-                         &c->mesh_c, &c->mesh_phi, &c->twiddle, &c->green_axis, &c->green_tab,
-                         &c->hs, &c->eh64, &c->eh32, &c->ig_flag, &c->ig_off};
+    if (c->arena)
+        return c->arena_size;
     size_t s = 0;
-    for (const DBuf *b : all)
+    for (const DBuf *b : all_bufs(const_cast<tpm_ctx *>(c)))
         s += b->cap;
     return s;
+}
+
+void visit_sizes(tpm_ctx *c, const tpm_params &P, int64_t n, int64_t E, bool mixed,
+                 const std::function<void(DBuf &, size_t, int)> &f) {
+    const size_t N = (size_t)n, NE = (size_t)E;
+    const size_t esz = P.precision == TPM_FP32 ? 4 : 8;
+    // fixed size, kept across builds
+    f(c->frame, sizeof(Frame), 2);
+    f(c->counters, 64 * sizeof(uint32_t), 2);
+    f(c->lvl_cursor, 32 * sizeof(uint32_t), 2);
+    f(c->err_flag, 16, 2);
+    // per particle: build (keys, sort, ranks, sorted copies, topology)
+    for (int b = 0; b < 2; b++) {
+        f(c->key[b], 8 * N, 0);
+        f(c->idx[b], 4 * N, 0);
+    }
+    f(c->hist, std::max(sort_scratch_bytes(n), topology_hist_bytes(n)), 0);
+    f(c->scan_tmp, (size_t)compaction_tiles(n) * 4, 0);
+    f(c->perm, 4 * N, 0);
+    f(c->rank, 4 * N, 0);
+    f(c->ps, 24 * N, 0);
+    f(c->ms, 8 * N, 0);
+    f(c->qs, 8 * N, 0);
+    f(c->dR, N, 0);
+    f(c->cnt, 4 * N, 0);
+    f(c->base, 4 * N, 0);
+    f(c->pe, 4 * N, 0);
+    if (!P.periodic)
+        f(c->bbox, bbox_bytes(n), 0);
+    if (mixed)
+        f(c->hs, 8 * N, 0);
+    // per particle: active sets, results, resident-server steps, selections
+    f(c->mark, 4 * N, 0);
+    f(c->act, 4 * N, 0);
+    f(c->slot, 4 * N, 0);
+    f(c->res, 3 * N * esz, 0);
+    f(c->rpot, N * esz, 0);
+    f(c->rnint, 4 * N, 0);
+    f(c->srv_an, 8 * N, 0);
+    if (P.pm_grid > 0)
+        f(c->srv_pm, 3 * N * esz, 0);
+    f(c->ig_flag, 4 * N, 0);
+    f(c->ig_off, 4 * N + 64, 0);
+    // per entry
+    if (E > 0) {
+        f(c->rec64, NE * sizeof(Rec64), 1);
+        f(c->efirst, 4 * NE, 1);
+        f(c->ecount, 4 * NE, 1);
+        f(c->lvl_list, 4 * std::max<size_t>(NE - std::min(NE, N), 1), 1);
+        if (P.precision == TPM_FP32)
+            f(c->rec32, NE * sizeof(Rec32), 1);
+        if (mixed) {
+            f(c->eh64, 8 * NE, 1);
+            if (P.precision == TPM_FP32)
+                f(c->eh32, 4 * NE, 1);
+        }
+    }
+    // mesh, transforms and tables (Sec. 3.3)
+    if (P.pm_grid > 0) {
+        const size_t M = P.periodic ? (size_t)P.pm_grid : 2 * (size_t)P.pm_grid;
+        const size_t n3 = M * M * M;
+        f(c->mesh_q, (esz == 8 ? 2 : 1) * n3 * 8, 2);
+        f(c->mesh_c, M * M * (M / 2 + 1) * 2 * esz, 2);
+        f(c->mesh_phi, n3 * esz, 2);
+        f(c->twiddle, M * 2 * esz + 64, 2);
+        f(c->green_axis, 2 * M * sizeof(double), 2);
+        if (!P.periodic) {
+            const size_t gh = (size_t)P.pm_grid + 1;
+            f(c->green_tab, gh * gh * gh * sizeof(double), 2);
+        }
+    }
 }
 
 static hipEvent_t take_event(tpm_ctx *c) {
@@ -116,19 +210,16 @@ static void free_all(tpm_ctx *c) {
     for (hipEvent_t e : c->event_pool)
         (void)hipEventDestroy(e);
     c->event_pool.clear();
-    DBuf *all[] = {&c->frame, &c->bbox, &c->key[0], &c->key[1], &c->idx[0], &c->idx[1],
-                   &c->hist, &c->scan_tmp, &c->perm, &c->rank, &c->ps, &c->ms, &c->qs,
-                   &c->dR, &c->cnt, &c->base, &c->lvl_cursor, &c->lvl_list, &c->rec64,
-                   &c->rec32, &c->efirst, &c->ecount, &c->pe, &c->mark, &c->act, &c->slot,
-                   &c->counters, &c->res, &c->rpot, &c->rnint, &c->srv_pm, &c->srv_an, &c->err_flag, &c->mesh_q,
-                   &c->mesh_c, &c->mesh_phi, &c->twiddle, &c->green_axis, &c->green_tab,
-                   &c->hs, &c->eh64, &c->eh32, &c->ig_flag, &c->ig_off};
-    for (DBuf *b : all) {
-        if (b->p)
+    for (DBuf *b : all_bufs(c)) {
+        if (b->p && !c->arena)
             (void)hipFree(b->p);
         b->p = nullptr;
         b->cap = 0;
     }
+    if (c->arena)
+        (void)hipFree(c->arena);
+    c->arena = nullptr;
+    c->arena_size = c->arena_lo = c->arena_hi = 0;
     c->green_tab_ng = 0;
     c->axis_tables_M = 0;
     if (c->hpin)
@@ -188,10 +279,15 @@ using namespace tpm;
 extern "C" {
 
 int tpm_create(const tpm_params *p, void *hip_stream, tpm_ctx **out) {
+    return tpm_create_arena(p, hip_stream, 0, out);
+}
+
+int tpm_create_arena(const tpm_params *p, void *hip_stream, int64_t arena_bytes,
+                     tpm_ctx **out) {
     if (!out)
         return TPM_EINVAL;
     *out = nullptr;
-    if (validate(p))
+    if (validate(p) || arena_bytes < 0)
         return TPM_EINVAL;
     tpm_ctx *c = new (std::nothrow) tpm_ctx();
     if (!c)
@@ -213,6 +309,26 @@ int tpm_create(const tpm_params *p, void *hip_stream, tpm_ctx **out) {
         hipSuccess) {
         delete c;
         return TPM_ENOMEM;
+    }
+    // buffers kept across builds take the arena's top end
+    visit_sizes(c, c->P, 1, 0, false, [](DBuf &b, size_t, int kind) {
+        if (kind == 2)
+            b.persistent = true;
+    });
+    if (arena_bytes > 0) {
+        void *a = nullptr;
+        if (hipMalloc(&a, (size_t)arena_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            free_all(c);
+            delete c;
+            return TPM_ENOMEM;
+        }
+        c->arena = (unsigned char *)a;
+        c->arena_size = (size_t)arena_bytes;
+        c->arena_lo = 0;
+        // every carved buffer starts on a 256-byte boundary (scalar loads and
+        // atomics need aligned addresses): the top end too
+        c->arena_hi = (size_t)arena_bytes & ~size_t(255);
     }
     *out = c;
     return TPM_OK;
@@ -239,21 +355,16 @@ int tpm_set_stream(tpm_ctx *c, void *s) {
 int64_t tpm_bytes_needed(const tpm_params *p, int64_t n) {
     if (validate(p) || n < 1)
         return -1;
-    // per particle: sort buffers, ranks, sorted SoA, build scratch, active set,
-    // results; per entry (estimated at 2.5 n): records, first/count, level list
-    const int64_t per_part = 16 + 8 + 4 + 4 + 24 + 8 + 8 + 1 + 4 + 4 + 4 + 12 + 24 + 8 + 4 + 4;
-    const int64_t per_entry = 64 + (p->precision == TPM_FP32 ? 32 : 0) + 12;
-    int64_t b = n * per_part + (n * 5 / 2 + 64) * per_entry + (1 << 20);
-    if (p->pm_grid > 0) {
-        const int64_t m = p->periodic ? p->pm_grid : 2 * (int64_t)p->pm_grid;
-        const int64_t n3 = m * m * m;
-        b += n3 * (8 + (p->precision == TPM_FP32 ? 12 : 24));
-        if (!p->periodic) {  // Green's function octant
-            const int64_t g = p->pm_grid + 1;
-            b += g * g * g * 8;
-        }
-    }
-    return b + b / 8;
+    // every buffer at its largest size for n particles and at most 2.5 n + 64
+    // entries, with individual softening, plus the headroom (an eighth) and
+    // the alignment of either allocation mode
+    tpm_ctx tmp;
+    tmp.P = *p;
+    size_t b = 0;
+    visit_sizes(&tmp, *p, n, n * 5 / 2 + 64, true, [&](DBuf &, size_t bytes, int) {
+        b += bytes + bytes / 8 + 256;
+    });
+    return (int64_t)b;
 }
 
 int64_t tpm_bytes_held(const tpm_ctx *c) { return c ? (int64_t)bytes_held(c) : -1; }
@@ -276,6 +387,24 @@ int tpm_build_tree_eps(tpm_ctx *c, int64_t n, const double *x, const double *y,
     c->pm_ready = 0;
     bump_memory_epoch();
     c->epoch = 0;  // marks must be cleared before the next active set
+    if (c->arena) {
+        // the previous build's buffers are released (later work on this
+        // stream runs after what was queued before); every per-particle
+        // buffer is carved now at its largest size, so that a context whose
+        // arena cannot hold them fails here, before any kernel runs
+        for (DBuf *b : all_bufs(c))
+            if (!b->persistent) {
+                b->p = nullptr;
+                b->cap = 0;
+            }
+        c->arena_lo = 0;
+        int rc = TPM_OK;
+        visit_sizes(c, c->P, n, 0, eps != nullptr, [&](DBuf &b, size_t bytes, int kind) {
+            if (rc == TPM_OK && kind == 0)
+                rc = ensure(c, b, bytes);
+        });
+        TPM_TRY(rc);
+    }
     if (!c->err_flag.p) {
         TPM_TRY(ensure(c, c->err_flag, 16));
         TPM_TRY(fill_u32(c, (uint32_t *)c->err_flag.p, 0u, 4));

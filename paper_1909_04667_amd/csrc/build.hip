@@ -458,6 +458,14 @@ __global__ __launch_bounds__(kBlock) void k_pack32(const Rec64 *__restrict__ rec
 
 }  // namespace
 
+size_t topology_hist_bytes(int64_t n) {
+    return (size_t)2 * kLevels * grid_for(n, kBlock) * sizeof(uint32_t);
+}
+
+size_t bbox_bytes(int64_t n) {
+    return (size_t)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock) * 6 * sizeof(double);
+}
+
 int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double *z,
           const double *mass, const double *eps) {
     hipStream_t st = c->stream;
@@ -495,7 +503,7 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
         TPM_HIP(c, hipMemcpyAsync(F, &c->frame_host, sizeof(Frame), hipMemcpyHostToDevice, st));
     } else {
         const int nparts = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
-        TPM_TRY(ensure(c, c->bbox, (size_t)nparts * 6 * sizeof(double)));
+        TPM_TRY(ensure(c, c->bbox, bbox_bytes(n)));
         k_bbox_partial<<<nparts, kBlock, 0, st>>>(x, y, z, n, (double *)c->bbox.p);
         TPM_LAUNCHED(c, "k_bbox_partial");
         k_frame_final<<<1, kBlock, 0, st>>>((const double *)c->bbox.p, nparts, F, P.shift[0],
@@ -525,7 +533,7 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
     const uint64_t *key = (const uint64_t *)c->key[0].p;
     uint32_t *lvl_count = (uint32_t *)c->counters.p;  // [0..21] level starts, [32] E, [33] nodes
     const uint32_t nb = grid_for(n, kBlock);
-    TPM_TRY(ensure(c, c->hist, (size_t)2 * kLevels * nb * sizeof(uint32_t)));
+    TPM_TRY(ensure(c, c->hist, topology_hist_bytes(n)));
     uint32_t *lhist = (uint32_t *)c->hist.p;
     uint32_t *loff = lhist + (size_t)kLevels * nb;
     TPM_TRY(timer_begin(c, TPM_TIMER_TOPOLOGY));

@@ -427,10 +427,15 @@ int scan_u32(tpm_ctx *c, const uint32_t *in, uint32_t *out, int64_t n, uint32_t 
     return TPM_OK;
 }
 
-int radix_sort_pairs(tpm_ctx *c, int64_t n) {
+size_t sort_scratch_bytes(int64_t n) {
     const int64_t nb = (n + kSortTile - 1) / kSortTile;
     // tile counters, digit histograms, look-back words of every pass
-    const int64_t words = kPasses + kPasses * kRadix + kPasses * nb * kRadix;
+    return (size_t)(kPasses + kPasses * kRadix + kPasses * nb * kRadix) * sizeof(uint64_t);
+}
+
+int radix_sort_pairs(tpm_ctx *c, int64_t n) {
+    const int64_t nb = (n + kSortTile - 1) / kSortTile;
+    const int64_t words = (int64_t)(sort_scratch_bytes(n) / sizeof(uint64_t));
     TPM_TRY(ensure(c, c->hist, (size_t)words * sizeof(uint64_t)));
     unsigned long long *ctr = (unsigned long long *)c->hist.p;
     unsigned long long *hist = ctr + kPasses;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <utility>
 #include <vector>
@@ -62,6 +63,7 @@ struct alignas(32) Rec32 {
 struct DBuf {
     void *p = nullptr;
     size_t cap = 0;
+    bool persistent = false;  // arena: kept across builds (top end of the arena)
 };
 
 }  // namespace tpm
@@ -113,6 +115,12 @@ struct tpm_ctx {
     tpm::DBuf green_tab;        // isolated mesh: transformed kernel, one octant
     int green_tab_ng = 0;       // pm_grid the table was built for (0: none)
     int axis_tables_M = 0;      // mesh size the twiddle and axis tables hold (0: none)
+    // device arena (tpm_create_arena): one allocation; per-build buffers are
+    // carved upward from its start and released at every build, persistent
+    // ones (mesh, tables, flags) downward from its end.  Null: each buffer is
+    // its own allocation, made when first needed.
+    unsigned char *arena = nullptr;
+    size_t arena_size = 0, arena_lo = 0, arena_hi = 0;
     // measurement: event pairs per timer class, and a pool of spare events
     int timing = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[TPM_TIMER_KINDS];
@@ -126,6 +134,18 @@ int fail(tpm_ctx *c, int code, const std::string &msg);
 int hip_check(tpm_ctx *c, hipError_t e, const char *what);
 int ensure(tpm_ctx *c, DBuf &b, size_t bytes);
 size_t bytes_held(const tpm_ctx *c);
+// Every device buffer of a context.
+std::vector<DBuf *> all_bufs(tpm_ctx *c);
+// Every device buffer a build of n particles with E entries (mixed: with
+// individual softening) and the calls after it take, at its largest size:
+// f(buffer, bytes, kind), kind 0 per particle, 1 per entry, 2 persistent.
+void visit_sizes(tpm_ctx *c, const tpm_params &P, int64_t n, int64_t E, bool mixed,
+                 const std::function<void(DBuf &, size_t, int)> &f);
+// Scratch of the radix sort of n keys (tile counters, histograms, look-back),
+// of the build's per-level node histograms, and of its bounding-box partials.
+size_t sort_scratch_bytes(int64_t n);
+size_t topology_hist_bytes(int64_t n);
+size_t bbox_bytes(int64_t n);
 // Count of events that rewrite tree records or free device memory (builds,
 // frees), library-wide: a kernel that outlives such an event may hold stale
 // scalar-cache lines of the affected addresses.

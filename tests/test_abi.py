@@ -53,7 +53,18 @@ def test_parameter_validation_on_host():
         h = ctypes.c_void_p()
         assert L.tpm_create(ctypes.byref(p), None, ctypes.byref(h)) == B.TPM_EINVAL, kw
         assert not h.value
+        assert L.tpm_create_arena(ctypes.byref(p), None, 1 << 20,
+                                  ctypes.byref(h)) == B.TPM_EINVAL, kw
+    h = ctypes.c_void_p()
+    assert L.tpm_create_arena(ctypes.byref(ok), None, -1, ctypes.byref(h)) == B.TPM_EINVAL
+    assert L.tpm_create_arena(ctypes.byref(ok), None, 1 << 20, None) == B.TPM_EINVAL
+    # the admission estimate grows with n and covers the mesh
+    sizes = [L.tpm_bytes_needed(ctypes.byref(ok), n) for n in (1, 10, 1000, 10 ** 6)]
+    assert sizes == sorted(sizes) and sizes[-1] > 150 * 10 ** 6
+    per = B.make_params(eps=0.01, periodic=True, box_size=10.0, pm_grid=128)
+    assert L.tpm_bytes_needed(ctypes.byref(per), 1000) > 128 ** 3 * 8
     # NULL arguments are rejected before anything touches a device
+    assert L.tpm_set_shift(None, None) == B.TPM_EINVAL
     assert L.tpm_build_tree(None, 10, None, None, None, None) == B.TPM_EINVAL
     assert L.tpm_compute_forces(None, 0, 1, None, None, None, None, None) == B.TPM_EINVAL
     assert L.tpm_check(None) == B.TPM_EINVAL
