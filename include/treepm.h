@@ -199,7 +199,7 @@ int tpm_compute_forces(tpm_ctx *ctx, int32_t opening, int64_t n_act, const int32
  * context's buffers.  It calls no hipMalloc, hipFree or other allocating
  * routine and records no timer events.  Limit: trees of at most
  * tpm_noalloc_max_n() = 2^20 particles (TPM_EINVAL beyond, before anything
- * is enqueued); the array takes 48 MiB on every GPU the library runs on,
+ * is enqueued); the array takes 52 MiB on every GPU the library runs on,
  * held until the process ends.  All calls on one GPU share that GPU's
  * array: calls that overlap on one GPU (other streams, other threads) race;
  * each call clears what it needs.  The tree itself comes from

@@ -76,7 +76,7 @@ std::vector<DBuf *> all_bufs(tpm_ctx *c) {
             &c->hist, &c->scan_tmp, &c->perm, &c->rank, &c->ps, &c->ms, &c->qs,
             &c->dR, &c->cnt, &c->base, &c->lvl_cursor, &c->lvl_list, &c->rec64,
             &c->rec32, &c->efirst, &c->ecount, &c->pe, &c->mark, &c->act, &c->slot,
-            &c->counters, &c->res, &c->rpot, &c->rnint, &c->srv_pm, &c->srv_an,
+            &c->counters, &c->res, &c->rpot, &c->srv_pm, &c->srv_an,
             &c->err_flag, &c->mesh_q, &c->mesh_c, &c->mesh_phi, &c->twiddle,
             &c->green_axis, &c->green_tab, &c->hs, &c->eh64, &c->eh32, &c->ig_flag,
             &c->ig_off};
@@ -124,12 +124,11 @@ void visit_sizes(tpm_ctx *c, const tpm_params &P, int64_t n, int64_t E, bool mix
     f(c->mark, 4 * N, 0);
     f(c->act, 4 * N, 0);
     f(c->slot, 4 * N, 0);
-    f(c->res, 3 * N * esz, 0);
+    f(c->res, 4 * N * esz, 0);
     f(c->rpot, N * esz, 0);
-    f(c->rnint, 4 * N, 0);
     f(c->srv_an, 8 * N, 0);
     if (P.pm_grid > 0)
-        f(c->srv_pm, 3 * N * esz, 0);
+        f(c->srv_pm, 4 * N * esz, 0);
     f(c->ig_flag, 4 * N, 0);
     f(c->ig_off, 4 * N + 64, 0);
     // per entry

@@ -19,19 +19,19 @@ namespace tpm {
 namespace {
 
 // Largest tree the array serves, and its layout (byte offsets, 256-aligned):
-// marks, active slots, slot map, results [3][n] and potentials [n] in FP64,
-// interaction counts, compaction tile counts, and the unique-active counter.
+// marks, active slots, slot map, results [n][4] (acceleration and interaction
+// count) and potentials [n] in FP64, compaction tile counts, and the
+// unique-active counter.
 constexpr int64_t kMaxN = int64_t(1) << 20;
 constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 constexpr size_t kOffMark = 0;
 constexpr size_t kOffAct = kOffMark + align256(4 * kMaxN);
 constexpr size_t kOffSlot = kOffAct + align256(4 * kMaxN);
 constexpr size_t kOffRes = kOffSlot + align256(4 * kMaxN);
-constexpr size_t kOffPot = kOffRes + align256(3 * 8 * kMaxN);
-constexpr size_t kOffNint = kOffPot + align256(8 * kMaxN);
-constexpr size_t kOffCounts = kOffNint + align256(4 * kMaxN);
+constexpr size_t kOffPot = kOffRes + align256(4 * 8 * kMaxN);
+constexpr size_t kOffCounts = kOffPot + align256(8 * kMaxN);
 constexpr size_t kOffNuniq = kOffCounts + align256(4 * kMaxN / 64 + 64);
-constexpr size_t kScratchBytes = kOffNuniq + 256;  // 48 MiB + 17 KiB
+constexpr size_t kScratchBytes = kOffNuniq + 256;  // 52 MiB + 17 KiB
 
 // In host code this name is only a stand-in for the device symbol: kernels
 // and copies receive the address kept in g_scratch[device] instead.
@@ -115,7 +115,6 @@ int tpm_compute_forces_noalloc(tpm_ctx *c, int32_t opening, int64_t n_act,
     w.slot = (uint32_t *)(s + kOffSlot);
     w.res = s + kOffRes;
     w.rpot = s + kOffPot;
-    w.rnint = (uint32_t *)(s + kOffNint);
     w.counts = (uint32_t *)(s + kOffCounts);
     w.nuniq = (uint32_t *)(s + kOffNuniq);
     return forces_into(c, opening, n_act, idx, anorm, acc, pot, nint, w, false);

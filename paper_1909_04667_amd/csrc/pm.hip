@@ -537,9 +537,10 @@ __global__ __launch_bounds__(kBlock) void k_interp(const uint32_t *__restrict__ 
         return;
     double F[3], P;
     interp_at<T>(ps, n, act[k], phi, mg, F, P);
-    res[k] = (T)F[0];
-    res[n + k] = (T)F[1];
-    res[2 * n + k] = (T)F[2];
+    T *r = res + 4 * (size_t)k;  // the slot's record (fourth value unused)
+    r[0] = (T)F[0];
+    r[1] = (T)F[1];
+    r[2] = (T)F[2];
     rpot[k] = (T)P;
 }
 
@@ -560,9 +561,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter_out(
         return;
     }
     const uint32_t sl = slot[rank[i]];
-    acc[k] = res[sl];
-    acc[n_act + k] = res[n + sl];
-    acc[2 * n_act + k] = res[2 * n + sl];
+    const T *r = res + 4 * (size_t)sl;
+    acc[k] = r[0];
+    acc[n_act + k] = r[1];
+    acc[2 * n_act + k] = r[2];
     if (pot)
         pot[k] = rpot[sl];
 }
@@ -798,7 +800,7 @@ template <typename T>
 int interp_t(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, void *pot) {
     const int64_t n = c->n;
     const MeshGeom mg = mesh_geom(c);
-    TPM_TRY(ensure(c, c->res, (size_t)3 * n * sizeof(T)));
+    TPM_TRY(ensure(c, c->res, (size_t)4 * n * sizeof(T)));
     TPM_TRY(ensure(c, c->rpot, (size_t)n * sizeof(T)));
     TPM_TRY(select_active(c, n_act, idx));
     const unsigned g = grid_for(std::min<int64_t>(n_act, n), kBlock);

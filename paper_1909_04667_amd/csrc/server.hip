@@ -98,7 +98,7 @@ struct alignas(64) SrvReq {
     uint32_t pad0;
     pmk::MeshGeom mg;     // mesh geometry (kMesh)
     const void *phi;      // potential mesh (kMesh)
-    void *res_pm;         // [3][n] mesh force in slot order (kMesh)
+    void *res_pm;         // [n][4] mesh force in slot order (kMesh)
     void *acc_pm;         // [3][n_act] mesh force in caller order (kMesh)
     double *anorm_out;    // [n] |a| in build order, read by the relative pass (kStep)
     uint64_t ticket;
@@ -411,9 +411,9 @@ __device__ __forceinline__ void item_pm(const SrvReq &R, uint32_t it, uint32_t n
         double F[3], P;
         pmk::interp_at<T, true>(R.A.ps, n, coherent_ld(R.A.act + k), (const T *)R.phi, R.mg, F,
                                 P);
-        coherent_st(res + k, (T)F[0]);
-        coherent_st(res + n + k, (T)F[1]);
-        coherent_st(res + 2 * (size_t)n + k, (T)F[2]);
+        coherent_st(res + 4 * (size_t)k, (T)F[0]);
+        coherent_st(res + 4 * (size_t)k + 1, (T)F[1]);
+        coherent_st(res + 4 * (size_t)k + 2, (T)F[2]);
     }
 }
 
@@ -429,9 +429,9 @@ __device__ __forceinline__ void item_norm(const SrvReq &R, uint32_t it, uint32_t
         double v[3];
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            v[d] = (double)coherent_ld(a + (size_t)d * n + k);
+            v[d] = (double)coherent_ld(a + 4 * (size_t)k + d);
             if (mesh)
-                v[d] += (double)coherent_ld(b + (size_t)d * n + k);
+                v[d] += (double)coherent_ld(b + 4 * (size_t)k + d);
         }
         coherent_st(R.anorm_out + R.A.perm[coherent_ld(R.A.act + k)],
                     sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
@@ -455,12 +455,12 @@ __device__ __forceinline__ void item_output(const SrvReq &R, uint32_t it) {
         } else {
             const uint32_t sl = coherent_ld(R.slot + R.rank[i]);
             for (int d = 0; d < 3; d++)
-                v[d] = coherent_ld(res + (size_t)d * n + sl);
+                v[d] = coherent_ld(res + 4 * (size_t)sl + d);
             if (mesh)
                 for (int d = 0; d < 3; d++)
-                    v[3 + d] = coherent_ld(rpm + (size_t)d * n + sl);
+                    v[3 + d] = coherent_ld(rpm + 4 * (size_t)sl + d);
             if (R.nint)
-                ni = coherent_ld(R.A.rnint + sl);
+                ni = count_of(coherent_ld(res + 4 * (size_t)sl + 3));
         }
         // outputs written through to memory (other dies' caches are not
         // written back for the host)
@@ -815,7 +815,7 @@ int submit_impl(tpm_server *s, tpm_ctx *c, bool step, int32_t opening, int64_t n
     if (step) {
         TPM_TRY(ensure(c, c->srv_an, (size_t)c->n * 8));
         if (mesh) {
-            TPM_TRY(ensure(c, c->srv_pm, (size_t)3 * c->n * esz));
+            TPM_TRY(ensure(c, c->srv_pm, (size_t)4 * c->n * esz));
             if (!c->pm_ready) {
                 TPM_TRY(pm_solve(c));
                 c->pm_ready = 1;

@@ -97,7 +97,7 @@ struct tpm_ctx {
     tpm::DBuf rec64, rec32, efirst, ecount;
     tpm::DBuf pe;               // rank -> entry
     tpm::DBuf mark, act, slot, counters;
-    tpm::DBuf res, rpot, rnint; // walk results in slot order
+    tpm::DBuf res, rpot;        // walk results in slot order ([n][4], [n])
     tpm::DBuf srv_pm, srv_an;   // resident server steps: mesh force (slot order), |a|
     tpm::DBuf err_flag;         // [0] bad active index, [1] bad softening length
     // individual softening (Sec. 3.2): spline supports per particle in curve
@@ -174,9 +174,9 @@ struct Work {
     uint32_t *slot = nullptr;   // [n] rank -> position in act
     uint32_t *counts = nullptr; // [ceil(n / scan tile)] compaction tile counts
     uint32_t *nuniq = nullptr;  // [1] number of unique actives
-    void *res = nullptr;        // [3][n] results in slot order (dtype of the context)
+    void *res = nullptr;        // [n][4] results in slot order (dtype of the context):
+                                // acceleration and the interaction count's bits
     void *rpot = nullptr;       // [n]
-    uint32_t *rnint = nullptr;  // [n]
 };
 
 // Primitives (prims.hip) ---------------------------------------------------
@@ -205,8 +205,8 @@ int forces(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx, const
 int forces_into(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx,
                 const double *anorm, void *acc, void *pot, uint32_t *nint, const Work &w,
                 bool timed);
-// the context's own working memory, allocated as needed (results: res,
-// rpot, rnint too); advances the context's mark epoch
+// the context's own working memory, allocated as needed (results: res and
+// rpot too); advances the context's mark epoch
 int work_of_ctx(tpm_ctx *c, bool results, Work &w);
 int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx);
 int select_active_into(tpm_ctx *c, int64_t n_act, const int32_t *idx, const Work &w);

@@ -70,8 +70,8 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_output(
     const int32_t *__restrict__ idx, int64_t n_act, int64_t n, const int32_t *__restrict__ rank,
     const uint32_t *__restrict__ slot, const T *__restrict__ res, const T *__restrict__ rpot,
-    const uint32_t *__restrict__ rnint, T *__restrict__ acc, T *__restrict__ pot,
-    uint32_t *__restrict__ nint, uint32_t *__restrict__ err) {
+    T *__restrict__ acc, T *__restrict__ pot, uint32_t *__restrict__ nint,
+    uint32_t *__restrict__ err) {
     int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= n_act)
         return;
@@ -88,14 +88,16 @@ __global__ __launch_bounds__(kBlock) void k_output(
         atomicOr(err, 1u);
         return;
     }
+    // the slot's record: acceleration and interaction count together
     const uint32_t sl = slot[rank[i]];
-    acc[k] = res[sl];
-    acc[n_act + k] = res[n + sl];
-    acc[2 * n_act + k] = res[2 * n + sl];
+    const T *r = res + 4 * (size_t)sl;
+    acc[k] = r[0];
+    acc[n_act + k] = r[1];
+    acc[2 * n_act + k] = r[2];
     if (pot)
         pot[k] = rpot[sl];
     if (nint)
-        nint[k] = rnint[sl];
+        nint[k] = count_of(r[3]);
 }
 
 template <typename T>
@@ -196,9 +198,8 @@ int work_of_ctx(tpm_ctx *c, bool results, Work &w) {
     TPM_TRY(ensure(c, c->scan_tmp, (size_t)compaction_tiles(n) * 4));
     if (results) {
         const size_t esz = c->P.precision == TPM_FP32 ? 4 : 8;
-        TPM_TRY(ensure(c, c->res, (size_t)3 * n * esz));
+        TPM_TRY(ensure(c, c->res, (size_t)4 * n * esz));
         TPM_TRY(ensure(c, c->rpot, (size_t)n * esz));
-        TPM_TRY(ensure(c, c->rnint, (size_t)n * 4));
     }
     w = Work{};
     w.mark = (uint32_t *)c->mark.p;
@@ -214,7 +215,6 @@ int work_of_ctx(tpm_ctx *c, bool results, Work &w) {
     w.nuniq = (uint32_t *)c->counters.p + 40;
     w.res = c->res.p;
     w.rpot = c->rpot.p;
-    w.rnint = (uint32_t *)c->rnint.p;
     return TPM_OK;
 }
 
@@ -310,7 +310,6 @@ void wk::fill_args(tpm_ctx *c, const double *anorm, const Work &w, WalkArgs &A) 
     A.fgexp = (float)(-1.4426950408889634 * A.inv2rs * A.inv2rs);
     A.res = w.res;
     A.rpot = w.rpot;
-    A.rnint = w.rnint;
     A.L2r = A.L * A.L;
     A.limr = 0.6 * A.L;
     A.hlr = 0.5 * A.L;
@@ -377,12 +376,12 @@ int forces_into(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx,
     if (fp32)
         k_output<float><<<ob, kBlock, 0, st>>>(
             idx, n_act, n, (const int32_t *)c->rank.p, w.slot, (const float *)w.res,
-            (const float *)w.rpot, w.rnint, (float *)acc, want_pot ? (float *)pot : nullptr,
+            (const float *)w.rpot, (float *)acc, want_pot ? (float *)pot : nullptr,
             nint, (uint32_t *)c->err_flag.p);
     else
         k_output<double><<<ob, kBlock, 0, st>>>(
             idx, n_act, n, (const int32_t *)c->rank.p, w.slot, (const double *)w.res,
-            (const double *)w.rpot, w.rnint, (double *)acc, want_pot ? (double *)pot : nullptr,
+            (const double *)w.rpot, (double *)acc, want_pot ? (double *)pot : nullptr,
             nint, (uint32_t *)c->err_flag.p);
     TPM_LAUNCHED(c, "k_output");
     return TPM_OK;
@@ -663,14 +662,13 @@ int tpm_batch_launch(tpm_batch *b) {
         if (c->P.precision == TPM_FP32)
             k_output<float><<<ob, kBlock, 0, b->stream>>>(
                 p.idx, p.n_act, c->n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
-                (const float *)c->res.p, (const float *)c->rpot.p, (const uint32_t *)c->rnint.p,
-                (float *)p.acc, nullptr, p.nint, (uint32_t *)c->err_flag.p);
+                (const float *)c->res.p, (const float *)c->rpot.p, (float *)p.acc, nullptr,
+                p.nint, (uint32_t *)c->err_flag.p);
         else
             k_output<double><<<ob, kBlock, 0, b->stream>>>(
                 p.idx, p.n_act, c->n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
-                (const double *)c->res.p, (const double *)c->rpot.p,
-                (const uint32_t *)c->rnint.p, (double *)p.acc, nullptr, p.nint,
-                (uint32_t *)c->err_flag.p);
+                (const double *)c->res.p, (const double *)c->rpot.p, (double *)p.acc, nullptr,
+                p.nint, (uint32_t *)c->err_flag.p);
         BHIP(b, hipGetLastError());
     }
     BHIP(b, hipEventRecord(b->done, b->stream));

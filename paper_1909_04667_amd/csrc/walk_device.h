@@ -38,9 +38,8 @@ struct WalkArgs {
     // image is every member's (periodic)
     float fpf2, fpf_ext;
     double pf2, pf_ext;
-    void *res;
-    void *rpot;
-    uint32_t *rnint;
+    void *res;   // [n][4] per slot: acceleration x, y, z and the interaction count
+    void *rpot;  // [n]
     // individual softening (Sec. 3.2): spline support per target (curve
     // order) and the largest support per entry (double, or float for FP32)
     const double *hs;
@@ -295,6 +294,29 @@ __device__ __forceinline__ void coherent_st(T *p, T v) {
 __device__ __forceinline__ uint32_t load_count(const uint32_t *p) {
     return __builtin_amdgcn_readfirstlane(
         __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// A slot's results are one record of four values: the acceleration and, in
+// the fourth, the interaction count carried in the value's bits (so the
+// output gathers read one record per target).
+__device__ __forceinline__ float count_bits(uint32_t n, float) { return __uint_as_float(n); }
+__device__ __forceinline__ double count_bits(uint32_t n, double) {
+    return __longlong_as_double((long long)n);
+}
+__device__ __forceinline__ uint32_t count_of(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint32_t count_of(double v) {
+    return (uint32_t)__double_as_longlong(v);
+}
+template <typename T>
+__device__ __forceinline__ void store_result(void *res, void *rpot, uint32_t slot, T a0, T a1,
+                                             T a2, bool pot_on, T pot, uint32_t nint) {
+    T *r = (T *)res + 4 * (size_t)slot;
+    coherent_st(r, a0);
+    coherent_st(r + 1, a1);
+    coherent_st(r + 2, a2);
+    coherent_st(r + 3, count_bits(nint, T()));
+    if (pot_on)
+        coherent_st((T *)rpot + slot, pot);
 }
 
 // Orders the wavefront's LDS accesses (lanes read what other lanes wrote).
@@ -613,15 +635,8 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave, I
     }
     if (TPM && qn)
         flush(qn, ns);
-    if (valid) {
-        double *res = (double *)A.res;
-        coherent_st(res + slot, a0);
-        coherent_st(res + A.n + slot, a1);
-        coherent_st(res + 2 * (size_t)A.n + slot, a2);
-        if (POT)
-            coherent_st((double *)A.rpot + slot, pot);
-        coherent_st(A.rnint + slot, nint);
-    }
+    if (valid)
+        store_result<double>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
 }
 
 // ---- FP32 walk ----------------------------------------------------------------
@@ -934,15 +949,8 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
             c = desc ? cu + 1u : r.skip;
         }
     }
-    if (valid) {
-        float *res = (float *)A.res;
-        coherent_st(res + slot, a0);
-        coherent_st(res + A.n + slot, a1);
-        coherent_st(res + 2 * (size_t)A.n + slot, a2);
-        if (POT)
-            coherent_st((float *)A.rpot + slot, pot);
-        coherent_st(A.rnint + slot, nint);
-    }
+    if (valid)
+        store_result<float>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
@@ -1047,13 +1055,7 @@ __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, u
             }
             e = step_in ? e + 1u : r.skip;
             if (e >= A.E) {
-                double *res = (double *)A.res;
-                coherent_st(res + slot, a0);
-                coherent_st(res + A.n + slot, a1);
-                coherent_st(res + 2 * (size_t)A.n + slot, a2);
-                if (POT)
-                    coherent_st((double *)A.rpot + slot, pot);
-                coherent_st(A.rnint + slot, nint);
+                store_result<double>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
                 slot += 64u;
                 live = slot < chunk_end;
                 if (live)
@@ -1141,13 +1143,7 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
             }
             e = (part || open) ? e + 1u : r.skip;
             if (e >= A.E) {
-                float *res = (float *)A.res;
-                coherent_st(res + slot, a0);
-                coherent_st(res + A.n + slot, a1);
-                coherent_st(res + 2 * (size_t)A.n + slot, a2);
-                if (POT)
-                    coherent_st((float *)A.rpot + slot, pot);
-                coherent_st(A.rnint + slot, nint);
+                store_result<float>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
                 slot += 64u;
                 live = slot < chunk_end;
                 if (live)
