@@ -410,14 +410,14 @@ def pass_bytes(n, E, ng, prec, periodic, masses=False):
     nodes = E - n
     t = 4 if prec == "fp32" else 8
     b = {}
-    # root cube (isolated: one read of the positions) and keys: positions in,
-    # key and index out
-    b["keys"] = (0 if periodic else 24 * n) + 24 * n + 12 * n
+    # root cube (isolated: one read of the positions) and keys: positions (and
+    # masses) in, key, index and the packed 32-byte position/mass record out
+    b["keys"] = (0 if periodic else 24 * n) + (32 if masses else 24) * n + 12 * n + 32 * n
     # digit histograms (one read of the keys) + 8 passes of (key, index) in and out
     b["sort"] = 8 * n + 8 * 24 * n
-    # index in, positions (and masses) gathered, permutation, rank, curve-order
+    # index in, the packed records gathered, permutation, rank, curve-order
     # positions, masses and packed integer coordinates out
-    b["gather"] = 4 * n + (32 if masses else 24) * n + 4 * n + 4 * n + 24 * n + 8 * n + 8 * n
+    b["gather"] = 4 * n + 32 * n + 4 * n + 4 * n + 24 * n + 8 * n + 8 * n
     # counts (keys in, depth and count out), scan of the counts (two reads, two
     # writes), emission (keys, depths, bases, positions, masses, integer
     # coordinates in; 64-byte records, first/count words, particle entries and

@@ -73,7 +73,7 @@ int ensure(tpm_ctx *c, DBuf &b, size_t bytes) {
 
 std::vector<DBuf *> all_bufs(tpm_ctx *c) {
     return {&c->frame, &c->bbox, &c->key[0], &c->key[1], &c->idx[0], &c->idx[1],
-            &c->hist, &c->scan_tmp, &c->perm, &c->rank, &c->ps, &c->ms, &c->qs,
+            &c->hist, &c->scan_tmp, &c->perm, &c->rank, &c->xyzm, &c->ps, &c->ms, &c->qs,
             &c->dR, &c->cnt, &c->base, &c->lvl_cursor, &c->lvl_list, &c->rec64,
             &c->rec32, &c->efirst, &c->ecount, &c->pe, &c->mark, &c->act, &c->slot,
             &c->counters, &c->res, &c->rpot, &c->srv_pm, &c->srv_an,
@@ -108,6 +108,7 @@ void visit_sizes(tpm_ctx *c, const tpm_params &P, int64_t n, int64_t E, bool mix
     f(c->hist, std::max(sort_scratch_bytes(n), topology_hist_bytes(n)), 0);
     f(c->scan_tmp, (size_t)compaction_tiles(n) * 4, 0);
     f(c->perm, 4 * N, 0);
+    f(c->xyzm, 32 * N, 0);
     f(c->rank, 4 * N, 0);
     f(c->ps, 24 * N, 0);
     f(c->ms, 8 * N, 0);

@@ -178,30 +178,36 @@ __device__ __forceinline__ uint64_t hilbert_key(uint32_t a0, uint32_t a1, uint32
     return (dilate3(X0) << 2) | (dilate3(X1) << 1) | dilate3(X2);
 }
 
+// Keys, and the caller's position and mass of each particle packed into one
+// 32-byte record (caller order), so that the gather into curve order reads
+// one record per particle instead of four scattered values.
 __global__ __launch_bounds__(kBlock) void k_keys(const double *__restrict__ x,
                                                  const double *__restrict__ y,
-                                                 const double *__restrict__ z, int64_t n,
+                                                 const double *__restrict__ z,
+                                                 const double *__restrict__ mass, int64_t n,
                                                  const Frame *__restrict__ Fp,
                                                  uint64_t *__restrict__ key,
-                                                 uint32_t *__restrict__ idx) {
+                                                 uint32_t *__restrict__ idx,
+                                                 double4 *__restrict__ xyzm) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n)
         return;
     const Frame F = *Fp;
+    const double xi = x[i], yi = y[i], zi = z[i];
     double p;
     uint32_t q0, q1, q2;
-    to_frame(x[i], F.x0[0], F, p, q0);
-    to_frame(y[i], F.x0[1], F, p, q1);
-    to_frame(z[i], F.x0[2], F, p, q2);
+    to_frame(xi, F.x0[0], F, p, q0);
+    to_frame(yi, F.x0[1], F, p, q1);
+    to_frame(zi, F.x0[2], F, p, q2);
     key[i] = hilbert_key(q0, q1, q2);
     idx[i] = (uint32_t)i;
+    xyzm[i] = make_double4(xi, yi, zi, mass ? mass[i] : 1.0 / (double)n);
 }
 
 // ---- gather into curve order -------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_gather(
-    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
-    const double *__restrict__ mass, int64_t n, const Frame *__restrict__ Fp,
+    const double4 *__restrict__ xyzm, int64_t n, const Frame *__restrict__ Fp,
     const uint32_t *__restrict__ sidx, int32_t *__restrict__ perm, int32_t *__restrict__ rank,
     double *__restrict__ ps, double *__restrict__ ms, uint64_t *__restrict__ qs,
     const double *__restrict__ eps, double *__restrict__ hs, uint32_t *__restrict__ bad_eps) {
@@ -212,15 +218,16 @@ __global__ __launch_bounds__(kBlock) void k_gather(
     const uint32_t i = sidx[s];
     perm[s] = (int32_t)i;
     rank[i] = (int32_t)s;
+    const double4 r = xyzm[i];
     double p0, p1, p2;
     uint32_t q0, q1, q2;
-    to_frame(x[i], F.x0[0], F, p0, q0);
-    to_frame(y[i], F.x0[1], F, p1, q1);
-    to_frame(z[i], F.x0[2], F, p2, q2);
+    to_frame(r.x, F.x0[0], F, p0, q0);
+    to_frame(r.y, F.x0[1], F, p1, q1);
+    to_frame(r.z, F.x0[2], F, p2, q2);
     ps[s] = p0;
     ps[n + s] = p1;
     ps[2 * n + s] = p2;
-    ms[s] = mass ? mass[i] : 1.0 / (double)n;
+    ms[s] = r.w;
     qs[s] = ((uint64_t)q0 << 42) | ((uint64_t)q1 << 21) | (uint64_t)q2;
     if (eps) {  // individual softening: spline support 2.8 eps, in curve order
         const double e = eps[i];
@@ -477,6 +484,7 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
         TPM_TRY(ensure(c, c->idx[b], (size_t)n * 4));
     }
     TPM_TRY(ensure(c, c->perm, (size_t)n * 4));
+    TPM_TRY(ensure(c, c->xyzm, (size_t)n * 32));
     TPM_TRY(ensure(c, c->rank, (size_t)n * 4));
     TPM_TRY(ensure(c, c->ps, (size_t)n * 24));
     TPM_TRY(ensure(c, c->ms, (size_t)n * 8));
@@ -511,8 +519,9 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
         TPM_LAUNCHED(c, "k_frame_final");
     }
     // 2. keys, 3. sort, gather
-    k_keys<<<grid_for(n, kBlock), kBlock, 0, st>>>(x, y, z, n, F, (uint64_t *)c->key[0].p,
-                                                   (uint32_t *)c->idx[0].p);
+    k_keys<<<grid_for(n, kBlock), kBlock, 0, st>>>(x, y, z, mass, n, F,
+                                                   (uint64_t *)c->key[0].p,
+                                                   (uint32_t *)c->idx[0].p, (double4 *)c->xyzm.p);
     TPM_LAUNCHED(c, "k_keys");
     TPM_TRY(timer_end(c, TPM_TIMER_KEYS));
     TPM_TRY(radix_sort_pairs(c, n));
@@ -524,7 +533,7 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
         TPM_TRY(ensure(c, c->hs, (size_t)n * 8));
     TPM_TRY(timer_begin(c, TPM_TIMER_GATHER));
     k_gather<<<grid_for(n, kBlock), kBlock, 0, st>>>(
-        x, y, z, mass, n, F, (const uint32_t *)c->idx[0].p, (int32_t *)c->perm.p,
+        (const double4 *)c->xyzm.p, n, F, (const uint32_t *)c->idx[0].p, (int32_t *)c->perm.p,
         (int32_t *)c->rank.p, (double *)c->ps.p, (double *)c->ms.p, (uint64_t *)c->qs.p, eps,
         c->mixed ? (double *)c->hs.p : nullptr, bad_eps);
     TPM_LAUNCHED(c, "k_gather");

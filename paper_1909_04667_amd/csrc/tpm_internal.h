@@ -91,6 +91,7 @@ struct tpm_ctx {
     tpm::DBuf hist;             // radix histograms / offsets
     tpm::DBuf scan_tmp;         // scan block sums
     tpm::DBuf perm, rank;       // rank -> build index, build index -> rank
+    tpm::DBuf xyzm;             // caller-order position and mass records [n] (build)
     tpm::DBuf ps, ms, qs;       // sorted positions [3][n], masses, packed q
     tpm::DBuf dR, cnt, base;    // build: neighbour depth, entries per particle
     tpm::DBuf lvl_cursor, lvl_list;
