@@ -295,10 +295,11 @@ int tpm_create_arena(const tpm_params *p, void *hip_stream, int64_t arena_bytes,
     c->P = *p;
     c->stream = (hipStream_t)hip_stream;
     // tuning override of the walk variant (0 automatic, 1 shared cursor,
-    // 2 independent lanes); both variants give identical results
+    // 2 independent lanes, 3 one wavefront per target); 1 and 2 give
+    // identical results, 3 the same interactions summed in another order
     if (const char *m = std::getenv("TPM_WALK_MODE")) {
         const int v = std::atoi(m);
-        c->walk_mode = (v == 1 || v == 2) ? v : 0;
+        c->walk_mode = (v >= 1 && v <= 3) ? v : 0;
     }
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;

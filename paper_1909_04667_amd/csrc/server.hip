@@ -77,7 +77,8 @@ constexpr uint32_t kStep = 1u;   // flags: the whole first force computation
 constexpr uint32_t kMesh = 2u;   //        with the mesh part
 
 // One request, as the host prepares it.  variant: bit 0 relative criterion,
-// 1 TreePM, 2 lane-independent walk, 3 periodic, 4 individual softening.
+// 1 TreePM, 3 periodic, 4 individual softening, bits 5-6 the walk variant
+// (wk::Variant).
 // Whole 64-byte lines, so no scalar-cache line holds parts of two
 // descriptors.
 struct alignas(64) SrvReq {
@@ -157,7 +158,7 @@ __device__ __forceinline__ void wait_mem() {
 }
 
 __device__ __forceinline__ uint32_t phase_items(uint32_t n, uint32_t n_act, uint32_t ph,
-                                                uint32_t nuniq) {
+                                                uint32_t nuniq, uint32_t variant) {
     switch (ph) {
     case kPhClear: return (n + kSrvChunk - 1) / kSrvChunk;
     case kPhMark:
@@ -166,7 +167,8 @@ __device__ __forceinline__ uint32_t phase_items(uint32_t n, uint32_t n_act, uint
     case kPhCompact: return (n + kSrvTile - 1) / kSrvTile;
     case kPhPm:
     case kPhNorm: return (nuniq + kSrvSlots - 1) / kSrvSlots;
-    default: return (nuniq + 63) / 64;  // walk groups (one slot per lane)
+    default: return (variant >> 5) == kSplitWalk ? nuniq            // one target per item
+                                                 : (nuniq + 63) / 64;  // 64 per item
     }
 }
 
@@ -278,7 +280,7 @@ __device__ uint32_t fetch(SrvDev *st, SrvHost *host, SrvReq *slots, Job *jobs) {
                                     ? kPhClear
                                     : kPhMark;
             __hip_atomic_fetch_add(&st->live, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            publish(st, jobs, sid, ph, phase_items(nn, na, ph, 0));
+            publish(st, jobs, sid, ph, phase_items(nn, na, ph, 0, 0));
         }
     }
     if (lane == 0 && n)
@@ -360,22 +362,28 @@ __device__ __forceinline__ void item_compact(const SrvReq &R, uint32_t it) {
 }
 
 template <bool FP32, bool PER, bool TPM, int OPEN, bool MIXED>
-__device__ __forceinline__ void srv_group(const WalkArgs &A, uint32_t g, bool lanes, IQ64 *Q) {
+__device__ __forceinline__ void srv_group(const WalkArgs &A, uint32_t g, uint32_t var,
+                                          WaveLds *Q) {
     if constexpr (FP32) {
-        if (lanes)
+        if (var == kSplitWalk)
+            walk_lanes32<PER, TPM, OPEN, false, MIXED, true>(A, g, 1u, Q->front);
+        else if (var == kLaneWalk)
             walk_lanes32<PER, TPM, OPEN, false, MIXED>(A, g, 1u);
         else
             walk_group32<PER, TPM, OPEN, false, MIXED>(A, g);
     } else {
-        if (lanes)
+        if (var == kSplitWalk)
+            walk_lanes64<PER, TPM, OPEN, false, MIXED, true>(A, g, 1u, Q->front);
+        else if (var == kLaneWalk)
             walk_lanes64<PER, TPM, OPEN, false, MIXED>(A, g, 1u);
         else
-            walk_group64<PER, TPM, OPEN, false, MIXED>(A, g, Q);
+            walk_group64<PER, TPM, OPEN, false, MIXED>(A, g, &Q->q);
     }
 }
 
 template <bool FP32, int OPEN, bool MIXED>
-__device__ __forceinline__ void srv_geometry(const SrvReq &R, uint32_t g, bool lanes, IQ64 *Q) {
+__device__ __forceinline__ void srv_geometry(const SrvReq &R, uint32_t g, uint32_t lanes,
+                                             WaveLds *Q) {
     if (R.variant & 8u)
         srv_group<FP32, true, true, OPEN, MIXED>(R.A, g, lanes, Q);
     else if (R.variant & 2u)
@@ -385,8 +393,8 @@ __device__ __forceinline__ void srv_geometry(const SrvReq &R, uint32_t g, bool l
 }
 
 template <bool FP32>
-__device__ __forceinline__ void item_walk(const SrvReq &R, uint32_t g, IQ64 *Q, bool rel) {
-    const bool lanes = (R.variant & 4u) != 0;
+__device__ __forceinline__ void item_walk(const SrvReq &R, uint32_t g, WaveLds *Q, bool rel) {
+    const uint32_t lanes = (R.variant >> 5) & 3u;  // walk variant
     const bool mixed = (R.variant & 16u) != 0;
     if (rel) {
         if (mixed)
@@ -480,11 +488,8 @@ template <bool FP32>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FP32 ? 4 : 2))) void k_server(
     SrvDev *st, SrvHost *host, SrvReq *slots, Job *jobs, unsigned long long idle_ticks) {
     const int lane = threadIdx.x & 63;
-    IQ64 *Q = nullptr;
-    if constexpr (!FP32) {
-        __shared__ IQ64 q[kBlock / 64];
-        Q = &q[threadIdx.x >> 6];
-    }
+    __shared__ WaveLds q[kBlock / 64];  // the walks' queue or frontiers
+    WaveLds *Q = &q[threadIdx.x >> 6];
     // per block: bumped when one of its wavefronts sees more items left, so
     // its sleeping siblings wake up and claim (an LDS read, no memory traffic)
     __shared__ uint32_t s_hint;
@@ -594,7 +599,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FP32 ? 4
                         nu = coherent_ld(R.A.nuniq);
                     if (nph >= kPhWalk && nph != kPhOutput && nu == 0)
                         nph = kPhOutput;  // no valid target: only the outputs remain
-                    publish(st, jobs, sid, nph, phase_items(R.A.n, R.n_act, nph, nu));
+                    publish(st, jobs, sid, nph, phase_items(R.A.n, R.n_act, nph, nu, R.variant));
                     __hip_atomic_fetch_add(&s_hint, 1u, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
@@ -846,7 +851,7 @@ int submit_impl(tpm_server *s, tpm_ctx *c, bool step, int32_t opening, int64_t n
     R.epoch = w.epoch;
     R.clear = w.clear ? 1u : 0u;
     R.variant = (opening == TPM_OPEN_REL ? 1u : 0u) | (c->P.pm_grid > 0 ? 2u : 0u) |
-                (wk::use_lanes(c, n_act) ? 4u : 0u) | (c->P.periodic ? 8u : 0u) |
+                ((uint32_t)wk::walk_variant(c, n_act) << 5) | (c->P.periodic ? 8u : 0u) |
                 (c->mixed ? 16u : 0u);
     R.flags = (step ? kStep : 0u) | (mesh ? kMesh : 0u);
     if (mesh) {

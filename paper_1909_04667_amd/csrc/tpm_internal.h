@@ -78,7 +78,8 @@ struct tpm_ctx {
     int built = 0;
     int pm_ready = 0;
     uint32_t epoch = 0;     // active-set marking generation
-    int walk_mode = 0;      // 0: automatic, 1: shared cursor, 2: independent lanes
+    int walk_mode = 0;      // 0: automatic, 1: shared cursor, 2: independent lanes,
+                            // 3: one wavefront per target
     tpm::Frame frame_host{};
     uint32_t level_count[tpm::kLevels] = {};
     uint32_t level_off[tpm::kLevels + 1] = {};

@@ -52,6 +52,19 @@ __global__ __launch_bounds__(kBlock) void k_walk32i(const WalkArgs A, uint32_t K
     walk_lanes32<PER, TPM, OPEN, POT, MIXED>(A, wave_id(), K);
 }
 
+// one wavefront per target (sparse active sets)
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_walk64s(const WalkArgs A) {
+    __shared__ uint32_t front[kBlock / 64][kFrontWords];
+    walk_lanes64<PER, TPM, OPEN, POT, MIXED, true>(A, wave_id(), 1u, front[threadIdx.x >> 6]);
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_walk32s(const WalkArgs A) {
+    __shared__ uint32_t front[kBlock / 64][kFrontWords];
+    walk_lanes32<PER, TPM, OPEN, POT, MIXED, true>(A, wave_id(), 1u, front[threadIdx.x >> 6]);
+}
+
 // ---- active set -> slots in curve order --------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_mark(const int32_t *__restrict__ idx, int64_t n_act,
@@ -127,14 +140,19 @@ __global__ __launch_bounds__(kBlock) void k_accel_norm(const int32_t *__restrict
 
 struct Launch {
     bool fp32;
-    bool lanes;       // lane-independent walk
+    Variant variant;
     uint32_t K;       // slots per lane (lane-independent walk)
     unsigned blocks;
 };
 
 template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 void launch_walk(const WalkArgs &A, const Launch &L, hipStream_t st) {
-    if (L.lanes) {
+    if (L.variant == kSplitWalk) {
+        if (L.fp32)
+            k_walk32s<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A);
+        else
+            k_walk64s<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A);
+    } else if (L.variant == kLaneWalk) {
         if (L.fp32)
             k_walk32i<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A, L.K);
         else
@@ -238,18 +256,29 @@ int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
     return select_active_into(c, n_act, idx, w);
 }
 
-// Walk variant (both give identical results): independent lanes for sparse
-// active sets, whose groups are too spread out for a shared cursor (it would
-// visit the union of their walks), and for FP64 TreePM of isolated systems
-// (their outer groups span many cutoff radii, and the FP64 interaction is
-// costly); the shared cursor otherwise (measured on the 128^3 box and the
-// Hernquist sphere).
-bool wk::use_lanes(const tpm_ctx *c, int64_t n_act) {
+// Walk variant.  Independent lanes (results identical to the shared cursor)
+// for sparse active sets, whose groups are too spread out for a shared cursor
+// (it would visit the union of their walks), and for FP64 TreePM of isolated
+// systems (their outer groups span many cutoff radii, and the FP64
+// interaction is costly); the shared cursor otherwise (measured on the 128^3
+// box and the Hernquist sphere).  One wavefront per target for active sets
+// of at most 4096 targets: a lane's serial walk would be the whole critical
+// path (measured: the 4096-particle Plummer sphere 0.74 -> 0.36 ms in FP32).
+// Larger sparse sets keep the lanes: there the frontier walk keeps every SIMD
+// busy but costs about four times the lane walk's work per target (the
+// clustered box's 0.1 % set, 16777 targets: 1.45 ms against 1.33 ms), and
+// concurrent requests of the serving loop fill the chip anyway.
+// TPM_WALK_MODE (1 shared cursor, 2 lanes, 3 one wavefront per target)
+// overrides the choice.
+Variant wk::walk_variant(const tpm_ctx *c, int64_t n_act) {
     if (c->walk_mode != 0)
-        return c->walk_mode == 2;
+        return c->walk_mode == 1 ? kGroupWalk : c->walk_mode == 2 ? kLaneWalk : kSplitWalk;
+    const int64_t targets = std::min<int64_t>(n_act, c->n);
+    if (targets <= 4096)
+        return kSplitWalk;
     const bool fp64_iso_tpm =
         c->P.precision == TPM_FP64 && c->P.pm_grid > 0 && !c->P.periodic;
-    return fp64_iso_tpm || 4 * n_act < c->n;
+    return (fp64_iso_tpm || 4 * n_act < c->n) ? kLaneWalk : kGroupWalk;
 }
 
 void wk::fill_args(tpm_ctx *c, const double *anorm, const Work &w, WalkArgs &A) {
@@ -348,15 +377,16 @@ int forces_into(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx,
     LA.fp32 = fp32;
     // lane-independent walks pay off where the interaction is expensive and
     // the wavefront's union of cutoff spheres is large: FP64 with TreePM
-    LA.lanes = use_lanes(c, n_act);
+    LA.variant = walk_variant(c, n_act);
     LA.K = 1;
-    if (LA.lanes) {
+    if (LA.variant == kLaneWalk) {
         // several slots per lane once there are enough wavefronts to fill the chip
         const int64_t slots_per_chip = 256 * 4 * 8;
         while (LA.K < 8 && groups / (2 * LA.K) >= 2 * slots_per_chip)
             LA.K *= 2;
     }
-    const int64_t waves = (groups + LA.K - 1) / LA.K;
+    const int64_t waves = LA.variant == kSplitWalk ? std::min<int64_t>(n_act, n)
+                                                  : (groups + LA.K - 1) / LA.K;
     LA.blocks = (unsigned)((waves + 3) / 4);
     const bool want_pot = pot != nullptr && P.want_potential;
     const int tkind = opening == TPM_OPEN_REL ? TPM_TIMER_WALK_REL : TPM_TIMER_WALK;
@@ -402,20 +432,24 @@ namespace {
 
 struct BatchReq {
     WalkArgs A;
-    uint32_t variant;  // bit 0 relative criterion, 1 TreePM, 2 lanes, 3 periodic,
-                       // 4 individual softening
+    uint32_t variant;  // bit 0 relative criterion, 1 TreePM, 3 periodic, 4 individual
+                       // softening, bits 5-6 the walk variant (wk::Variant)
     uint32_t first;    // first work item of the request
 };
 
+// The batch kernel holds the shared-cursor and lane walks only; requests
+// that take one wavefront per target are launched on their own (inlined
+// here, that walk would push the kernel's registers into heavy spills).
 template <bool FP32, bool PER, bool TPM, int OPEN, bool MIXED>
-__device__ __forceinline__ void batch_group(const WalkArgs &A, uint32_t g, bool lanes, IQ64 *Q) {
+__device__ __forceinline__ void batch_group(const WalkArgs &A, uint32_t g, uint32_t var,
+                                            IQ64 *Q) {
     if constexpr (FP32) {
-        if (lanes)
+        if (var == kLaneWalk)
             walk_lanes32<PER, TPM, OPEN, false, MIXED>(A, g, 1u);
         else
             walk_group32<PER, TPM, OPEN, false, MIXED>(A, g);
     } else {
-        if (lanes)
+        if (var == kLaneWalk)
             walk_lanes64<PER, TPM, OPEN, false, MIXED>(A, g, 1u);
         else
             walk_group64<PER, TPM, OPEN, false, MIXED>(A, g, Q);
@@ -423,7 +457,7 @@ __device__ __forceinline__ void batch_group(const WalkArgs &A, uint32_t g, bool 
 }
 
 template <bool FP32, int OPEN, bool MIXED>
-__device__ __forceinline__ void batch_geometry(const BatchReq &R, uint32_t g, bool lanes,
+__device__ __forceinline__ void batch_geometry(const BatchReq &R, uint32_t g, uint32_t lanes,
                                                IQ64 *Q) {
     if (R.variant & 8u)  // periodic box (always with the mesh)
         batch_group<FP32, true, true, OPEN, MIXED>(R.A, g, lanes, Q);
@@ -463,7 +497,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         const BatchReq &R = reqs[lo];
         const uint32_t g = item - R.first;
-        const bool lanes = (R.variant & 4u) != 0;
+        const uint32_t lanes = (R.variant >> 5) & 3u;  // walk variant
         const bool rel = (R.variant & 1u) != 0, mixed = (R.variant & 16u) != 0;
         if (rel) {
             if (mixed)
@@ -603,6 +637,13 @@ int tpm_batch_launch(tpm_batch *b) {
     }
     // stage: active sets of every request on the batch stream, FP32 first
     uint32_t items[2] = {0, 0}, nreq[2] = {0, 0};
+    struct Own {  // a request walked by a launch of its own
+        WalkArgs A;
+        Launch L;
+        int32_t opening;
+        bool mixed, periodic, tpm;
+    };
+    std::vector<Own> own;
     std::vector<size_t> order;
     for (int pass = 0; pass < 2; pass++)
         for (size_t k = 0; k < np; k++)
@@ -625,10 +666,18 @@ int tpm_batch_launch(tpm_batch *b) {
         R = BatchReq{};
         fill_args(c, p.anorm, w, R.A);
         R.variant = (p.opening == TPM_OPEN_REL ? 1u : 0u) | (c->P.pm_grid > 0 ? 2u : 0u) |
-                    (use_lanes(c, p.n_act) ? 4u : 0u) | (c->P.periodic ? 8u : 0u) |
+                    ((uint32_t)walk_variant(c, p.n_act) << 5) | (c->P.periodic ? 8u : 0u) |
                     (c->mixed ? 16u : 0u);
         R.first = items[which];
-        const int64_t groups = p.n_act > 0 ? (std::min<int64_t>(p.n_act, c->n) + 63) / 64 : 0;
+        const int64_t tg = std::min<int64_t>(p.n_act, c->n);
+        const bool split = p.n_act > 0 && walk_variant(c, p.n_act) == kSplitWalk;
+        if (split) {  // its own launch, after the staging below
+            Launch LA{c->P.precision == TPM_FP32, kSplitWalk, 1u,
+                      (unsigned)((tg + 3) / 4)};
+            own.push_back({R.A, LA, p.opening, c->mixed != 0, c->P.periodic != 0,
+                           c->P.pm_grid > 0});
+        }
+        const int64_t groups = (p.n_act > 0 && !split) ? (tg + 63) / 64 : 0;
         items[which] += (uint32_t)groups;
         nreq[which]++;
     }
@@ -651,6 +700,15 @@ int tpm_batch_launch(tpm_batch *b) {
         const uint32_t blocks = std::min<uint32_t>(max_blocks, (items[1] + 3) / 4);
         k_walk_batch<false><<<blocks, kBlock, 0, b->stream>>>(dreq + nreq[0], nreq[1], items[1],
                                                               b->counter + 1);
+        BHIP(b, hipGetLastError());
+    }
+    for (const Own &o : own) {
+        if (o.periodic)
+            dispatch_mixed<true, true>(o.A, o.L, o.opening, false, o.mixed, b->stream);
+        else if (o.tpm)
+            dispatch_mixed<false, true>(o.A, o.L, o.opening, false, o.mixed, b->stream);
+        else
+            dispatch_mixed<false, false>(o.A, o.L, o.opening, false, o.mixed, b->stream);
         BHIP(b, hipGetLastError());
     }
     // outputs in each request's caller order

@@ -976,21 +976,148 @@ __device__ __forceinline__ uint32_t wave_id() {
 // a chunk of 64 * K consecutive slots; lane l takes slots l, l + 64, ... of
 // the chunk one after the other, which evens out the lanes' work while the
 // wave's targets stay spatially close on the curve.
+//
+// FRONT (sparse active sets, too few targets to fill the chip one per lane):
+// a wavefront walks ONE target (slot `wave`).  Phase 1 takes the walk's upper
+// part breadth first: the lanes take the entries of the current frontier one
+// each; an entry whose subtree holds at most kFrontLeaf entries is set aside
+// undecided for phase 2, a larger one is decided as the sequential walk
+// decides it (interacting where it interacts) and, when it is a cube that is
+// opened, its children (found along the skip pointers) form the next
+// frontier.  A cube with more than 8 children (coincident particles in a
+// depth-21 cell) is set aside whole; phase 2 decides it again (the same
+// decision: opened).  Phase 2: lane l walks the set-aside subtrees l, l + 64,
+// ... depth first, so no lane walks more than kFrontLeaf entries per subtree
+// while the work near the target is spread over the lanes.  Every
+// interaction of the sequential walk happens once, in one lane, with the same
+// operands; the 64 partial sums are added in a fixed tree order, so results
+// are deterministic but rounded differently from the other variants
+// (interaction counts are identical).  Phase 1 expands while the frontier
+// holds at most 64 entries and at most 448 are set aside; then the rest of
+// the frontier is set aside undecided.  `front`: 2048 words of LDS per
+// wavefront (two frontiers of 512, 1024 set aside).
+constexpr uint32_t kFrontWords = 2048;
+constexpr uint32_t kFrontLeaf = 128;
 
-template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
-__device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, uint32_t K) {
+// LDS of one wavefront in kernels that run either walk: the FP64 queue or
+// the FRONT walk's frontiers.
+union WaveLds {
+    IQ64 q;
+    uint32_t front[kFrontWords];
+};
+
+// Partial sums of a wavefront's lanes to lane 0, in a fixed tree order.
+template <typename T>
+__device__ __forceinline__ void lanes_to_first(T &a0, T &a1, T &a2, T &pot, uint32_t &nint,
+                                               bool pot_on) {
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_down(a0, o);
+        a1 += __shfl_down(a1, o);
+        a2 += __shfl_down(a2, o);
+        if (pot_on)
+            pot += __shfl_down(pot, o);
+        nint += __shfl_down(nint, o);
+    }
+}
+
+// Phase 1 of the FRONT walk.  visit(e, r) decides entry e for the target
+// (with its interaction) and returns true to descend; recs(e) loads record e.
+// Leaves the final frontier in *cur (nf entries).
+__device__ __forceinline__ bool is_particle(const Rec64 &r) {
+    return (r.meta & kParticleFlag) != 0;
+}
+__device__ __forceinline__ bool is_particle(const Rec32 &r) {
+    return (r.cx_meta & kRecParticle) != 0;
+}
+
+// Exclusive prefix over the wavefront's lanes of v, and the total.
+__device__ __forceinline__ uint32_t lanes_prefix(uint32_t v, uint32_t &total) {
+    const int lane = threadIdx.x & 63;
+    uint32_t in = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(in, o);
+        if (lane >= o)
+            in += t;
+    }
+    total = __builtin_amdgcn_readfirstlane(__shfl(in, 63));
+    return in - v;
+}
+
+// Phase 1 of the FRONT walk.  visit(e, r) decides entry e for the target
+// (with its interaction) and returns true to descend.  Leaves the set-aside
+// subtrees in *aside (na entries).
+template <typename Rec, typename Visit>
+__device__ __forceinline__ void expand_front(const Rec *__restrict__ R, uint32_t *front,
+                                             uint32_t *&aside, uint32_t &na, Visit &visit) {
+    const int lane = threadIdx.x & 63;
+    uint32_t *cur = front, *nxt = front + 512;
+    aside = front + 1024;
+    na = 0u;
+    if (lane == 0)
+        cur[0] = 0u;  // the root
+    uint32_t nf = 1u;
+    wave_sync();
+    while (nf != 0u && nf <= 64u && na <= 448u) {
+        uint32_t nkid = 0u, nset = 0u, e = 0u, skip = 0u;
+        bool big = false;
+        if ((uint32_t)lane < nf) {
+            e = cur[lane];
+            const Rec r = R[e];
+            skip = r.skip;
+            if (skip - e <= kFrontLeaf) {
+                nset = 1u;  // small subtree: walked whole in phase 2
+            } else if (visit(e, r) && !is_particle(r)) {  // an opened cube
+                uint32_t c = e + 1u;
+                while (c < skip && nkid < 8u) {
+                    nkid++;
+                    c = R[c].skip;
+                }
+                big = c < skip;
+                if (big) {  // more than 8 children: set aside whole
+                    nkid = 0u;
+                    nset = 1u;
+                }
+            }
+        }
+        uint32_t tk, ts;
+        const uint32_t ok = lanes_prefix(nkid, tk);
+        const uint32_t os = lanes_prefix(nset, ts);
+        if (nset)
+            aside[na + os] = e;
+        if (nkid) {
+            uint32_t c = e + 1u;
+            for (uint32_t k = 0; k < nkid; k++) {
+                nxt[ok + k] = c;
+                c = R[c].skip;
+            }
+        }
+        wave_sync();
+        uint32_t *t = cur;
+        cur = nxt;
+        nxt = t;
+        nf = tk;
+        na += ts;
+    }
+    // the rest of the frontier (at most 512 entries), set aside undecided
+    for (uint32_t k = (uint32_t)lane; k < nf; k += 64u)
+        aside[na + k] = cur[k];
+    na += nf;
+    wave_sync();
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED, bool FRONT = false>
+__device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, uint32_t K,
+                                             uint32_t *front = nullptr) {
     const int lane = threadIdx.x & 63;
     const uint32_t nu = load_count(A.nuniq);
-    const uint32_t base = wave * 64u * K;
+    const uint32_t base = FRONT ? wave : wave * 64u * K;
     if (base >= nu)
         return;
     const uint32_t chunk_end = min(nu, base + 64u * K);
     const Rec64 *__restrict__ R = (const Rec64 *)A.rec;
-    uint32_t slot = base + lane;
-    bool live = slot < chunk_end;
     double x0 = 0.0, x1 = 0.0, x2 = 0.0, an = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0, pot = 0.0,
            hi = 0.0;
-    uint32_t self = 0, nint = 0, e = 0;
+    uint32_t self = 0, nint = 0;
     auto start = [&](uint32_t sl) {
         const uint32_t s = coherent_ld(A.act + sl);
         x0 = A.ps[s];
@@ -1003,85 +1130,123 @@ __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, u
             hi = A.hs[s];
         a0 = a1 = a2 = pot = 0.0;
         nint = 0;
-        e = 0;
     };
-    if (live)
-        start(slot);
-    while (__ballot(live)) {
-        if (live) {
-            const Rec64 r = R[e];
-            const double he = MIXED ? ((const double *)A.eh)[e] : 0.0;
-            const double d0 = wrap64<PER>(r.com[0] - x0, A.box, A.half);
-            const double d1 = wrap64<PER>(r.com[1] - x1, A.box, A.half);
-            const double d2 = wrap64<PER>(r.com[2] - x2, A.box, A.half);
-            const double dd = fma(d0, d0, fma(d1, d1, d2 * d2));
-            bool inter, step_in;
-            if (r.meta & kParticleFlag) {
-                step_in = true;
-                inter = e != self && (!TPM || dd < A.rc2);
-            } else {
-                const double L = ldexp(A.L, -(int)(r.meta & 0xffu));
-                const double c0 = wrap64<PER>(r.cen[0] - x0, A.box, A.half);
-                const double c1 = wrap64<PER>(r.cen[1] - x1, A.box, A.half);
-                const double c2 = wrap64<PER>(r.cen[2] - x2, A.box, A.half);
-                bool discard = false;
-                if (TPM) {
-                    const double hl = 0.5 * L;
-                    double e0 = fabs(c0) - hl, e1 = fabs(c1) - hl, e2 = fabs(c2) - hl;
-                    e0 = e0 > 0.0 ? e0 : 0.0;
-                    e1 = e1 > 0.0 ? e1 : 0.0;
-                    e2 = e2 > 0.0 ? e2 : 0.0;
-                    discard = fma(e0, e0, fma(e1, e1, e2 * e2)) > A.rc2;
-                }
-                bool open = false;
-                if (!discard) {
-                    if (OPEN == TPM_OPEN_BH)
-                        open = (L * L) > A.theta2 * dd;
-                    else
-                        open = (A.G * r.mass) * (L * L) > (A.alpha * an) * (dd * dd);
-                    const double lim = 0.6 * L;
-                    if (fabs(c0) < lim && fabs(c1) < lim && fabs(c2) < lim)
-                        open = true;
-                    if (MIXED && hi < he && dd < he * he)
-                        open = true;
-                }
-                step_in = open;
-                inter = !discard && !open;
+    // entry e for this lane's target: the decision and the interaction, as
+    // in a sequential walk; true: descend into e
+    auto visit = [&](uint32_t e, const Rec64 &r) -> bool {
+        const double he = MIXED ? ((const double *)A.eh)[e] : 0.0;
+        const double d0 = wrap64<PER>(r.com[0] - x0, A.box, A.half);
+        const double d1 = wrap64<PER>(r.com[1] - x1, A.box, A.half);
+        const double d2 = wrap64<PER>(r.com[2] - x2, A.box, A.half);
+        const double dd = fma(d0, d0, fma(d1, d1, d2 * d2));
+        bool inter, step_in;
+        if (r.meta & kParticleFlag) {
+            step_in = true;
+            inter = e != self && (!TPM || dd < A.rc2);
+        } else {
+            const double L = ldexp(A.L, -(int)(r.meta & 0xffu));
+            const double c0 = wrap64<PER>(r.cen[0] - x0, A.box, A.half);
+            const double c1 = wrap64<PER>(r.cen[1] - x1, A.box, A.half);
+            const double c2 = wrap64<PER>(r.cen[2] - x2, A.box, A.half);
+            bool discard = false;
+            if (TPM) {
+                const double hl = 0.5 * L;
+                double e0 = fabs(c0) - hl, e1 = fabs(c1) - hl, e2 = fabs(c2) - hl;
+                e0 = e0 > 0.0 ? e0 : 0.0;
+                e1 = e1 > 0.0 ? e1 : 0.0;
+                e2 = e2 > 0.0 ? e2 : 0.0;
+                discard = fma(e0, e0, fma(e1, e1, e2 * e2)) > A.rc2;
             }
-            if (inter) {
-                interact64<TPM, POT, MIXED>(A, r.mass, d0, d1, d2, dd, hi > he ? hi : he, a0, a1,
-                                            a2, pot);
-                nint++;
+            bool open = false;
+            if (!discard) {
+                if (OPEN == TPM_OPEN_BH)
+                    open = (L * L) > A.theta2 * dd;
+                else
+                    open = (A.G * r.mass) * (L * L) > (A.alpha * an) * (dd * dd);
+                const double lim = 0.6 * L;
+                if (fabs(c0) < lim && fabs(c1) < lim && fabs(c2) < lim)
+                    open = true;
+                if (MIXED && hi < he && dd < he * he)
+                    open = true;
             }
-            e = step_in ? e + 1u : r.skip;
-            if (e >= A.E) {
-                store_result<double>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
-                slot += 64u;
-                live = slot < chunk_end;
-                if (live)
-                    start(slot);
+            step_in = open;
+            inter = !discard && !open;
+        }
+        if (inter) {
+            interact64<TPM, POT, MIXED>(A, r.mass, d0, d1, d2, dd, hi > he ? hi : he, a0, a1,
+                                        a2, pot);
+            nint++;
+        }
+        return step_in;
+    };
+    if constexpr (!FRONT) {
+        uint32_t slot = base + lane;
+        bool live = slot < chunk_end;
+        uint32_t e = 0;
+        if (live)
+            start(slot);
+        while (__ballot(live)) {
+            if (live) {
+                const Rec64 r = R[e];
+                e = visit(e, r) ? e + 1u : r.skip;
+                if (e >= A.E) {
+                    store_result<double>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
+                    slot += 64u;
+                    live = slot < chunk_end;
+                    e = 0;
+                    if (live)
+                        start(slot);
+                }
             }
         }
+    } else {
+        start(base);
+        uint32_t *cur, nf;  // the set-aside subtrees
+        expand_front<Rec64>(R, front, cur, nf, visit);
+        // phase 2: the set-aside subtrees lane, lane + 64, ...
+        uint32_t k = (uint32_t)lane;
+        bool live = k < nf;
+        uint32_t e = 0, end = 0;
+        if (live) {
+            e = cur[k];
+            end = R[e].skip;
+        }
+        while (__ballot(live)) {
+            if (live) {
+                const Rec64 r = R[e];
+                e = visit(e, r) ? e + 1u : r.skip;
+                if (e >= end) {
+                    k += 64u;
+                    live = k < nf;
+                    if (live) {
+                        e = cur[k];
+                        end = R[e].skip;
+                    }
+                }
+            }
+        }
+        lanes_to_first(a0, a1, a2, pot, nint, POT);
+        if (lane == 0)
+            store_result<double>(A.res, A.rpot, base, a0, a1, a2, POT, pot, nint);
     }
 }
 
-template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
-__device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, uint32_t K) {
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED, bool FRONT = false>
+__device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, uint32_t K,
+                                             uint32_t *front = nullptr) {
     const int lane = threadIdx.x & 63;
     const uint32_t nu = load_count(A.nuniq);
-    const uint32_t base = wave * 64u * K;
+    const uint32_t base = FRONT ? wave : wave * 64u * K;
     if (base >= nu)
         return;
     const uint32_t chunk_end = min(nu, base + 64u * K);
     const Rec32 *__restrict__ R = (const Rec32 *)A.rec;
     const double len21 = ldexp(A.L, -kMaxLevel);
-    uint32_t slot = base + lane;
-    bool live = slot < chunk_end;
     constexpr int SH = PER ? kRecShiftPer : kRecShiftIso;
     int32_t G0 = 0, G1 = 0, G2 = 0;
     float xr0 = 0.f, xr1 = 0.f, xr2 = 0.f, alpha_an = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f,
           pot = 0.f, hi = 0.f;
-    uint32_t self = 0, nint = 0, e = 0;
+    uint32_t self = 0, nint = 0;
     auto start = [&](uint32_t sl) {
         const uint32_t s = coherent_ld(A.act + sl);
         const uint64_t qq = A.qs[s];
@@ -1101,62 +1266,104 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
             hi = (float)A.hs[s];
         a0 = a1 = a2 = pot = 0.f;
         nint = 0;
-        e = 0;
     };
-    if (live)
-        start(slot);
-    while (__ballot(live)) {
-        if (live) {
-            const Rec32 r = R[e];
-            const float he = MIXED ? ((const float *)A.eh)[e] : 0.0f;
-            const int32_t cm = r.cx_meta;
-            const float c0 = fmaf((float)wsub(cm & -(1 << SH), G0), A.fu, -xr0);
-            const float c1 = fmaf((float)wsub(r.cy, G1), A.fu, -xr1);
-            const float c2 = fmaf((float)wsub(r.cz, G2), A.fu, -xr2);
-            const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
-            const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-            const bool part = (cm & kRecParticle) != 0;
-            const float L = __builtin_amdgcn_ldexpf(A.fL, -(cm & kRecLevel));
-            bool discard = false;
-            if (TPM) {
-                const float hl = 0.5f * L;
-                const float e0 = fmaxf(fabsf(c0) - hl, 0.0f);
-                const float e1 = fmaxf(fabsf(c1) - hl, 0.0f);
-                const float e2 = fmaxf(fabsf(c2) - hl, 0.0f);
-                discard = !part && fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) > A.frc2;
-            }
-            const float L2 = L * L;
-            bool crit;
-            if (OPEN == TPM_OPEN_BH)
-                crit = L2 > A.ftheta2 * dd;
-            else
-                crit = r.gm * L2 > alpha_an * (dd * dd);
-            const float lim = 0.6f * L;
-            const bool box = fabsf(c0) < lim && fabsf(c1) < lim && fabsf(c2) < lim;
-            const bool soft_open = MIXED && hi < he && dd < he * he;
-            const bool open = !part && !discard && (crit || box || soft_open);
-            const bool inter = part ? (e != self && (!TPM || dd < A.frc2)) : (!discard && !open);
-            if (inter) {
-                interact32<TPM, POT, MIXED>(A, r.gm, d0, d1, d2, dd, hi > he ? hi : he, a0, a1,
-                                            a2, pot);
-                nint++;
-            }
-            e = (part || open) ? e + 1u : r.skip;
-            if (e >= A.E) {
-                store_result<float>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
-                slot += 64u;
-                live = slot < chunk_end;
-                if (live)
-                    start(slot);
+    // entry e for this lane's target: the decision and the interaction, as
+    // in a sequential walk; true: descend into e
+    auto visit = [&](uint32_t e, const Rec32 &r) -> bool {
+        const float he = MIXED ? ((const float *)A.eh)[e] : 0.0f;
+        const int32_t cm = r.cx_meta;
+        const float c0 = fmaf((float)wsub(cm & -(1 << SH), G0), A.fu, -xr0);
+        const float c1 = fmaf((float)wsub(r.cy, G1), A.fu, -xr1);
+        const float c2 = fmaf((float)wsub(r.cz, G2), A.fu, -xr2);
+        const float d0 = c0 + r.dx, d1 = c1 + r.dy, d2 = c2 + r.dz;
+        const float dd = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+        const bool part = (cm & kRecParticle) != 0;
+        const float L = __builtin_amdgcn_ldexpf(A.fL, -(cm & kRecLevel));
+        bool discard = false;
+        if (TPM) {
+            const float hl = 0.5f * L;
+            const float e0 = fmaxf(fabsf(c0) - hl, 0.0f);
+            const float e1 = fmaxf(fabsf(c1) - hl, 0.0f);
+            const float e2 = fmaxf(fabsf(c2) - hl, 0.0f);
+            discard = !part && fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) > A.frc2;
+        }
+        const float L2 = L * L;
+        bool crit;
+        if (OPEN == TPM_OPEN_BH)
+            crit = L2 > A.ftheta2 * dd;
+        else
+            crit = r.gm * L2 > alpha_an * (dd * dd);
+        const float lim = 0.6f * L;
+        const bool box = fabsf(c0) < lim && fabsf(c1) < lim && fabsf(c2) < lim;
+        const bool soft_open = MIXED && hi < he && dd < he * he;
+        const bool open = !part && !discard && (crit || box || soft_open);
+        const bool inter = part ? (e != self && (!TPM || dd < A.frc2)) : (!discard && !open);
+        if (inter) {
+            interact32<TPM, POT, MIXED>(A, r.gm, d0, d1, d2, dd, hi > he ? hi : he, a0, a1, a2,
+                                        pot);
+            nint++;
+        }
+        return part || open;
+    };
+    if constexpr (!FRONT) {
+        uint32_t slot = base + lane;
+        bool live = slot < chunk_end;
+        uint32_t e = 0;
+        if (live)
+            start(slot);
+        while (__ballot(live)) {
+            if (live) {
+                const Rec32 r = R[e];
+                e = visit(e, r) ? e + 1u : r.skip;
+                if (e >= A.E) {
+                    store_result<float>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
+                    slot += 64u;
+                    live = slot < chunk_end;
+                    e = 0;
+                    if (live)
+                        start(slot);
+                }
             }
         }
+    } else {
+        start(base);
+        uint32_t *cur, nf;  // the set-aside subtrees
+        expand_front<Rec32>(R, front, cur, nf, visit);
+        // phase 2: the set-aside subtrees lane, lane + 64, ...
+        uint32_t k = (uint32_t)lane;
+        bool live = k < nf;
+        uint32_t e = 0, end = 0;
+        if (live) {
+            e = cur[k];
+            end = R[e].skip;
+        }
+        while (__ballot(live)) {
+            if (live) {
+                const Rec32 r = R[e];
+                e = visit(e, r) ? e + 1u : r.skip;
+                if (e >= end) {
+                    k += 64u;
+                    live = k < nf;
+                    if (live) {
+                        e = cur[k];
+                        end = R[e].skip;
+                    }
+                }
+            }
+        }
+        lanes_to_first(a0, a1, a2, pot, nint, POT);
+        if (lane == 0)
+            store_result<float>(A.res, A.rpot, base, a0, a1, a2, POT, pot, nint);
     }
 }
 
 // Host side (walk.hip): the walk arguments of one call from the context and
 // its working memory, and the choice of the lane-independent walk.
 void fill_args(tpm_ctx *c, const double *anorm, const Work &w, WalkArgs &A);
-bool use_lanes(const tpm_ctx *c, int64_t n_act);
+// Walk variant for an active set of n_act: shared cursor (64 targets per
+// wavefront), independent lanes, or one wavefront per target (FRONT).
+enum Variant : uint32_t { kGroupWalk = 0, kLaneWalk = 1, kSplitWalk = 2 };
+Variant walk_variant(const tpm_ctx *c, int64_t n_act);
 
 }  // namespace wk
 }  // namespace tpm

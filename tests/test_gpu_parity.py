@@ -238,7 +238,9 @@ def test_walk_variants_identical(case, prec, monkeypatch):
     """The shared-cursor walk and the independent-lane walk visit each
     target's entries in the same depth-first order with the same arithmetic:
     accelerations, potentials and interaction counts are bit-identical, on
-    the full set and on a sparse subset (ragged last wavefront)."""
+    the full set and on a sparse subset (ragged last wavefront).  The walk
+    with one wavefront per target (64 ranges of the depth-first sequence)
+    makes the same interactions, summed in another order."""
     mk, kw, opening = FORCE_CASES[case]
     p = mk()
     eps = _case_eps(p, kw)
@@ -251,7 +253,7 @@ def test_walk_variants_identical(case, prec, monkeypatch):
     sets = [np.arange(p.n), np.random.default_rng(17).choice(p.n, max(1, p.n // 7 + 5),
                                                              replace=False)]
     out = {}
-    for mode in ("1", "2"):
+    for mode in ("1", "2", "3"):
         monkeypatch.setenv("TPM_WALK_MODE", mode)
         ctx = _ctx(precision=prec, want_potential=True, **kw)
         _build(ctx, p, eps)
@@ -266,6 +268,17 @@ def test_walk_variants_identical(case, prec, monkeypatch):
     for k in range(len(sets)):
         for a, b in zip(out["1"][k], out["2"][k]):
             assert torch.equal(a, b), (case, prec, k)
+        # one wavefront per target: the same interactions (identical counts),
+        # partial sums of 64 ranges added in another order
+        acc1, pot1, n1 = out["1"][k]
+        acc3, pot3, n3 = out["3"][k]
+        assert torch.equal(n1, n3), (case, prec, k)
+        u = 2.0 ** (-24 if prec == "fp32" else -53)
+        mag = acc1.double().norm(dim=0)
+        scale = mag.clamp_min(float(mag.square().mean().sqrt()))  # no small-|a| blow-up
+        err = (acc3.double() - acc1.double()).norm(dim=0) / scale
+        # rounding of two summation orders of at most n_int terms
+        assert float(err.max()) <= 64 * u * float(n1.max()), (case, prec, k, float(err.max()))
 
 
 @pytest.mark.parametrize("case", ["plummer_bh", "plummer_rel", "box_bh", "box_clustered",
@@ -294,17 +307,31 @@ def test_fp32_against_fp64(case):
 
 
 def test_active_subsets_and_duplicates():
+    """A subset's forces are the full set's at the same targets: bit for bit
+    where both take the same walk variant (the lane walk is bit-identical to
+    the shared cursor), to rounding where the subset takes one wavefront per
+    target (at most 4096 targets: the same interactions summed in another
+    order; interaction counts identical)."""
     p = W.plummer(6000, 12)
     ctx = _ctx(eps=0.01, want_potential=True)
     _build(ctx, p)
-    full, fpot = ctx.compute_forces(_t(np.arange(p.n), torch.int32), "bh")
+    nfull = torch.empty(p.n, dtype=torch.int32, device=_dev())
+    full, fpot = ctx.compute_forces(_t(np.arange(p.n), torch.int32), "bh", n_interactions=nfull)
     full = full.cpu().numpy()
+    nfull = nfull.cpu().numpy()
+    rms = float(np.sqrt(np.mean(np.sum(full * full, axis=0))))
     rng = np.random.default_rng(3)
-    for frac in (0.001, 0.05, 0.5):
+    for frac in (0.001, 0.05, 0.5, 0.9):
         sub = rng.choice(p.n, max(1, int(frac * p.n)), replace=False)
         sub = np.concatenate([sub, sub[:3]])  # duplicates
-        acc, _ = ctx.compute_forces(_t(sub, torch.int32), "bh")
-        assert np.array_equal(acc.cpu().numpy(), full[:, sub])
+        nint = torch.empty(sub.size, dtype=torch.int32, device=_dev())
+        acc, _ = ctx.compute_forces(_t(sub, torch.int32), "bh", n_interactions=nint)
+        acc = acc.cpu().numpy()
+        assert np.array_equal(nint.cpu().numpy(), nfull[sub])
+        if sub.size > 4096:
+            assert np.array_equal(acc, full[:, sub])
+        else:
+            assert np.abs(acc - full[:, sub]).max() <= 1e-13 * rms
     # empty active set is a no-op
     acc, _ = ctx.compute_forces(_t(np.zeros(0), torch.int32), "bh")
     assert acc.shape == (3, 0)
