@@ -385,7 +385,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(
 // curve order -- M = (M1 + M2) + ..., X = fma(M_k, s_k, X), s = X / M -- and
 // set the node's particle count, skip pointer and leaf-parent flag.  With individual
 // softening the node also takes the largest spline support of its children.
+// The particle count follows from the first particles of the node and of the
+// entry after its subtree (particles of a subtree are consecutive on the
+// curve), so the children's counts are not read.
 __global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uint32_t E,
+                                                    uint32_t n, const uint32_t *__restrict__ efirst,
                                                     uint32_t *__restrict__ ecount,
                                                     const uint32_t *__restrict__ list,
                                                     uint32_t count, uint32_t lev,
@@ -395,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uin
         return;
     const uint32_t e = list[i];
     double M = 0.0, X0 = 0.0, X1 = 0.0, X2 = 0.0, hmax = 0.0;
-    uint32_t cnt = 0, k = e + 1;
+    uint32_t k = e + 1;
     while (k < E && (rec[k].meta & 0xffu) > lev) {
         if (eh)
             hmax = eh[k] > hmax ? eh[k] : hmax;
@@ -404,9 +408,9 @@ __global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uin
         X0 = fma(mk, rec[k].com[0], X0);
         X1 = fma(mk, rec[k].com[1], X1);
         X2 = fma(mk, rec[k].com[2], X2);
-        cnt += ecount[k];
         k = rec[k].skip;
     }
+    const uint32_t cnt = (k < E ? efirst[k] : n) - efirst[e];
     rec[e].mass = M;
     rec[e].com[0] = X0 / M;
     rec[e].com[1] = X1 / M;
@@ -604,7 +608,8 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
         if (!cnt)
             continue;
         k_moments<<<grid_for(cnt, kBlock), kBlock, 0, st>>>(
-            rec, E, (uint32_t *)c->ecount.p, (const uint32_t *)c->lvl_list.p + c->level_off[l],
+            rec, E, (uint32_t)n, (const uint32_t *)c->efirst.p, (uint32_t *)c->ecount.p,
+            (const uint32_t *)c->lvl_list.p + c->level_off[l],
             cnt, (uint32_t)l, eh);
         TPM_LAUNCHED(c, "k_moments");
     }
