@@ -425,10 +425,13 @@ def pass_bytes(n, E, ng, prec, periodic, masses=False):
     b["topology"] = (13 * n + 16 * n + (8 + 1 + 4 + 24 + 8 + 8) * n + 72 * E + 4 * n
                      + 4 * nodes)
     # moments: every entry read once as a child, every node written with its
-    # count; FP32 records: every record, first word and coordinate read, 32 B out
+    # count
     b["moments"] = 64 * E + 4 * E + 68 * nodes
     if prec == "fp32":
-        b["moments"] += (64 + 4 + 8 + 32) * E
+        # FP32 records: the emission writes a particle's whole (32 B) and a
+        # node's integer centre (12 B); the moments read and complete a node's
+        b["topology"] += 32 * n + 12 * nodes
+        b["moments"] += 64 * nodes
     if ng:
         M = ng if periodic else 2 * ng
         m3 = M ** 3

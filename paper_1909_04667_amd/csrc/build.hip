@@ -295,11 +295,30 @@ __device__ __forceinline__ uint64_t prefix_at(uint64_t k, int lev) {
     return k >> (3 * (kMaxLevel - lev));
 }
 
+// FP32 record of an entry: exact integer centre of its cell at level lev
+// (units of L 2^-22, shifted left by sh so that 32-bit differences wrap
+// modulo a periodic box), level and particle flag in the freed low bits of x.
+__device__ __forceinline__ void rec32_centre(Rec32 &o, const uint32_t q[3], int lev, int sh,
+                                             bool part) {
+    int32_t C[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const uint32_t P = q[a] >> (kBits - lev);
+        C[a] = (int32_t)(((2u * P + 1u) << (kBits - lev)));
+    }
+    o.cx_meta = (int32_t)((uint32_t)C[0] << sh) | lev | (part ? kRecParticle : 0);
+    o.cy = (int32_t)((uint32_t)C[1] << sh);
+    o.cz = (int32_t)((uint32_t)C[2] << sh);
+}
+
 // Emit the particle entry and the node entries a particle starts.  Skip
 // pointers and counts of nodes are filled bottom-up by k_moments: every
 // entry carries a depth (nodes: their level; a particle: the level of the
 // cell it occupies alone, one below its deepest shared prefix), and the
 // subtree of a node of level l ends at the first later entry of depth <= l.
+// FP32 contexts (out32 set): a particle's FP32 record is written whole here,
+// a node's integer centre and level (its offsets, G m, skip and leaf-parent
+// flag follow from k_moments).
 __global__ __launch_bounds__(kBlock) void k_emit(
     const uint64_t *__restrict__ key, int64_t n, const int8_t *__restrict__ dR,
     const uint32_t *__restrict__ base, const Frame *__restrict__ Fp,
@@ -307,7 +326,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     const uint64_t *__restrict__ qs, Rec64 *__restrict__ rec, uint32_t *__restrict__ efirst,
     uint32_t *__restrict__ ecount, uint32_t *__restrict__ pe,
     const uint32_t *__restrict__ loff, uint32_t nb, uint32_t *__restrict__ lvl_list,
-    const double *__restrict__ hs, double *__restrict__ eh) {
+    const double *__restrict__ hs, double *__restrict__ eh, double G, Rec32 *__restrict__ out32,
+    float *__restrict__ eh32) {
     __shared__ uint32_t h[kLevels][kBlock / 64];
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool live = s < n;
@@ -339,6 +359,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(
         return;
     const Frame F = *Fp;
     const uint32_t ep = b + (uint32_t)nn;
+    const int sh = F.periodic ? kRecShiftPer : kRecShiftIso;
+    const uint64_t qq = qs[s];
+    const uint32_t q[3] = {(uint32_t)(qq >> 42) & 0x1fffffu, (uint32_t)(qq >> 21) & 0x1fffffu,
+                           (uint32_t)qq & 0x1fffffu};
     {
         Rec64 R;
         R.com[0] = ps[s];
@@ -356,12 +380,22 @@ __global__ __launch_bounds__(kBlock) void k_emit(
         pe[s] = ep;
         if (eh)
             eh[ep] = hs[s];
+        if (out32) {  // offset from the centre of its depth-21 cell
+            Rec32 o;
+            rec32_centre(o, q, kMaxLevel, sh, true);
+            const double len = ldexp(F.L, -kMaxLevel);
+            o.dx = (float)(R.com[0] - (F.x0[0] + ((double)q[0] + 0.5) * len));
+            o.dy = (float)(R.com[1] - (F.x0[1] + ((double)q[1] + 0.5) * len));
+            o.dz = (float)(R.com[2] - (F.x0[2] + ((double)q[2] + 0.5) * len));
+            o.gm = (float)(G * R.mass);
+            o.skip = R.skip;
+            out32[ep] = o;
+            if (eh32)
+                eh32[ep] = (float)hs[s];
+        }
     }
     if (nn == 0)
         return;
-    const uint64_t qq = qs[s];
-    const uint32_t q[3] = {(uint32_t)(qq >> 42) & 0x1fffffu, (uint32_t)(qq >> 21) & 0x1fffffu,
-                           (uint32_t)qq & 0x1fffffu};
     for (int lev = l + 1; lev <= r; ++lev) {
         const uint32_t e = b + (uint32_t)(lev - l - 1);
         Rec64 R;
@@ -377,6 +411,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(
         R.meta = (uint32_t)lev;
         rec[e] = R;
         efirst[e] = (uint32_t)s;
+        if (out32) {
+            Rec32 o{};
+            rec32_centre(o, q, lev, sh, false);
+            out32[e] = o;
+        }
     }
 }
 
@@ -388,12 +427,16 @@ __global__ __launch_bounds__(kBlock) void k_emit(
 // The particle count follows from the first particles of the node and of the
 // entry after its subtree (particles of a subtree are consecutive on the
 // curve), so the children's counts are not read.
+// FP32 contexts (out32 set): the node's FP32 record is completed (offset of
+// the centre of mass from the cell centre, G m, skip, leaf-parent flag).
 __global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uint32_t E,
                                                     uint32_t n, const uint32_t *__restrict__ efirst,
                                                     uint32_t *__restrict__ ecount,
                                                     const uint32_t *__restrict__ list,
                                                     uint32_t count, uint32_t lev,
-                                                    double *__restrict__ eh) {
+                                                    double *__restrict__ eh, double G,
+                                                    Rec32 *__restrict__ out32,
+                                                    float *__restrict__ eh32) {
     uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= count)
         return;
@@ -411,61 +454,32 @@ __global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uin
         k = rec[k].skip;
     }
     const uint32_t cnt = (k < E ? efirst[k] : n) - efirst[e];
+    const double s0 = X0 / M, s1 = X1 / M, s2 = X2 / M;
     rec[e].mass = M;
-    rec[e].com[0] = X0 / M;
-    rec[e].com[1] = X1 / M;
-    rec[e].com[2] = X2 / M;
+    rec[e].com[0] = s0;
+    rec[e].com[1] = s1;
+    rec[e].com[2] = s2;
     rec[e].skip = k;
     ecount[e] = cnt;
-    if (k - e - 1u == cnt)  // no entry below but the particles themselves
+    const bool leaf_parent = k - e - 1u == cnt;  // no entry below but the particles themselves
+    if (leaf_parent)
         rec[e].meta |= kLeafParentFlag;
     if (eh)
         eh[e] = hmax;
+    if (out32) {
+        Rec32 o = out32[e];  // integer centre and level from k_emit
+        o.dx = (float)(s0 - rec[e].cen[0]);
+        o.dy = (float)(s1 - rec[e].cen[1]);
+        o.dz = (float)(s2 - rec[e].cen[2]);
+        o.gm = (float)(G * M);
+        o.cx_meta |= leaf_parent ? kRecLeafParent : 0;
+        o.skip = k;
+        out32[e] = o;
+        if (eh32)
+            eh32[e] = (float)hmax;
+    }
 }
 
-// FP32 records: exact integer centres, float offsets of the centre of mass.
-__global__ __launch_bounds__(kBlock) void k_pack32(const Rec64 *__restrict__ rec, uint32_t E,
-                                                   const uint32_t *__restrict__ efirst,
-                                                   const uint64_t *__restrict__ qs,
-                                                   const Frame *__restrict__ Fp, double G,
-                                                   Rec32 *__restrict__ out,
-                                                   const double *__restrict__ eh,
-                                                   float *__restrict__ eh32) {
-    uint32_t e = blockIdx.x * kBlock + threadIdx.x;
-    if (e >= E)
-        return;
-    if (eh)
-        eh32[e] = (float)eh[e];
-    const Frame F = *Fp;
-    const Rec64 R = rec[e];
-    const bool part = (R.meta & kParticleFlag) != 0;
-    const int lev = part ? kMaxLevel : (int)(R.meta & 0xffu);
-    const uint64_t qq = qs[efirst[e]];
-    const uint32_t q[3] = {(uint32_t)(qq >> 42) & 0x1fffffu, (uint32_t)(qq >> 21) & 0x1fffffu,
-                           (uint32_t)qq & 0x1fffffu};
-    int32_t C[3];
-    double off[3];
-    const double len = ldexp(F.L, -lev);
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const uint32_t P = q[a] >> (kBits - lev);
-        C[a] = (int32_t)(((2u * P + 1u) << (kBits - lev)));
-        const double cen = F.x0[a] + ((double)P + 0.5) * len;
-        off[a] = R.com[a] - cen;
-    }
-    const int sh = F.periodic ? kRecShiftPer : kRecShiftIso;
-    Rec32 o;
-    o.dx = (float)off[0];
-    o.dy = (float)off[1];
-    o.dz = (float)off[2];
-    o.gm = (float)(G * R.mass);
-    o.cx_meta = (int32_t)((uint32_t)C[0] << sh) | lev | (part ? kRecParticle : 0) |
-                ((R.meta & kLeafParentFlag) ? kRecLeafParent : 0);
-    o.cy = (int32_t)((uint32_t)C[1] << sh);
-    o.cz = (int32_t)((uint32_t)C[2] << sh);
-    o.skip = R.skip;
-    out[e] = o;
-}
 
 }  // namespace
 
@@ -588,6 +602,17 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
     TPM_TRY(ensure(c, c->ecount, (size_t)E * 4));
     TPM_TRY(ensure(c, c->lvl_list, (size_t)(off > 0 ? off : 1) * 4));
     Rec64 *rec = (Rec64 *)c->rec64.p;
+    // FP32 records: written by the emission and completed by the moments
+    Rec32 *rec32 = nullptr;
+    float *eh32 = nullptr;
+    if (P.precision == TPM_FP32) {
+        TPM_TRY(ensure(c, c->rec32, (size_t)E * sizeof(Rec32)));
+        rec32 = (Rec32 *)c->rec32.p;
+        if (c->mixed) {
+            TPM_TRY(ensure(c, c->eh32, (size_t)E * 4));
+            eh32 = (float *)c->eh32.p;
+        }
+    }
     double *eh = nullptr;
     if (c->mixed) {
         TPM_TRY(ensure(c, c->eh64, (size_t)E * 8));
@@ -598,7 +623,7 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
         key, n, (const int8_t *)c->dR.p, (const uint32_t *)c->base.p, F,
         (const double *)c->ps.p, (const double *)c->ms.p, (const uint64_t *)c->qs.p, rec,
         (uint32_t *)c->efirst.p, (uint32_t *)c->ecount.p, (uint32_t *)c->pe.p, loff, nb,
-        (uint32_t *)c->lvl_list.p, (const double *)c->hs.p, eh);
+        (uint32_t *)c->lvl_list.p, (const double *)c->hs.p, eh, P.G, rec32, eh32);
     TPM_LAUNCHED(c, "k_emit");
     TPM_TRY(timer_end(c, TPM_TIMER_TOPOLOGY));
     // 5. moments, deepest level first
@@ -610,17 +635,8 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
         k_moments<<<grid_for(cnt, kBlock), kBlock, 0, st>>>(
             rec, E, (uint32_t)n, (const uint32_t *)c->efirst.p, (uint32_t *)c->ecount.p,
             (const uint32_t *)c->lvl_list.p + c->level_off[l],
-            cnt, (uint32_t)l, eh);
+            cnt, (uint32_t)l, eh, P.G, rec32, eh32);
         TPM_LAUNCHED(c, "k_moments");
-    }
-    if (P.precision == TPM_FP32) {
-        TPM_TRY(ensure(c, c->rec32, (size_t)E * sizeof(Rec32)));
-        if (c->mixed)
-            TPM_TRY(ensure(c, c->eh32, (size_t)E * 4));
-        k_pack32<<<grid_for(E, kBlock), kBlock, 0, st>>>(
-            rec, E, (const uint32_t *)c->efirst.p, (const uint64_t *)c->qs.p, F, P.G,
-            (Rec32 *)c->rec32.p, eh, c->mixed ? (float *)c->eh32.p : nullptr);
-        TPM_LAUNCHED(c, "k_pack32");
     }
     TPM_TRY(timer_end(c, TPM_TIMER_MOMENTS));
     c->n = n;

@@ -430,7 +430,6 @@ __device__ __forceinline__ void item_pm(const SrvReq &R, uint32_t it, uint32_t n
 template <typename T>
 __device__ __forceinline__ void item_norm(const SrvReq &R, uint32_t it, uint32_t nu) {
     const int lane = threadIdx.x & 63;
-    const uint32_t n = R.A.n;
     const T *a = (const T *)R.A.res, *b = (const T *)R.res_pm;
     const bool mesh = (R.flags & kMesh) != 0;
     for (uint32_t k = it * kSrvSlots + lane; k < min(nu, (it + 1) * kSrvSlots); k += 64) {
