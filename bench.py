@@ -428,10 +428,10 @@ def pass_bytes(n, E, ng, prec, periodic, masses=False):
     # count
     b["moments"] = 64 * E + 4 * E + 68 * nodes
     if prec == "fp32":
-        # FP32 records: the emission writes a particle's whole (32 B) and a
-        # node's integer centre (12 B); the moments read and complete a node's
-        b["topology"] += 32 * n + 12 * nodes
-        b["moments"] += 64 * nodes
+        # FP32 records: the emission writes a particle's (32 B), the moments a
+        # node's (its first particle's packed coordinates in, 32 B out)
+        b["topology"] += 32 * n
+        b["moments"] += (8 + 32) * nodes
     if ng:
         M = ng if periodic else 2 * ng
         m3 = M ** 3

@@ -316,9 +316,8 @@ __device__ __forceinline__ void rec32_centre(Rec32 &o, const uint32_t q[3], int 
 // entry carries a depth (nodes: their level; a particle: the level of the
 // cell it occupies alone, one below its deepest shared prefix), and the
 // subtree of a node of level l ends at the first later entry of depth <= l.
-// FP32 contexts (out32 set): a particle's FP32 record is written whole here,
-// a node's integer centre and level (its offsets, G m, skip and leaf-parent
-// flag follow from k_moments).
+// FP32 contexts (out32 set): a particle's FP32 record is written here, a
+// node's by k_moments.
 __global__ __launch_bounds__(kBlock) void k_emit(
     const uint64_t *__restrict__ key, int64_t n, const int8_t *__restrict__ dR,
     const uint32_t *__restrict__ base, const Frame *__restrict__ Fp,
@@ -411,11 +410,6 @@ __global__ __launch_bounds__(kBlock) void k_emit(
         R.meta = (uint32_t)lev;
         rec[e] = R;
         efirst[e] = (uint32_t)s;
-        if (out32) {
-            Rec32 o{};
-            rec32_centre(o, q, lev, sh, false);
-            out32[e] = o;
-        }
     }
 }
 
@@ -427,20 +421,27 @@ __global__ __launch_bounds__(kBlock) void k_emit(
 // The particle count follows from the first particles of the node and of the
 // entry after its subtree (particles of a subtree are consecutive on the
 // curve), so the children's counts are not read.
-// FP32 contexts (out32 set): the node's FP32 record is completed (offset of
-// the centre of mass from the cell centre, G m, skip, leaf-parent flag).
+// FP32 contexts (out32 set): the node's FP32 record is written too (exact
+// integer centre from its first particle's cell, float offset of the centre of
+// mass from it, G m, skip, leaf-parent flag).
 __global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uint32_t E,
                                                     uint32_t n, const uint32_t *__restrict__ efirst,
                                                     uint32_t *__restrict__ ecount,
                                                     const uint32_t *__restrict__ list,
                                                     uint32_t count, uint32_t lev,
                                                     double *__restrict__ eh, double G,
+                                                    const uint64_t *__restrict__ qs, int sh,
                                                     Rec32 *__restrict__ out32,
                                                     float *__restrict__ eh32) {
     uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= count)
         return;
     const uint32_t e = list[i];
+    // what does not depend on the children first, so that its loads overlap
+    // the walk over them
+    Rec64 R = rec[e];
+    const uint32_t f = efirst[e];
+    const uint64_t qq = out32 ? qs[f] : 0ull;
     double M = 0.0, X0 = 0.0, X1 = 0.0, X2 = 0.0, hmax = 0.0;
     uint32_t k = e + 1;
     while (k < E && (rec[k].meta & 0xffu) > lev) {
@@ -453,24 +454,26 @@ __global__ __launch_bounds__(kBlock) void k_moments(Rec64 *__restrict__ rec, uin
         X2 = fma(mk, rec[k].com[2], X2);
         k = rec[k].skip;
     }
-    const uint32_t cnt = (k < E ? efirst[k] : n) - efirst[e];
-    const double s0 = X0 / M, s1 = X1 / M, s2 = X2 / M;
-    rec[e].mass = M;
-    rec[e].com[0] = s0;
-    rec[e].com[1] = s1;
-    rec[e].com[2] = s2;
-    rec[e].skip = k;
-    ecount[e] = cnt;
+    const uint32_t cnt = (k < E ? efirst[k] : n) - f;
     const bool leaf_parent = k - e - 1u == cnt;  // no entry below but the particles themselves
-    if (leaf_parent)
-        rec[e].meta |= kLeafParentFlag;
+    R.mass = M;
+    R.com[0] = X0 / M;
+    R.com[1] = X1 / M;
+    R.com[2] = X2 / M;
+    R.skip = k;
+    R.meta |= leaf_parent ? kLeafParentFlag : 0u;
+    rec[e] = R;
+    ecount[e] = cnt;
     if (eh)
         eh[e] = hmax;
-    if (out32) {
-        Rec32 o = out32[e];  // integer centre and level from k_emit
-        o.dx = (float)(s0 - rec[e].cen[0]);
-        o.dy = (float)(s1 - rec[e].cen[1]);
-        o.dz = (float)(s2 - rec[e].cen[2]);
+    if (out32) {  // exact integer centre from the node's first particle
+        const uint32_t q[3] = {(uint32_t)(qq >> 42) & 0x1fffffu,
+                               (uint32_t)(qq >> 21) & 0x1fffffu, (uint32_t)qq & 0x1fffffu};
+        Rec32 o;
+        rec32_centre(o, q, (int)lev, sh, false);
+        o.dx = (float)(R.com[0] - R.cen[0]);
+        o.dy = (float)(R.com[1] - R.cen[1]);
+        o.dz = (float)(R.com[2] - R.cen[2]);
         o.gm = (float)(G * M);
         o.cx_meta |= leaf_parent ? kRecLeafParent : 0;
         o.skip = k;
@@ -602,7 +605,7 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
     TPM_TRY(ensure(c, c->ecount, (size_t)E * 4));
     TPM_TRY(ensure(c, c->lvl_list, (size_t)(off > 0 ? off : 1) * 4));
     Rec64 *rec = (Rec64 *)c->rec64.p;
-    // FP32 records: written by the emission and completed by the moments
+    // FP32 records: particles' written by the emission, nodes' by the moments
     Rec32 *rec32 = nullptr;
     float *eh32 = nullptr;
     if (P.precision == TPM_FP32) {
@@ -635,7 +638,8 @@ int build(tpm_ctx *c, int64_t n, const double *x, const double *y, const double 
         k_moments<<<grid_for(cnt, kBlock), kBlock, 0, st>>>(
             rec, E, (uint32_t)n, (const uint32_t *)c->efirst.p, (uint32_t *)c->ecount.p,
             (const uint32_t *)c->lvl_list.p + c->level_off[l],
-            cnt, (uint32_t)l, eh, P.G, rec32, eh32);
+            cnt, (uint32_t)l, eh, P.G, (const uint64_t *)c->qs.p,
+            P.periodic ? kRecShiftPer : kRecShiftIso, rec32, eh32);
         TPM_LAUNCHED(c, "k_moments");
     }
     TPM_TRY(timer_end(c, TPM_TIMER_MOMENTS));
