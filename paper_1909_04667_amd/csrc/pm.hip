@@ -547,8 +547,9 @@ __global__ __launch_bounds__(kBlock) void k_interp(const uint32_t *__restrict__ 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scatter_out(
     const int32_t *__restrict__ idx, int64_t n_act, int64_t n, const int32_t *__restrict__ rank,
-    const uint32_t *__restrict__ slot, const T *__restrict__ res, const T *__restrict__ rpot,
-    T *__restrict__ acc, T *__restrict__ pot, uint32_t *__restrict__ err) {
+    const uint32_t *__restrict__ slot, const uint32_t *__restrict__ nuniq,
+    const T *__restrict__ res, const T *__restrict__ rpot, T *__restrict__ acc,
+    T *__restrict__ pot, uint32_t *__restrict__ err) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= n_act)
         return;
@@ -560,7 +561,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter_out(
         atomicOr(err, 1u);
         return;
     }
-    const uint32_t sl = slot[rank[i]];
+    // with every particle active the slots are the ranks
+    const uint32_t rk = (uint32_t)rank[i];
+    const uint32_t sl = *nuniq == (uint32_t)n ? rk : slot[rk];
     const T *r = res + 4 * (size_t)sl;
     acc[k] = r[0];
     acc[n_act + k] = r[1];
@@ -810,7 +813,8 @@ int interp_t(tpm_ctx *c, int64_t n_act, const int32_t *idx, void *acc, void *pot
     TPM_LAUNCHED(c, "k_interp");
     k_scatter_out<T><<<grid_for(n_act, kBlock), kBlock, 0, c->stream>>>(
         idx, n_act, n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
-        (const T *)c->res.p, (const T *)c->rpot.p, (T *)acc, (T *)pot,
+        (const uint32_t *)c->counters.p + 40, (const T *)c->res.p, (const T *)c->rpot.p,
+        (T *)acc, (T *)pot,
         (uint32_t *)c->err_flag.p);
     TPM_LAUNCHED(c, "k_scatter_out");
     return TPM_OK;

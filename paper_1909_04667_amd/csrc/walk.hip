@@ -82,9 +82,9 @@ __global__ __launch_bounds__(kBlock) void k_mark(const int32_t *__restrict__ idx
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_output(
     const int32_t *__restrict__ idx, int64_t n_act, int64_t n, const int32_t *__restrict__ rank,
-    const uint32_t *__restrict__ slot, const T *__restrict__ res, const T *__restrict__ rpot,
-    T *__restrict__ acc, T *__restrict__ pot, uint32_t *__restrict__ nint,
-    uint32_t *__restrict__ err) {
+    const uint32_t *__restrict__ slot, const uint32_t *__restrict__ nuniq,
+    const T *__restrict__ res, const T *__restrict__ rpot, T *__restrict__ acc,
+    T *__restrict__ pot, uint32_t *__restrict__ nint, uint32_t *__restrict__ err) {
     int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= n_act)
         return;
@@ -101,8 +101,10 @@ __global__ __launch_bounds__(kBlock) void k_output(
         atomicOr(err, 1u);
         return;
     }
-    // the slot's record: acceleration and interaction count together
-    const uint32_t sl = slot[rank[i]];
+    // the slot's record: acceleration and interaction count together (with
+    // every particle active the slots are the ranks, and the lookup is skipped)
+    const uint32_t rk = (uint32_t)rank[i];
+    const uint32_t sl = *nuniq == (uint32_t)n ? rk : slot[rk];
     const T *r = res + 4 * (size_t)sl;
     acc[k] = r[0];
     acc[n_act + k] = r[1];
@@ -405,12 +407,12 @@ int forces_into(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx,
     const unsigned ob = grid_for(n_act, kBlock);
     if (fp32)
         k_output<float><<<ob, kBlock, 0, st>>>(
-            idx, n_act, n, (const int32_t *)c->rank.p, w.slot, (const float *)w.res,
+            idx, n_act, n, (const int32_t *)c->rank.p, w.slot, w.nuniq, (const float *)w.res,
             (const float *)w.rpot, (float *)acc, want_pot ? (float *)pot : nullptr,
             nint, (uint32_t *)c->err_flag.p);
     else
         k_output<double><<<ob, kBlock, 0, st>>>(
-            idx, n_act, n, (const int32_t *)c->rank.p, w.slot, (const double *)w.res,
+            idx, n_act, n, (const int32_t *)c->rank.p, w.slot, w.nuniq, (const double *)w.res,
             (const double *)w.rpot, (double *)acc, want_pot ? (double *)pot : nullptr,
             nint, (uint32_t *)c->err_flag.p);
     TPM_LAUNCHED(c, "k_output");
@@ -720,12 +722,12 @@ int tpm_batch_launch(tpm_batch *b) {
         if (c->P.precision == TPM_FP32)
             k_output<float><<<ob, kBlock, 0, b->stream>>>(
                 p.idx, p.n_act, c->n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
-                (const float *)c->res.p, (const float *)c->rpot.p, (float *)p.acc, nullptr,
+                (const uint32_t *)c->counters.p + 40, (const float *)c->res.p, (const float *)c->rpot.p, (float *)p.acc, nullptr,
                 p.nint, (uint32_t *)c->err_flag.p);
         else
             k_output<double><<<ob, kBlock, 0, b->stream>>>(
                 p.idx, p.n_act, c->n, (const int32_t *)c->rank.p, (const uint32_t *)c->slot.p,
-                (const double *)c->res.p, (const double *)c->rpot.p, (double *)p.acc, nullptr,
+                (const uint32_t *)c->counters.p + 40, (const double *)c->res.p, (const double *)c->rpot.p, (double *)p.acc, nullptr,
                 p.nint, (uint32_t *)c->err_flag.p);
         BHIP(b, hipGetLastError());
     }
