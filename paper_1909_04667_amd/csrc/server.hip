@@ -838,6 +838,7 @@ int submit_impl(tpm_server *s, tpm_ctx *c, bool step, int32_t opening, int64_t n
     s->free_slots.pop_back();
     SrvReq R{};
     wk::fill_args(c, step ? (const double *)c->srv_an.p : anorm, w, R.A);
+    R.A.coherent = 1u;  // later items of the request read the results in this kernel
     R.idx = idx;
     R.rank = (const int32_t *)c->rank.p;
     R.mark = w.mark;

@@ -297,6 +297,7 @@ void wk::fill_args(tpm_ctx *c, const double *anorm, const Work &w, WalkArgs &A) 
     A.pe = (const uint32_t *)c->pe.p;
     A.perm = (const int32_t *)c->perm.p;
     A.anorm = anorm;
+    A.coherent = 0u;
     for (int a = 0; a < 3; a++)
         A.x0[a] = c->frame_host.x0[a];
     A.L = c->frame_host.L;

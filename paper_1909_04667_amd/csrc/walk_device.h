@@ -44,6 +44,10 @@ struct WalkArgs {
     // order) and the largest support per entry (double, or float for FP32)
     const double *hs;
     const void *eh;
+    // results stored device-coherently (written through to memory at once):
+    // set by the resident server, whose later work items read them inside
+    // the same kernel; other launches store plainly (visible at kernel end)
+    uint32_t coherent;
 };
 
 // Wavefront masks: ballot of a lane predicate, and a mask read back as the
@@ -308,15 +312,28 @@ __device__ __forceinline__ uint32_t count_of(double v) {
     return (uint32_t)__double_as_longlong(v);
 }
 template <typename T>
-__device__ __forceinline__ void store_result(void *res, void *rpot, uint32_t slot, T a0, T a1,
-                                             T a2, bool pot_on, T pot, uint32_t nint) {
-    T *r = (T *)res + 4 * (size_t)slot;
-    coherent_st(r, a0);
-    coherent_st(r + 1, a1);
-    coherent_st(r + 2, a2);
-    coherent_st(r + 3, count_bits(nint, T()));
-    if (pot_on)
-        coherent_st((T *)rpot + slot, pot);
+__device__ __forceinline__ void store_result(const WalkArgs &A, uint32_t slot, T a0, T a1, T a2,
+                                             bool pot_on, T pot, uint32_t nint) {
+    T *r = (T *)A.res + 4 * (size_t)slot;
+    if (A.coherent) {
+        coherent_st(r, a0);
+        coherent_st(r + 1, a1);
+        coherent_st(r + 2, a2);
+        coherent_st(r + 3, count_bits(nint, T()));
+        if (pot_on)
+            coherent_st((T *)A.rpot + slot, pot);
+    } else {  // the whole record in one (FP32) or two (FP64) 16-byte stores
+        if constexpr (sizeof(T) == 4) {
+            typedef T T4 __attribute__((ext_vector_type(4)));
+            *(T4 *)r = T4{a0, a1, a2, count_bits(nint, T())};
+        } else {
+            typedef T T2 __attribute__((ext_vector_type(2)));
+            ((T2 *)r)[0] = T2{a0, a1};
+            ((T2 *)r)[1] = T2{a2, count_bits(nint, T())};
+        }
+        if (pot_on)
+            ((T *)A.rpot)[slot] = pot;
+    }
 }
 
 // Orders the wavefront's LDS accesses (lanes read what other lanes wrote).
@@ -636,7 +653,7 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave, I
     if (TPM && qn)
         flush(qn, ns);
     if (valid)
-        store_result<double>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
+        store_result<double>(A, slot, a0, a1, a2, POT, pot, nint);
 }
 
 // ---- FP32 walk ----------------------------------------------------------------
@@ -950,7 +967,7 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
         }
     }
     if (valid)
-        store_result<float>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
+        store_result<float>(A, slot, a0, a1, a2, POT, pot, nint);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
@@ -1190,7 +1207,7 @@ __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, u
                 const Rec64 r = R[e];
                 e = visit(e, r) ? e + 1u : r.skip;
                 if (e >= A.E) {
-                    store_result<double>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
+                    store_result<double>(A, slot, a0, a1, a2, POT, pot, nint);
                     slot += 64u;
                     live = slot < chunk_end;
                     e = 0;
@@ -1227,7 +1244,7 @@ __device__ __forceinline__ void walk_lanes64(const WalkArgs &A, uint32_t wave, u
         }
         lanes_to_first(a0, a1, a2, pot, nint, POT);
         if (lane == 0)
-            store_result<double>(A.res, A.rpot, base, a0, a1, a2, POT, pot, nint);
+            store_result<double>(A, base, a0, a1, a2, POT, pot, nint);
     }
 }
 
@@ -1316,7 +1333,7 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
                 const Rec32 r = R[e];
                 e = visit(e, r) ? e + 1u : r.skip;
                 if (e >= A.E) {
-                    store_result<float>(A.res, A.rpot, slot, a0, a1, a2, POT, pot, nint);
+                    store_result<float>(A, slot, a0, a1, a2, POT, pot, nint);
                     slot += 64u;
                     live = slot < chunk_end;
                     e = 0;
@@ -1353,7 +1370,7 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
         }
         lanes_to_first(a0, a1, a2, pot, nint, POT);
         if (lane == 0)
-            store_result<float>(A.res, A.rpot, base, a0, a1, a2, POT, pot, nint);
+            store_result<float>(A, base, a0, a1, a2, POT, pot, nint);
     }
 }
 
