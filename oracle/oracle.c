@@ -1160,8 +1160,8 @@ void orc_pm(int64_t n, const double *x, const double *y, const double *z,
 }
 
 /* ------------------------------------------------------------------ */
-/* Particle-mesh long-range force without periodicity (Sec. 3.3: zero  */
-/* padding and a different Green's function).                          */
+/* Particle-mesh long-range force without periodicity (Sec. 3.3: an   */
+/* isolated system takes a padded mesh with its own Green's function). */
 /*                                                                     */
 /* The ng-cell mesh spans the root cube [x0, x0 + L) plus two cells on */
 /* each side: h = L / (ng - 4), mesh origin x0 - 2h.  It is embedded in */
