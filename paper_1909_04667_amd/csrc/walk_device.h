@@ -939,10 +939,14 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
         if (inter)
             interact32_wave<TPM, POT, MIXED>(A, inter, r.gm, d0, d1, d2, dd, hp, a0, a1, a2, pot,
                                              nint);
-        if (TPM && desc && (cm & kRecLeafParent) && prefilter) {
-            // the children cu + 1 .. skip - 1 are particles, walked by the
-            // lanes that opened the cube; the cursor then moves past them
-            const uint32_t end = r.skip;
+        {
+            // an opened leaf parent (with the prefilter): the children
+            // cu + 1 .. skip - 1 are particles, walked here by the lanes that
+            // opened the cube, and the cursor then moves past them; for any
+            // other cube the run is empty (one path through the loop for the
+            // accumulators either way)
+            const bool run = TPM && desc && (cm & kRecLeafParent) && prefilter;
+            const uint32_t end = run ? r.skip : cu + 1u;
             for (uint32_t base = cu + 1u; base < end; base += 64u) {
                 const uint32_t k = min(64u, end - base);
                 bool near = false;
@@ -961,9 +965,7 @@ __device__ __forceinline__ void walk_group32(const WalkArgs &A, uint32_t wave) {
                     particle(uniform_rec32(R, e), e, desc);
                 }
             }
-            c = end;
-        } else {
-            c = desc ? cu + 1u : r.skip;
+            c = run ? r.skip : desc ? cu + 1u : r.skip;
         }
     }
     if (valid)
