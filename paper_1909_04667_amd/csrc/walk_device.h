@@ -625,8 +625,11 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave, I
         next = lane_in(mine & ~open) ? r.skip : next;
         if (inter)
             push(inter, r.mass, d0, d1, d2, dd, hp);
-        if (TPM && desc && (r.meta & kLeafParentFlag) && prefilter) {
-            const uint32_t end = r.skip;
+        {
+            // an opened leaf parent (with the prefilter): its particle
+            // children walked here; for any other cube the run is empty
+            const bool run = TPM && desc && (r.meta & kLeafParentFlag) && prefilter;
+            const uint32_t end = run ? r.skip : cu + 1u;
             for (uint32_t base = cu + 1u; base < end; base += 64u) {
                 const uint32_t k = min(64u, end - base);
                 bool near = false;
@@ -645,9 +648,7 @@ __device__ __forceinline__ void walk_group64(const WalkArgs &A, uint32_t wave, I
                     particle(uniform_rec(R, e), e, desc);
                 }
             }
-            c = end;
-        } else {
-            c = desc ? cu + 1u : r.skip;
+            c = run ? r.skip : desc ? cu + 1u : r.skip;
         }
     }
     if (TPM && qn)
