@@ -264,19 +264,25 @@ int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
 // systems (their outer groups span many cutoff radii, and the FP64
 // interaction is costly); the shared cursor otherwise (measured on the 128^3
 // box and the Hernquist sphere).  One wavefront per target for active sets
-// of at most 4096 targets: a lane's serial walk would be the whole critical
-// path (measured: the 4096-particle Plummer sphere 0.74 -> 0.36 ms in FP32).
-// Larger sparse sets keep the lanes: there the frontier walk keeps every SIMD
-// busy but costs about four times the lane walk's work per target (the
-// clustered box's 0.1 % set, 16777 targets: 1.45 ms against 1.33 ms), and
-// concurrent requests of the serving loop fill the chip anyway.
+// of at most 4096 targets, and of at most 65536 in trees of 2^22 particles or
+// more: with that few wavefronts a lane's serial walk (the longest, which
+// grows with the tree) is the critical path, while the frontier walk spreads
+// each target over its wavefront and fills the chip.  Measured, FP32
+// relative walk, lanes against one wavefront per target: the densest targets
+// of the clustered 256^3 box, 16777 targets 1.41 / 0.35 ms, 41943: 1.41 /
+// 0.75, 83886: 1.46 / 1.28, 167772: 1.73 / 2.41 (FP64 even at 84 k); the
+// 4096-particle Plummer sphere 0.74 -> 0.32 ms.  In smaller trees the lane
+// walks are short and the frontier walk's larger work per target loses
+// (block steps of a 2^18 Hernquist sphere with sets up to 65536: 15.6 ms
+// against 25.5 ms for the integration; the serving mix, up to 2^21
+// particles per system: half the burst capacity).
 // TPM_WALK_MODE (1 shared cursor, 2 lanes, 3 one wavefront per target)
 // overrides the choice.
 Variant wk::walk_variant(const tpm_ctx *c, int64_t n_act) {
     if (c->walk_mode != 0)
         return c->walk_mode == 1 ? kGroupWalk : c->walk_mode == 2 ? kLaneWalk : kSplitWalk;
     const int64_t targets = std::min<int64_t>(n_act, c->n);
-    if (targets <= 4096)
+    if (targets <= 4096 || (targets <= 65536 && c->n >= (int64_t(1) << 22)))
         return kSplitWalk;
     const bool fp64_iso_tpm =
         c->P.precision == TPM_FP64 && c->P.pm_grid > 0 && !c->P.periodic;

@@ -1012,10 +1012,11 @@ __device__ __forceinline__ uint32_t wave_id() {
 // interaction of the sequential walk happens once, in one lane, with the same
 // operands; the 64 partial sums are added in a fixed tree order, so results
 // are deterministic but rounded differently from the other variants
-// (interaction counts are identical).  Phase 1 expands while the frontier
-// holds at most 64 entries and at most 448 are set aside; then the rest of
-// the frontier is set aside undecided.  `front`: 2048 words of LDS per
-// wavefront (two frontiers of 512, 1024 set aside).
+// (interaction counts are identical).  Phase 1 expands level by level while
+// the frontier and the set-aside list together hold at most 512 entries
+// (each level's frontier taken 64 entries at a time); then the rest of the
+// frontier is set aside undecided.  `front`: 2048 words of LDS per wavefront
+// (two frontiers of 512, 1024 set aside).
 constexpr uint32_t kFrontWords = 2048;
 constexpr uint32_t kFrontLeaf = 128;
 
@@ -1077,46 +1078,60 @@ __device__ __forceinline__ void expand_front(const Rec *__restrict__ R, uint32_t
         cur[0] = 0u;  // the root
     uint32_t nf = 1u;
     wave_sync();
-    while (nf != 0u && nf <= 64u && na <= 448u) {
-        uint32_t nkid = 0u, nset = 0u, e = 0u, skip = 0u;
-        bool big = false;
-        if ((uint32_t)lane < nf) {
-            e = cur[lane];
-            const Rec r = R[e];
-            skip = r.skip;
-            if (skip - e <= kFrontLeaf) {
-                nset = 1u;  // small subtree: walked whole in phase 2
-            } else if (visit(e, r) && !is_particle(r)) {  // an opened cube
-                uint32_t c = e + 1u;
-                while (c < skip && nkid < 8u) {
-                    nkid++;
-                    c = R[c].skip;
+    // one level per pass, its frontier taken 64 entries at a time.  Bounds:
+    // the next frontier holds at most 512 entries (an opened cube whose
+    // children do not fit any more is set aside whole, to be opened again in
+    // phase 2), and a level starts only while na + nf <= 512, so that the
+    // set-aside list (1024 words) also takes the final frontier
+    while (nf != 0u && na + nf <= 512u) {
+        uint32_t nn = 0u;
+        for (uint32_t b = 0; b < nf; b += 64u) {
+            uint32_t nkid = 0u, nset = 0u, e = 0u;
+            if (b + (uint32_t)lane < nf) {
+                e = cur[b + lane];
+                const Rec r = R[e];
+                const uint32_t skip = r.skip;
+                if (skip - e <= kFrontLeaf) {
+                    nset = 1u;  // small subtree: walked whole in phase 2
+                } else if (visit(e, r) && !is_particle(r)) {  // an opened cube
+                    uint32_t c = e + 1u;
+                    while (c < skip && nkid < 8u) {
+                        nkid++;
+                        c = R[c].skip;
+                    }
+                    if (c < skip) {  // more than 8 children: set aside whole
+                        nkid = 0u;
+                        nset = 1u;
+                    }
                 }
-                big = c < skip;
-                if (big) {  // more than 8 children: set aside whole
+            }
+            uint32_t tk, ts;
+            uint32_t ok = lanes_prefix(nkid, tk);
+            if (nn + tk > 512u) {  // the lanes whose children no longer fit
+                if (nkid && nn + ok + nkid > 512u) {
                     nkid = 0u;
                     nset = 1u;
                 }
+                ok = lanes_prefix(nkid, tk);
             }
-        }
-        uint32_t tk, ts;
-        const uint32_t ok = lanes_prefix(nkid, tk);
-        const uint32_t os = lanes_prefix(nset, ts);
-        if (nset)
-            aside[na + os] = e;
-        if (nkid) {
-            uint32_t c = e + 1u;
-            for (uint32_t k = 0; k < nkid; k++) {
-                nxt[ok + k] = c;
-                c = R[c].skip;
+            const uint32_t os = lanes_prefix(nset, ts);
+            if (nset)
+                aside[na + os] = e;
+            if (nkid) {
+                uint32_t c = e + 1u;
+                for (uint32_t k = 0; k < nkid; k++) {
+                    nxt[nn + ok + k] = c;
+                    c = R[c].skip;
+                }
             }
+            nn += tk;
+            na += ts;
         }
         wave_sync();
         uint32_t *t = cur;
         cur = nxt;
         nxt = t;
-        nf = tk;
-        na += ts;
+        nf = nn;
     }
     // the rest of the frontier (at most 512 entries), set aside undecided
     for (uint32_t k = (uint32_t)lane; k < nf; k += 64u)

@@ -310,8 +310,8 @@ def test_active_subsets_and_duplicates():
     """A subset's forces are the full set's at the same targets: bit for bit
     where both take the same walk variant (the lane walk is bit-identical to
     the shared cursor), to rounding where the subset takes one wavefront per
-    target (at most 4096 targets: the same interactions summed in another
-    order; interaction counts identical)."""
+    target (at most 4096 targets in a tree of this size: the same
+    interactions summed in another order; interaction counts identical)."""
     p = W.plummer(6000, 12)
     ctx = _ctx(eps=0.01, want_potential=True)
     _build(ctx, p)
