@@ -52,6 +52,55 @@ __global__ __launch_bounds__(kBlock) void k_walk32i(const WalkArgs A, uint32_t K
     walk_lanes32<PER, TPM, OPEN, POT, MIXED>(A, wave_id(), K);
 }
 
+// Sparse active sets with a cutoff: a census counts the compact groups
+// (group_compact), then one of two launches walks every group -- with the
+// shared cursor when at least half of the groups are compact (a set of dense
+// clumps, as the deepest time bins are), with independent lanes otherwise;
+// the other launch returns at once.  The two walks give the same results.
+// Measured on the clustered 256^3 box, FP32 relative walk, against lanes for
+// every sparse set: the densest 1 % 1.17 against 1.65 ms, the densest 10 %
+// 3.81 against 4.44, random 1 % and 10 % unchanged (lanes: 1.66, 6.18).
+// (Choosing per group inside one kernel made its lane walk slower: 7.6
+// against 6.0 ms on the random 10 %.)
+template <bool PER>
+__global__ __launch_bounds__(kBlock) void k_census(const WalkArgs A, uint32_t *census) {
+    const uint32_t wave = wave_id();
+    if (wave * 64u >= load_count(A.nuniq))
+        return;
+    if (group_compact<PER>(A, wave) && (threadIdx.x & 63) == 0)
+        atomicAdd(census, 1u);
+}
+
+__device__ __forceinline__ bool mostly_compact(const WalkArgs &A) {
+    const uint32_t groups = (load_count(A.nuniq) + 63u) / 64u;
+    return 2ull * load_count(A.census) >= groups;
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_walk64m(const WalkArgs A) {
+    __shared__ IQ64 q[kBlock / 64];
+    if (mostly_compact(A))
+        walk_group64<PER, TPM, OPEN, POT, MIXED>(A, wave_id(), &q[threadIdx.x >> 6]);
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_walk64im(const WalkArgs A) {
+    if (!mostly_compact(A))
+        walk_lanes64<PER, TPM, OPEN, POT, MIXED>(A, wave_id(), 1u);
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_walk32m(const WalkArgs A) {
+    if (mostly_compact(A))
+        walk_group32<PER, TPM, OPEN, POT, MIXED>(A, wave_id());
+}
+
+template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_walk32im(const WalkArgs A) {
+    if (!mostly_compact(A))
+        walk_lanes32<PER, TPM, OPEN, POT, MIXED>(A, wave_id(), 1u);
+}
+
 // one wavefront per target (sparse active sets)
 template <bool PER, bool TPM, int OPEN, bool POT, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_walk64s(const WalkArgs A) {
@@ -159,6 +208,17 @@ void launch_walk(const WalkArgs &A, const Launch &L, hipStream_t st) {
             k_walk32i<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A, L.K);
         else
             k_walk64i<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A, L.K);
+    } else if (L.variant == kGroupOrLanes) {
+        if constexpr (TPM) {  // chosen only with a cutoff
+            k_census<PER><<<L.blocks, kBlock, 0, st>>>(A, (uint32_t *)A.census);
+            if (L.fp32) {
+                k_walk32m<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A);
+                k_walk32im<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A);
+            } else {
+                k_walk64m<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A);
+                k_walk64im<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A);
+            }
+        }
     } else {
         if (L.fp32)
             k_walk32<PER, TPM, OPEN, POT, MIXED><<<L.blocks, kBlock, 0, st>>>(A);
@@ -278,7 +338,7 @@ int select_active(tpm_ctx *c, int64_t n_act, const int32_t *idx) {
 // particles per system: half the burst capacity).
 // TPM_WALK_MODE (1 shared cursor, 2 lanes, 3 one wavefront per target)
 // overrides the choice.
-Variant wk::walk_variant(const tpm_ctx *c, int64_t n_act) {
+Variant wk::walk_variant(const tpm_ctx *c, int64_t n_act, bool census_ok) {
     if (c->walk_mode != 0)
         return c->walk_mode == 1 ? kGroupWalk : c->walk_mode == 2 ? kLaneWalk : kSplitWalk;
     const int64_t targets = std::min<int64_t>(n_act, c->n);
@@ -286,7 +346,12 @@ Variant wk::walk_variant(const tpm_ctx *c, int64_t n_act) {
         return kSplitWalk;
     const bool fp64_iso_tpm =
         c->P.precision == TPM_FP64 && c->P.pm_grid > 0 && !c->P.periodic;
-    return (fp64_iso_tpm || 4 * n_act < c->n) ? kLaneWalk : kGroupWalk;
+    if (fp64_iso_tpm)
+        return kLaneWalk;
+    if (4 * n_act >= c->n)
+        return kGroupWalk;
+    // a sparse set: with a cutoff, as the census of its groups decides
+    return census_ok && c->P.pm_grid > 0 ? kGroupOrLanes : kLaneWalk;
 }
 
 void wk::fill_args(tpm_ctx *c, const double *anorm, const Work &w, WalkArgs &A) {
@@ -304,6 +369,7 @@ void wk::fill_args(tpm_ctx *c, const double *anorm, const Work &w, WalkArgs &A) 
     A.perm = (const int32_t *)c->perm.p;
     A.anorm = anorm;
     A.coherent = 0u;
+    A.census = nullptr;
     for (int a = 0; a < 3; a++)
         A.x0[a] = c->frame_host.x0[a];
     A.L = c->frame_host.L;
@@ -344,6 +410,7 @@ void wk::fill_args(tpm_ctx *c, const double *anorm, const Work &w, WalkArgs &A) 
         A.pf2 = (rcut + tol64) * (rcut + tol64);
         A.pf_ext = P.periodic ? 0.5 * P.box_size - rcut - 2.0 * tol64 : 1.0e300;
     }
+    A.group_ext2 = 0.25 * A.rc2;
     A.finv2rs = (float)A.inv2rs;
     A.fgexp = (float)(-1.4426950408889634 * A.inv2rs * A.inv2rs);
     A.res = w.res;
@@ -386,7 +453,11 @@ int forces_into(tpm_ctx *c, int32_t opening, int64_t n_act, const int32_t *idx,
     LA.fp32 = fp32;
     // lane-independent walks pay off where the interaction is expensive and
     // the wavefront's union of cutoff spheres is large: FP64 with TreePM
-    LA.variant = walk_variant(c, n_act);
+    LA.variant = walk_variant(c, n_act, true);
+    if (LA.variant == kGroupOrLanes) {  // the census word follows the unique count
+        A.census = w.nuniq + 1;
+        TPM_TRY(fill_u32(c, w.nuniq + 1, 0u, 1));
+    }
     LA.K = 1;
     if (LA.variant == kLaneWalk) {
         // several slots per lane once there are enough wavefronts to fill the chip

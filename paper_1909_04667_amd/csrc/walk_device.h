@@ -44,6 +44,10 @@ struct WalkArgs {
     // order) and the largest support per entry (double, or float for FP32)
     const double *hs;
     const void *eh;
+    // largest extent of a group's targets for the shared cursor in the
+    // census of compact groups (squared; TreePM: half the cutoff radius)
+    double group_ext2;
+    const uint32_t *census;  // count of compact groups (sparse sets with a cutoff)
     // results stored device-coherently (written through to memory at once):
     // set by the resident server, whose later work items read them inside
     // the same kernel; other launches store plainly (visible at kernel end)
@@ -1396,9 +1400,48 @@ __device__ __forceinline__ void walk_lanes32(const WalkArgs &A, uint32_t wave, u
 // its working memory, and the choice of the lane-independent walk.
 void fill_args(tpm_ctx *c, const double *anorm, const Work &w, WalkArgs &A);
 // Walk variant for an active set of n_act: shared cursor (64 targets per
-// wavefront), independent lanes, or one wavefront per target (FRONT).
-enum Variant : uint32_t { kGroupWalk = 0, kLaneWalk = 1, kSplitWalk = 2 };
-Variant walk_variant(const tpm_ctx *c, int64_t n_act);
+// wavefront), independent lanes, one wavefront per target (FRONT), or the
+// shared cursor or lanes as a census of the groups' extents decides on the
+// device (the two give the same results).
+enum Variant : uint32_t { kGroupWalk = 0, kLaneWalk = 1, kSplitWalk = 2, kGroupOrLanes = 3 };
+// The walk for an active set of n_act targets.  census_ok: kGroupOrLanes may
+// be returned (single-system launches; the batch and the resident server
+// take the lanes there).
+Variant walk_variant(const tpm_ctx *c, int64_t n_act, bool census_ok = false);
+
+// Whether the targets of group `wave` (its 64 slots; the caller has checked
+// that the group is not empty) lie within a box of side sqrt(A.group_ext2)
+// (nearest images in a periodic box), so that a shared cursor walks little
+// more than each target's own walk.  Wavefront-uniform.
+template <bool PER>
+__device__ __forceinline__ bool group_compact(const WalkArgs &A, uint32_t wave) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t nu = load_count(A.nuniq);
+    const uint32_t slot = wave * 64u + lane;
+    const uint32_t s = coherent_ld(A.act + (slot < nu ? slot : wave * 64u));
+    double lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double x = A.ps[(size_t)a * A.n + s];
+        const double x0 = __shfl(x, 0);
+        double d = x - x0;
+        if (PER)
+            d = fabs(d) > A.half ? d - copysign(A.box, d) : d;
+        lo[a] = hi[a] = d;
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmin(lo[a], __shfl_xor(lo[a], o));
+            hi[a] = fmax(hi[a], __shfl_xor(hi[a], o));
+        }
+    }
+    double e = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+        e = fmax(e, hi[a] - lo[a]);
+    return __builtin_amdgcn_readfirstlane((int)(e * e <= A.group_ext2)) != 0;
+}
 
 }  // namespace wk
 }  // namespace tpm

@@ -338,6 +338,32 @@ def test_active_subsets_and_duplicates():
     ctx.check()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sparse_sets_group_or_lanes_identical(prec):
+    """Sparse active sets with a cutoff take the shared cursor or independent
+    lanes as a census of their groups' extents decides on the device: the two
+    give the same results, so every subset equals the full set at its targets
+    bit for bit -- a compact set (a slab), a spread-out one (random) and
+    their union."""
+    p = W.zeldovich_box(40, box=100.0, seed=23)  # 64000 particles
+    kw = dict(precision=prec, periodic=True, box_size=100.0, pm_grid=64, eps=0.05)
+    ctx = _ctx(**kw)
+    _build(ctx, p)
+    nfull = torch.empty(p.n, dtype=torch.int32, device=_dev())
+    full, _ = ctx.compute_forces(_t(np.arange(p.n), torch.int32), "bh", n_interactions=nfull)
+    full, nfull = full.cpu(), nfull.cpu()
+    slab = np.argsort(p.x, kind="stable")[:6000]
+    rand = np.random.default_rng(29).choice(p.n, 6000, replace=False)
+    both = np.union1d(slab, rand)
+    for sub in (slab, rand, both):
+        assert 4096 < sub.size and 4 * sub.size < p.n  # the per-group choice
+        nint = torch.empty(sub.size, dtype=torch.int32, device=_dev())
+        acc, _ = ctx.compute_forces(_t(sub, torch.int32), "bh", n_interactions=nint)
+        ctx.check()
+        assert torch.equal(nint.cpu(), nfull[sub])
+        assert torch.equal(acc.cpu(), full[:, sub])
+
+
 def test_out_of_range_index_reported():
     from paper_1909_04667_amd import binding as B
     p = W.plummer(500, 13)
