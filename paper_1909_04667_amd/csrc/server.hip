@@ -81,7 +81,11 @@ constexpr uint32_t kMesh = 2u;   //        with the mesh part
 // (wk::Variant).
 // Whole 64-byte lines, so no scalar-cache line holds parts of two
 // descriptors.
-struct alignas(64) SrvReq {
+// Whole 128-byte L2 lines per descriptor: a wavefront that reads descriptor i
+// must not bring any part of descriptor i + 1 into its die's L2 before the
+// fetcher has written it (the fetcher's stores from another die would not
+// replace that stale copy, and later scalar loads of i + 1 would read it).
+struct alignas(128) SrvReq {
     WalkArgs A;
     const int32_t *idx;   // caller's active list [n_act]
     const int32_t *rank;  // build index -> rank
@@ -106,6 +110,7 @@ struct alignas(64) SrvReq {
     uint32_t slot_id;     // host slot: completion flag and ring entry
     uint32_t desc;        // device descriptor index
 };
+static_assert(sizeof(SrvReq) % 128 == 0, "descriptors own whole L2 lines");
 static_assert(sizeof(SrvReq) % 8 == 0, "descriptor copied in 8-byte words");
 constexpr uint32_t kReqWords = sizeof(SrvReq) / 8;
 
