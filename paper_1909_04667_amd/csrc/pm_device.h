@@ -21,7 +21,8 @@ struct MeshGeom {
 // Mesh force F = -grad Phi and potential P at the particle of curve-order slot
 // s: CIC weights of its position, and at each of the eight mesh points the
 // four-point difference of the potential along each axis (coefficients 2/3
-// and 1/12), everything in double.
+// and 1/12; the sum over the corners divided by h once), everything in
+// double.
 // LEAN: the eight corners one after the other, not unrolled (the same
 // operations in the same order, fewer live registers), for kernels whose
 // other work sets their register budget.
@@ -66,23 +67,20 @@ __device__ __forceinline__ void interp_at(const double *__restrict__ ps, int64_t
             wt *= up ? w[a] : 1.0 - w[a];
             t[a] = i0[a] + up;
         }
-        // -grad Phi at mesh point t
+        // -grad Phi at mesh point t, times h (the division by h follows the sum)
         {
             const double g = ((2.0 / 3.0) * (at(t[0] + 1, t[1], t[2]) - at(t[0] - 1, t[1], t[2])) -
-                              (1.0 / 12.0) * (at(t[0] + 2, t[1], t[2]) - at(t[0] - 2, t[1], t[2]))) /
-                             h;
+                              (1.0 / 12.0) * (at(t[0] + 2, t[1], t[2]) - at(t[0] - 2, t[1], t[2])));
             F[0] += wt * -g;
         }
         {
             const double g = ((2.0 / 3.0) * (at(t[0], t[1] + 1, t[2]) - at(t[0], t[1] - 1, t[2])) -
-                              (1.0 / 12.0) * (at(t[0], t[1] + 2, t[2]) - at(t[0], t[1] - 2, t[2]))) /
-                             h;
+                              (1.0 / 12.0) * (at(t[0], t[1] + 2, t[2]) - at(t[0], t[1] - 2, t[2])));
             F[1] += wt * -g;
         }
         {
             const double g = ((2.0 / 3.0) * (at(t[0], t[1], t[2] + 1) - at(t[0], t[1], t[2] - 1)) -
-                              (1.0 / 12.0) * (at(t[0], t[1], t[2] + 2) - at(t[0], t[1], t[2] - 2))) /
-                             h;
+                              (1.0 / 12.0) * (at(t[0], t[1], t[2] + 2) - at(t[0], t[1], t[2] - 2)));
             F[2] += wt * -g;
         }
         P += wt * at(t[0], t[1], t[2]);
@@ -96,6 +94,9 @@ __device__ __forceinline__ void interp_at(const double *__restrict__ ps, int64_t
         for (int c = 0; c < 8; c++)
             corner(c);
     }
+    F[0] /= h;
+    F[1] /= h;
+    F[2] /= h;
 }
 
 // Mesh geometry of the current build (host, pm.hip).
