@@ -186,6 +186,11 @@ int tpm_set_shift(tpm_ctx *ctx, const double *shift);
  * pot:         device [n_act] of the same type, or NULL.
  * n_interactions: device uint32[n_act] node + particle interactions per
  *              target (the cost factor g_i of Sec. 8), or NULL.
+ * Results are deterministic.  Small active sets (at most 4096 targets, or
+ * 65536 in trees of 2^22 particles or more) are walked with one wavefront per
+ * target, which adds a target's interactions in another order than larger
+ * sets do: its force may then differ in the last bits between sets of the
+ * two kinds; interaction counts never differ.
  * Enqueues work only; does not synchronise. */
 int tpm_compute_forces(tpm_ctx *ctx, int32_t opening, int64_t n_act, const int32_t *active_idx,
                        const double *a_old_norm, void *acc, void *pot,
